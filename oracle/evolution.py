@@ -1,0 +1,171 @@
+"""Alternating-minimisation load step and per-step statistics.
+
+Oracle (test infrastructure only).  Follows Sec. 3.2.1 and Algorithm 2:
+for each strain increment, alternate the mechanics solve at fixed phi and the
+phase-field solve at fixed strain until ||phi_n+1 - phi_n||_1 < Tol_AM, with
+the irreversibility constraint taken from the phase field at the start of the
+load step.  Sec. 3.2.1 also defines the stiffness measure C.
+
+Readings of the paper:
+  * ``load_step(eps_bar)`` takes the macroscopic strain of the step directly
+    (Algorithm 2 increments it by a fixed Delta eps_bar).
+  * Tol_AM is stated in units where lengths are scaled by l (Sec. 3.3): the
+    default here is 1e-3 l^2 in pixel units; the L1 norm sums |.| times the
+    pixel area.
+  * Fields follow Algorithm 2 literally: after a step the strain is the one of
+    the last mechanics solve and phi the one of the last phase-field solve.
+  * With an initial phase field the phase-field problem is first solved at
+    zero strain with phi_con(phi_init) (Algorithm 2, first two lines).
+  * C = sigma_bar_ij / eps_bar_ij at the component with the largest
+    |eps_bar_ij| (Sec. 3.2.1).
+"""
+
+import numpy as np
+
+from . import constitutive as cm
+from . import mechanics as mech
+from . import phasefield as pf
+from . import spectral as sp
+
+
+class Problem:
+    """One periodic 2-D microstructure and its evolving state.
+
+    Parameters mirror the library's problem configuration: Young's modulus
+    field E (ny, nx), Poisson ratio nu, length scale ell (pixels), G_c, AT
+    model (1 or 2), split ('none' | 'spectral'), irreversibility
+    ('crack_set' | 'damage').
+    """
+
+    def __init__(self, E, nu=0.2, ell=2.0, gc=1.0, at=1, split="spectral",
+                 irreversibility="crack_set", threshold=0.9, k_res=0.0,
+                 eta_over_dt=0.0, tol_mech=1e-8, tol_pf=1e-8, tol_am=None,
+                 tol_abs_mech=0.0, tol_abs_pf=0.0, max_cg=10000,
+                 max_newton=30, max_bccg=10000, max_am=1000, phi_init=None):
+        self.E = np.asarray(E, dtype=np.float64)
+        self.ny, self.nx = self.E.shape
+        self.nu, self.ell, self.gc, self.at = float(nu), float(ell), float(gc), int(at)
+        self.split, self.irr, self.threshold = split, irreversibility, float(threshold)
+        self.k_res, self.eta_dt = float(k_res), float(eta_over_dt)
+        self.tol_mech, self.tol_pf = float(tol_mech), float(tol_pf)
+        self.tol_abs_mech, self.tol_abs_pf = float(tol_abs_mech), float(tol_abs_pf)
+        self.tol_am = 1e-3 * self.ell ** 2 if tol_am is None else float(tol_am)
+        self.max_cg, self.max_newton = int(max_cg), int(max_newton)
+        self.max_bccg, self.max_am = int(max_bccg), int(max_am)
+        self.lam, self.mu = cm.lame(self.E, self.nu)
+        self.eps_star = np.zeros((self.ny, self.nx, 2, 2))
+        self.eps_bar = np.zeros((2, 2))
+        self.phi = np.zeros((self.ny, self.nx))
+        if phi_init is not None:
+            phi_init = np.asarray(phi_init, dtype=np.float64)
+            lo = pf.constraint_field(phi_init, self.irr, self.threshold)
+            op = pf.Operator(np.zeros_like(self.phi), self.at, self.gc, self.ell)
+            self.phi, _ = pf.bccg(phi_init, lo, np.ones_like(lo), op, self.tol_pf,
+                                  self.tol_abs_pf, self.max_bccg)
+        self.phi_ref = self.phi.copy()
+        self.step_count = 0
+
+    # -- pointwise fields ------------------------------------------------
+    def strain(self):
+        return self.eps_bar + self.eps_star
+
+    def stress(self):
+        return cm.stress(self.strain(), self.phi, self.lam, self.mu, self.split, self.k_res)
+
+    def psi_plus(self):
+        return cm.psi0(self.strain(), self.lam, self.mu, self.split)[0]
+
+    def displacement(self):
+        """Periodic fluctuation u* (zero mean); the affine part is eps_bar x."""
+        return sp.displacement_from_strain(self.eps_star)
+
+    # -- energies --------------------------------------------------------
+    def elastic_energy(self, phi=None, eps_star=None):
+        phi = self.phi if phi is None else phi
+        eps = self.eps_bar + (self.eps_star if eps_star is None else eps_star)
+        return float(np.sum(cm.energy_density(eps, phi, self.lam, self.mu, self.split, self.k_res)))
+
+    def fracture_energy(self, phi=None):
+        return pf.fracture_energy(self.phi if phi is None else phi, self.at, self.gc, self.ell)
+
+    # -- sub-problems ----------------------------------------------------
+    def solve_mechanics(self):
+        self.eps_star, info = mech.solve(self.eps_star, self.eps_bar, self.phi, self.lam,
+                                         self.mu, self.split, self.k_res, self.tol_mech,
+                                         self.tol_abs_mech, self.max_newton, self.max_cg)
+        return info
+
+    def solve_phase_field(self, lo, phi_old=None):
+        op = pf.Operator(self.psi_plus(), self.at, self.gc, self.ell, self.eta_dt, phi_old)
+        phi, info = pf.bccg(self.phi, lo, np.ones_like(lo), op, self.tol_pf,
+                            self.tol_abs_pf, self.max_bccg)
+        return phi, info
+
+    # -- Algorithm 2, one strain increment --------------------------------
+    def load_step(self, eps_bar, trace=None):
+        """Advance one load step at macroscopic strain ``eps_bar`` (2x2 or
+        (xx, yy, xy)).  ``trace`` (a list) receives (F_e, F_f) after every
+        sub-solve.  Returns a stats dict."""
+        eps_bar = np.asarray(eps_bar, dtype=np.float64)
+        if eps_bar.shape == (3,):
+            eps_bar = cm.sym_tensor(*eps_bar)
+        self.eps_bar = eps_bar
+        self.phi_ref = self.phi.copy()
+        lo = pf.constraint_field(self.phi_ref, self.irr, self.threshold)
+        phi_old = self.phi_ref if self.eta_dt != 0.0 else None
+        am = newton = cg = bccg = 0
+        dphi = np.inf
+        converged = True
+        while dphi > self.tol_am:
+            if am >= self.max_am:
+                converged = False
+                break
+            mi = self.solve_mechanics()
+            newton += mi["newton"]
+            cg += mi["cg"]
+            converged &= mi["converged"]
+            if trace is not None:
+                trace.append((self.elastic_energy(), self.fracture_energy()))
+            phi_new, pi = self.solve_phase_field(lo, phi_old)
+            bccg += pi["iterations"]
+            converged &= pi["stopped"] == "converged"
+            dphi = float(np.sum(np.abs(phi_new - self.phi)))
+            self.phi = phi_new
+            am += 1
+            if trace is not None:
+                trace.append((self.elastic_energy(), self.fracture_energy()))
+        self.step_count += 1
+        return self.stats(am=am, newton=newton, cg=cg, bccg=bccg, dphi=dphi,
+                          converged=converged)
+
+    def stats(self, **extra):
+        sig = self.stress()
+        sbar = sig.mean(axis=(0, 1))
+        comps = [(0, 0), (1, 1), (0, 1)]
+        ebar = [self.eps_bar[i, j] for i, j in comps]
+        k = int(np.argmax(np.abs(ebar)))
+        stiff = sbar[comps[k]] / ebar[k] if ebar[k] != 0.0 else float("nan")
+        out = {
+            "F_e": self.elastic_energy(),
+            "F_f": self.fracture_energy(),
+            "sigma_bar": [float(sbar[i, j]) for i, j in comps],
+            "C_bar": float(stiff),
+            "phi_max": float(self.phi.max()),
+            "phi_mean": float(self.phi.mean()),
+            "crack_px": int(np.count_nonzero(self.phi > 0.9)),
+        }
+        out.update(extra)
+        return out
+
+    # -- state transfer ---------------------------------------------------
+    def get_state(self):
+        return {"eps_star": self.eps_star.copy(), "phi": self.phi.copy(),
+                "phi_ref": self.phi_ref.copy(), "eps_bar": self.eps_bar.copy(),
+                "step": self.step_count}
+
+    def set_state(self, state):
+        self.eps_star = np.asarray(state["eps_star"], dtype=np.float64).copy()
+        self.phi = np.asarray(state["phi"], dtype=np.float64).copy()
+        self.phi_ref = np.asarray(state.get("phi_ref", self.phi), dtype=np.float64).copy()
+        self.eps_bar = np.asarray(state.get("eps_bar", np.zeros((2, 2))), dtype=np.float64).copy()
+        self.step_count = int(state.get("step", 0))

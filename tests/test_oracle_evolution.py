@@ -1,0 +1,161 @@
+"""Pins for oracle.evolution (Alg. 2 alternating minimisation): homogeneous
+strength closed forms with the paper's printed values (Sec. 3.3, 4.2.2),
+homogeneous fixed points, energy decrease over AM iterations, irreversibility
+invariants, state round trip."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import constitutive as cm
+from oracle import phasefield as pf
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "strength_closed_forms.json")))
+
+
+@pytest.mark.parametrize("split", ["none", "spectral"])
+def test_uniaxial_strength_printed_values(split):
+    """Sec. 3.3: homogeneous AT1 under uniaxial strain stays undamaged up to
+    eps_M = 0.005809 and the stress peaks at sigma_M = 64.55 G_c/l there
+    (nu = 0.2, E0 = 1e4 G_c/l)."""
+    g = GOLDEN["uniaxial_strain_AT1"]
+    E = np.full((5, 5), g["E0"])
+    sig_peak = []
+    for f in (0.99, 1.0, 1.01, 1.2):
+        p = oracle.Problem(E, nu=g["nu"], ell=g["ell"], gc=g["gc"], at=1, split=split)
+        st = p.load_step((0.0, f * g["eps_M"], 0.0))
+        lam, mu = cm.lame(g["E0"], g["nu"])
+        psi = 0.5 * (lam + 2 * mu) * (f * g["eps_M"]) ** 2
+        want = max(0.0, 1 - 3 * g["gc"] / (16 * g["ell"] * psi))
+        if f < 1.0:
+            assert st["phi_max"] == 0.0
+        np.testing.assert_allclose(p.phi, want, atol=2e-3 if f == 1.0 else 1e-9)
+        sig_peak.append(st["sigma_bar"][1])
+    assert max(sig_peak) == pytest.approx(g["sigma_M"], abs=0.05)
+    assert sig_peak[3] < sig_peak[1]
+
+
+def test_shear_strength_printed_values():
+    """Sec. 4.2.2: pure shear with the strain-spectral split, nu = 0.4:
+    onset at eps_12,M = 0.007246 with sigma_12,M = 51.75 G_c/l."""
+    g = GOLDEN["pure_shear_AT1_spectral"]
+    E = np.full((5, 5), g["E0"])
+    below = oracle.Problem(E, nu=g["nu"], ell=g["ell"], gc=g["gc"], at=1, split="spectral")
+    st = below.load_step((0.0, 0.0, 0.995 * g["eps12_M"]))
+    assert st["phi_max"] == 0.0
+    assert st["sigma_bar"][2] == pytest.approx(0.995 * g["sigma12_M"], abs=0.05)
+    above = oracle.Problem(E, nu=g["nu"], ell=g["ell"], gc=g["gc"], at=1, split="spectral")
+    st = above.load_step((0.0, 0.0, 1.005 * g["eps12_M"]))
+    assert st["phi_max"] > 0.0
+
+
+@pytest.mark.parametrize("e", [0.1, 0.3, 0.6])
+def test_at2_homogeneous_fixed_point(e):
+    """AT2 homogeneous: phi = 2 psi0+ / (2 psi0+ + G_c/l) after one step."""
+    E = np.full((6, 6), 1.0)
+    p = oracle.Problem(E, nu=0.2, ell=2.0, gc=1.0, at=2, split="spectral")
+    p.load_step((0.0, e, 0.0))
+    lam, mu = cm.lame(1.0, 0.2)
+    psi = 0.5 * (lam + 2 * mu) * e * e
+    np.testing.assert_allclose(p.phi, 2 * psi / (2 * psi + 1.0 / 2.0), atol=1e-9)
+
+
+def _hetero(n=24, seed=3, amp=0.3):
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n, n))
+    k = np.fft.fftfreq(n) * 2 * np.pi
+    filt = np.exp(-(k[:, None] ** 2 + k[None, :] ** 2) * 9.0 / 4)
+    z = np.fft.ifft2(np.fft.fft2(z) * filt).real
+    z = (z - z.mean()) / z.std()
+    return np.maximum(1 + amp * z, 0.5)
+
+
+@pytest.mark.parametrize("split", ["none", "spectral"])
+@pytest.mark.parametrize("at", [1, 2])
+def test_am_energy_non_increasing(split, at):
+    """Each AM half-step minimises F in one variable with fixed bounds, so
+    F = F_e + F_f does not increase over the inner iterations (variational
+    models, Sec. 3.2.1)."""
+    E = _hetero()
+    p = oracle.Problem(E, nu=0.2, ell=1.5, gc=1.0, at=at, split=split, tol_mech=1e-11,
+                       tol_pf=1e-11, max_am=12)
+    em = np.sqrt(3 / (8 * 1.5 * (10 / 9)))
+    for f in (0.8, 1.05):
+        tr = []
+        p.load_step((0.0, f * em, 0.0), trace=tr)
+        F = np.array([a + b for a, b in tr])
+        assert np.all(np.diff(F) <= 1e-8 * np.abs(F).max())
+
+
+@pytest.mark.parametrize("irr", ["crack_set", "damage"])
+def test_irreversibility_and_bounds(irr):
+    E = _hetero(seed=5)
+    p = oracle.Problem(E, nu=0.2, ell=1.5, gc=1.0, at=1, split="spectral",
+                       irreversibility=irr, tol_mech=1e-9, tol_pf=1e-9, max_am=8)
+    em = np.sqrt(3 / (8 * 1.5 * (10 / 9)))
+    for f in (0.9, 1.0, 1.1, 1.2, 0.6):
+        p.load_step((0.0, f * em, 0.0))
+        lo = pf.constraint_field(p.phi_ref, irr)
+        assert np.all(p.phi >= lo - 1e-12)
+        assert np.all(p.phi >= 0.0) and np.all(p.phi <= 1.0)
+        if irr == "damage":
+            assert np.all(p.phi >= p.phi_ref - 1e-12)
+
+
+def test_phase_field_kkt_after_step():
+    E = _hetero(seed=6)
+    p = oracle.Problem(E, nu=0.2, ell=1.5, gc=1.0, at=1, split="spectral", tol_mech=1e-11,
+                       tol_pf=1e-11, max_am=1)
+    em = np.sqrt(3 / (8 * 1.5 * (10 / 9)))
+    p.load_step((0.0, 1.1 * em, 0.0))
+    # the PF solve of the last AM iteration used the strain now stored
+    op = pf.Operator(p.psi_plus(), 1, 1.0, 1.5)
+    lo = pf.constraint_field(p.phi_ref, "crack_set")
+    r = op.J(p.phi) - op.b
+    scale = np.abs(op.b).max()
+    free = (p.phi > lo + 1e-12) & (p.phi < 1 - 1e-12)
+    assert np.abs(r[free]).max() < 1e-7 * scale * np.sqrt(p.phi.size)
+    assert np.all(r[p.phi <= lo + 1e-12] > -1e-7 * scale)
+
+
+def test_initial_crack_solve():
+    """Alg. 2, first two lines: with phi_init the phase field is solved at
+    zero strain under phi_con(phi_init)."""
+    n = 32
+    phi_init = np.zeros((n, n))
+    phi_init[n // 2, : n // 2] = 1.0
+    p = oracle.Problem(np.ones((n, n)), ell=2.0, at=1, phi_init=phi_init, tol_pf=1e-10)
+    assert np.all(p.phi >= pf.constraint_field(phi_init, "crack_set") - 1e-12)
+    assert p.phi[n // 2, 0] == 1.0 and 0 < p.phi[n // 2 + 1, 2] < 1
+    assert p.phi[0, -1] == 0.0
+
+
+def test_state_roundtrip_is_deterministic():
+    E = _hetero(seed=7)
+    kw = dict(nu=0.2, ell=1.5, gc=1.0, at=1, split="spectral", tol_mech=1e-9, tol_pf=1e-9, max_am=5)
+    em = np.sqrt(3 / (8 * 1.5 * (10 / 9)))
+    loads = [(0.0, f * em, 0.0) for f in (0.5, 1.0, 1.1)]
+    a = oracle.Problem(E, **kw)
+    for L in loads:
+        a.load_step(L)
+    b = oracle.Problem(E, **kw)
+    b.load_step(loads[0])
+    st = b.get_state()
+    c = oracle.Problem(E, **kw)
+    c.set_state(st)
+    for L in loads[1:]:
+        c.load_step(L)
+    np.testing.assert_array_equal(a.phi, c.phi)
+    np.testing.assert_array_equal(a.eps_star, c.eps_star)
+
+
+def test_displacement_matches_strain():
+    E = _hetero(seed=8)
+    p = oracle.Problem(E, nu=0.2, ell=1.5, at=1, split="none", tol_mech=1e-11)
+    p.load_step((0.02, 0.1, 0.03))
+    u = p.displacement()
+    from oracle import spectral as sp
+    np.testing.assert_allclose(sp.symmetric_gradient(u), p.eps_star, atol=1e-10)

@@ -1,0 +1,128 @@
+"""Pins for oracle.spectral: transform convention, compatibility projection,
+collocation Laplacian, displacement recovery (Sec. 3.1, 3.1.1, 3.1.2)."""
+
+import numpy as np
+import pytest
+
+from oracle import spectral as sp
+
+GRIDS = [(4, 4), (5, 7), (6, 6), (8, 16), (5, 4)]
+
+
+def brute_dft(f):
+    """The paper's forward transform written out (Sec. 3.1), with the 1/|N|
+    factor, on the index set in grid order."""
+    ny, nx = f.shape
+    out = np.zeros((ny, nx), dtype=complex)
+    for ky in range(ny):
+        for kx in range(nx):
+            s = 0.0
+            for jy in range(ny):
+                for jx in range(nx):
+                    s += f[jy, jx] * np.exp(-2j * np.pi * (kx * jx / nx + ky * jy / ny))
+            out[ky, kx] = s / (nx * ny)
+    return out
+
+
+@pytest.mark.parametrize("shape", GRIDS)
+def test_fft_matches_brute_force_dft(shape):
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal(shape)
+    np.testing.assert_allclose(sp.fft_field(f) / f.size, brute_dft(f), atol=1e-13)
+    np.testing.assert_allclose(sp.ifft_field(sp.fft_field(f)), f, atol=1e-13)
+
+
+def _rand_sym(rng, shape):
+    a = rng.standard_normal(shape + (2, 2))
+    return 0.5 * (a + np.swapaxes(a, -1, -2))
+
+
+def ddot_sum(a, b):
+    return float(np.sum(a * b))
+
+
+@pytest.mark.parametrize("shape", GRIDS)
+def test_projection_idempotent_selfadjoint(shape):
+    rng = np.random.default_rng(2)
+    a, b = _rand_sym(rng, shape), _rand_sym(rng, shape)
+    ga = sp.project(a)
+    np.testing.assert_allclose(sp.project(ga), ga, atol=1e-12)
+    assert abs(ddot_sum(ga, b) - ddot_sum(a, sp.project(b))) < 1e-10
+    # symmetric output, zero mean
+    np.testing.assert_allclose(ga, np.swapaxes(ga, -1, -2), atol=1e-13)
+    np.testing.assert_allclose(ga.mean(axis=(0, 1)), 0.0, atol=1e-13)
+    # constants are removed
+    c = np.broadcast_to(np.array([[1.0, 0.3], [0.3, -2.0]]), shape + (2, 2)).copy()
+    np.testing.assert_allclose(sp.project(c), 0.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("shape", GRIDS)
+def test_projection_keeps_gradients(shape):
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(shape + (2,))
+    eps = sp.symmetric_gradient(u)
+    np.testing.assert_allclose(sp.project(eps), eps, atol=1e-12)
+
+
+def _dense_range_projector(ny, nx):
+    """Orthogonal projector (in the A:B metric) onto the range of the
+    discrete symmetric gradient, from dense linear algebra.  Coordinates per
+    pixel: (e_xx, sqrt2 e_xy, e_yy), which turns A:B into the dot product."""
+    n = ny * nx
+    cols = []
+    for k in range(2 * n):
+        u = np.zeros(2 * n)
+        u[k] = 1.0
+        e = sp.symmetric_gradient(u.reshape(2, ny, nx).transpose(1, 2, 0))
+        cols.append(np.concatenate([e[..., 0, 0].ravel(), np.sqrt(2) * e[..., 0, 1].ravel(),
+                                    e[..., 1, 1].ravel()]))
+    B = np.array(cols).T
+    U, s, _ = np.linalg.svd(B, full_matrices=False)
+    rank = int(np.sum(s > 1e-9 * s.max()))
+    Ur = U[:, :rank]
+    return Ur @ Ur.T
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (5, 5), (4, 6), (5, 6), (3, 5)])
+def test_projection_equals_dense_projector(shape):
+    ny, nx = shape
+    n = ny * nx
+    P = _dense_range_projector(ny, nx)
+    G = np.zeros((3 * n, 3 * n))
+    for k in range(3 * n):
+        v = np.zeros(3 * n)
+        v[k] = 1.0
+        a = np.zeros((ny, nx, 2, 2))
+        a[..., 0, 0] = v[:n].reshape(ny, nx)
+        a[..., 0, 1] = a[..., 1, 0] = v[n:2 * n].reshape(ny, nx) / np.sqrt(2)
+        a[..., 1, 1] = v[2 * n:].reshape(ny, nx)
+        g = sp.project(a)
+        G[:, k] = np.concatenate([g[..., 0, 0].ravel(), np.sqrt(2) * g[..., 0, 1].ravel(),
+                                  g[..., 1, 1].ravel()])
+    np.testing.assert_allclose(G, P, atol=1e-10)
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (7, 9), (6, 10)])
+def test_laplacian_plane_waves(shape):
+    ny, nx = shape
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    for ky in range(ny // 2 + 1):
+        for kx in range(nx // 2 + 1):
+            f = np.cos(2 * np.pi * (kx * x / nx + ky * y / ny))
+            lam = (2 * np.pi * kx / nx) ** 2 + (2 * np.pi * ky / ny) ** 2
+            np.testing.assert_allclose(sp.laplacian(f), -lam * f, atol=1e-11)
+
+
+def test_laplacian_nyquist_checkerboard_kept():
+    f = np.fromfunction(lambda y, x: (-1.0) ** (x + y), (8, 8))
+    np.testing.assert_allclose(sp.laplacian(f), -2 * np.pi ** 2 * f, atol=1e-11)
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (9, 7), (6, 10)])
+def test_displacement_recovery_roundtrip(shape):
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal(shape + (2,))
+    eps = sp.symmetric_gradient(u)
+    u2 = sp.displacement_from_strain(eps)
+    np.testing.assert_allclose(sp.symmetric_gradient(u2), eps, atol=1e-11)
+    np.testing.assert_allclose(u2.mean(axis=(0, 1)), 0.0, atol=1e-12)
