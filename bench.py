@@ -1,0 +1,218 @@
+"""Benchmark: staggered FFT phase-field fracture solve on one MI355X.
+
+Workload (default, "batched"): 64 independent realizations of a 512x512
+periodic microstructure, E = max(1 + 0.2 z, 0.5) with z a unit-variance
+Gaussian random field of correlation length 16 px (seeds 3000..3063), AT1,
+strain-spectral split, l = 2 px, crack-set irreversibility, uniaxial-strain
+ramp of 200 load steps to 1.5 eps_M; FP32 fields with FP64 reductions; all
+realizations in one batched launch per kernel, independent per-problem
+progression.
+
+A "step" is one load step (alternating minimisation to Tol_AM: mechanics
+Newton-CG + phase-field BCCG) of every realization.  The ramp's early steps
+are run untimed to reach the window (preparation), then W warmup steps, then
+K timed steps.  value = (mechanics CG + BCCG iterations) x grid points per
+second over the timed steps.
+
+Also reported on the same line:
+  roofline      dominant kernel's algorithmic HBM bytes / its event time
+                (HIP events on the solver stream during the timed steps)
+  plain_gpu     the plain single-instance path (256x256, one problem,
+                host check after every tick) over its full 200-step ramp
+  cpu_baseline  the FP64 NumPy oracle on one host core, on a bounded sample
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-pt CG iters/s & HBM GB/s, batched FP32 vs plain GPU @1e-4 err; p50/p99"
+HBM_PEAK_GBS = 8000.0
+KERNELS = ("rowfwd", "col", "rowinv")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def iters(stats):
+    cg = sum(s["cg_iters"] for row in stats for s in row)
+    pf = sum(s["bccg_iters"] for row in stats for s in row)
+    return cg, pf
+
+
+def batched_leg(args):
+    import numpy as np
+    import torch
+
+    import spff_inputs as si
+    from paper_2203_16467_amd import spff
+
+    n, B = args.grid, args.batch
+    E = np.stack([si.young_modulus(n, args.corr, args.amp, 3000 + i) for i in range(B)])
+    ramp = si.uniaxial_ramp(200, 0.2, 2.0)
+    cfg = spff.default_config(nx=n, ny=n, use_graph=1, ticks_per_sync=16)
+    p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
+    s0 = args.start - args.warmup
+    t = time.time()
+    if s0 > 0:
+        p.run_sequence(ramp[:s0])
+    log(f"[bench] prepared {B}x{n}^2 to load step {s0} in {time.time() - t:.1f}s")
+    p.profile_enable(True)
+    if args.warmup > 0:
+        p.run_sequence(ramp[s0:args.start])
+    log(f"[bench] warmup steps {s0}..{args.start - 1} done")
+    p.profile_enable(True)  # reset the kernel totals for the timed region
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, stats = p.run_sequence(ramp[args.start:args.start + args.steps])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = p.profile_read()
+    cg, pf = iters(stats)
+    ncrack = sum(1 for row in stats if row[-1]["crack_px"] > 0)
+    log(f"[bench] timed {args.steps} steps in {dt:.2f}s: cg {cg} bccg {pf}, cracked {ncrack}/{B}, status {st}")
+    p.close()
+    return {"dt": dt, "cg": cg, "pf": pf, "status": st, "prof": prof, "ncrack": ncrack, "E0": E[0],
+            "ramp": ramp, "n": n, "B": B}
+
+
+def plain_leg(args):
+    import torch
+
+    import spff_inputs as si
+    from paper_2203_16467_amd import spff
+
+    n = 256
+    E = si.young_modulus(n, 8.0, 0.1, 2000)
+    ramp = si.uniaxial_ramp(200, 0.2, 2.0)
+    cfg = spff.default_config(nx=n, ny=n, use_graph=0, ticks_per_sync=1)
+    p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
+    p.run_sequence(ramp[:2])  # warmup
+    p.close()
+    p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, stats = p.run_sequence(ramp)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cg, pf = iters(stats)
+    p.close()
+    log(f"[bench] plain 256^2 single: 200 steps in {dt:.2f}s, cg {cg} bccg {pf}")
+    return {"value": (cg + pf) * n * n / dt, "unit": "grid-pt-iters/s",
+            "workload": "plain: one 256x256 problem (E = max(1+0.1z,0.5), corr 8 px, seed 2000), AT1, "
+                        "strain-spectral, l = 2 px, crack-set, 200-step ramp to 1.5 eps_M; host status check "
+                        "after every tick, no graph",
+            "seconds": dt, "cg_iters": cg, "bccg_iters": pf}
+
+
+def cpu_leg(res, budget_s):
+    """The FP64 oracle on one host core, realization 0 of the workload, for as
+    many load steps as fit the budget (at least one)."""
+    import numpy as np
+
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    E = res["E0"].astype(np.float64)
+    o = oracle.Problem(E, nu=0.2, ell=2.0, gc=1.0, at=1, split="spectral", tol_mech=1e-6, tol_pf=1e-6)
+    # sample: mechanics-dominated steps from an early state of the ramp
+    # (the oracle at a nucleation step can take hours)
+    ramp = res["ramp"]
+    t0 = time.perf_counter()
+    cg = pf = 0
+    k = 0
+    while True:
+        stt = o.load_step(ramp[20 + k])
+        cg += stt["cg"]
+        pf += stt["bccg"]
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister()
+    n = E.shape[0]
+    return {"value": (cg + pf) * n * n / dt, "unit": "grid-pt-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle, realization 0 ({n}x{n}), load steps 21..{20 + k} of the ramp from a "
+                      f"zero state (mechanics Newton-CG dominated; {cg} CG + {pf} BCCG iterations in {dt:.1f}s), "
+                      f"one thread",
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--start", type=int, default=88, help="first timed load step of the 200-step ramp")
+    ap.add_argument("--grid", type=int, default=512)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--corr", type=float, default=16.0)
+    ap.add_argument("--amp", type=float, default=0.2)
+    ap.add_argument("--no-plain", dest="plain", action="store_false")
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build runs one process on one MI355X "
+              f"(--gpus {args.gpus} is not supported; independent problems shard across GPUs by "
+              f"placement, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    if args.start < args.warmup or args.start + args.steps > 200:
+        sys.exit("window must lie inside the 200-step ramp")
+
+    res = batched_leg(args)
+    value = (res["cg"] + res["pf"]) * res["n"] ** 2 / res["dt"]
+    prof = res["prof"]
+    dom = max(KERNELS, key=lambda k: prof["kernel_ms"][k])
+    ms = prof["kernel_ms"][dom]
+    achieved = prof["alg_bytes"][dom] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    all_ms = sum(prof["kernel_ms"][k] for k in KERNELS)
+    all_b = sum(prof["alg_bytes"][k] for k in KERNELS)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-pt-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["dt"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched: {res['B']} realizations of {res['n']}x{res['n']} (E = max(1+{args.amp}z, 0.5), "
+                        f"corr {args.corr:g} px, seeds 3000..), AT1, strain-spectral split, l = 2 px, crack-set, "
+                        f"uniaxial-strain ramp of 200 steps to 1.5 eps_M; timed load steps {args.start}.."
+                        f"{args.start + args.steps - 1}; FP32 fields, FP64 reductions",
+            "batch": res["B"], "grid": [res["n"], res["n"]], "parallelism": "single GPU",
+        },
+        "breakdown": {"cg_iters": res["cg"], "bccg_iters": res["pf"], "seconds": res["dt"],
+                      "realizations_cracked": res["ncrack"], "status": res["status"],
+                      "kernel_ms": prof["kernel_ms"], "kernel_launches": prof["launches"],
+                      "alg_GBs_all_fft_kernels": all_b / (all_ms * 1e-3) / 1e9 if all_ms > 0 else None},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    if args.plain:
+        pl = plain_leg(args)
+        out["plain_gpu"] = pl
+        out["vs_plain"] = value / pl["value"]
+    if args.cpu_baseline:
+        out["cpu_baseline"] = cpu_leg(res, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * spff.h -- C ABI of the spectral phase-field fracture library for MI355X
+ * (gfx950).
+ *
+ * The library solves the staggered quasi-static phase-field fracture problem
+ * of Andrews & Pastewka, "Crack-path selection in phase-field models for
+ * brittle fracture" (arXiv:2203.16467) on 2-D periodic grids:
+ *   - mechanics: Fourier-Galerkin equilibrium with the strain as unknown,
+ *     eps = eps_bar + eps*, Newton on eps* with conjugate gradients on the
+ *     compatibility-projected tangent problem (Sec. 3.1.1);
+ *   - phase field: Fourier-collocation Laplacian, bound-constrained
+ *     conjugate gradients (Sec. 3.1.2, Algorithm 1);
+ *   - one load step = alternating minimisation at a prescribed macroscopic
+ *     strain until ||phi_n+1 - phi_n||_1 < Tol_AM (Sec. 3.2.1, Algorithm 2).
+ * Constitutive choices: isotropic energy with h(phi) = (1-phi)^2, or the
+ * strain-spectral split (Sec. 2.1); AT1 or AT2 local fracture energy;
+ * crack-set or damage irreversibility (Sec. 2.1, constraint field).
+ *
+ * Conventions shared by every entry point
+ *   - Grid: ny rows by nx columns, unit spacing, row-major [y][x] arrays.
+ *     nx and ny are powers of two, 8 <= n <= 4096.
+ *   - Tensors are stored as three planes (xx, yy, xy) of tensor components
+ *     (the shear plane holds eps_xy, not the engineering strain).
+ *   - "real" is float for precision SPFF_FP32 (fields stored and transformed
+ *     in FP32, every dot product, norm and energy sum accumulated in FP64)
+ *     and double for SPFF_FP64.  All device arrays passed in or out use the
+ *     problem's real type.
+ *   - Device pointers are HIP device addresses on the current device; the
+ *     caller owns all of them.  The library never allocates device memory:
+ *     every persistent and scratch array lives in the caller's workspace.
+ *     It allocates small host-side handles and pinned host status buffers.
+ *   - The stream argument is a hipStream_t passed as void* (NULL = the
+ *     default stream).  All device work of a handle is enqueued on it; calls
+ *     that return results synchronise that stream.
+ *   - Return value: 0 = OK, > 0 = warning (results valid), < 0 = error;
+ *     after an error the state of the handle is unchanged unless stated.
+ *     spff_last_error() returns a thread-local message for the last non-OK
+ *     status.
+ *   - A handle is not thread-safe; use it from one thread at a time.
+ */
+#ifndef SPFF_H
+#define SPFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPFF_OK = 0,
+  SPFF_WARN_NOT_CONVERGED = 1, /* an iteration cap was hit; fields valid */
+  SPFF_E_INVALID = -1,         /* bad argument / configuration / input field */
+  SPFF_E_NOMEM = -2,           /* workspace too small */
+  SPFF_E_DEVICE = -3,          /* HIP runtime error */
+  SPFF_E_NONFINITE = -4,       /* a reduction produced NaN or Inf */
+  SPFF_E_BUSY = -5             /* request still pending / no free slot */
+} spff_status;
+
+enum { SPFF_AT1 = 1, SPFF_AT2 = 2 };
+enum { SPFF_SPLIT_NONE = 0, SPFF_SPLIT_SPECTRAL = 1 };
+enum { SPFF_IRR_CRACK_SET = 0, SPFF_IRR_DAMAGE = 1 };
+enum { SPFF_FP32 = 0, SPFF_FP64 = 1 };
+
+/* Field selection bits for spff_get_fields, in output order. */
+enum {
+  SPFF_FIELD_PHI = 1u << 0,      /* phase field phi, 1 plane */
+  SPFF_FIELD_PHI_REF = 1u << 1,  /* irreversibility reference: phi at the start
+                                    of the last load step, 1 plane */
+  SPFF_FIELD_STRAIN = 1u << 2,   /* total strain eps_bar + eps*, 3 planes */
+  SPFF_FIELD_STRESS = 1u << 3,   /* stress sigma(eps, phi), 3 planes */
+  SPFF_FIELD_PSI_PLUS = 1u << 4, /* crack driving energy psi0+(eps), 1 plane */
+  SPFF_FIELD_EPS_STAR = 1u << 5  /* strain fluctuation eps*, 3 planes */
+};
+
+/* Problem configuration (Sec. 2.1, 3.1, 3.2.1; defaults from
+ * spff_default_config). */
+typedef struct spff_config {
+  int32_t nx, ny;          /* grid, powers of two in [8, 4096] */
+  int32_t at;              /* SPFF_AT1 (w = phi, c_w = 8/3) or SPFF_AT2 (w = phi^2, c_w = 2) */
+  int32_t split;           /* SPFF_SPLIT_NONE (isotropic) or SPFF_SPLIT_SPECTRAL */
+  int32_t irreversibility; /* SPFF_IRR_CRACK_SET or SPFF_IRR_DAMAGE */
+  int32_t precision;       /* SPFF_FP32 or SPFF_FP64 */
+  double nu;               /* Poisson ratio, -1 < nu < 0.5 (plane strain) */
+  double ell;              /* regularisation length in pixels, > 0 */
+  double gc;               /* critical energy release rate, > 0 */
+  double crack_set_threshold; /* crack-set constraint: phi_ref >= threshold (0.9) */
+  double k_res;            /* residual stiffness added to h(phi); 0 in the paper */
+  double eta_over_dt;      /* viscous term eta/dt; 0 = alternating minimisation */
+  double tol_mech, tol_abs_mech; /* mechanics: ||G[sigma]|| <= tol*max(||sigma_hom||,||R0||) + tol_abs */
+  double tol_pf, tol_abs_pf;     /* phase field: ||r|| <= tol*max(||b||,||r0||) + tol_abs */
+  double tol_am;           /* AM stop: sum |phi_n+1 - phi_n| < tol_am (pixel units); <0: 1e-3 ell^2 */
+  int32_t max_cg, max_newton, max_bccg, max_am; /* iteration caps */
+  int32_t ticks_per_sync;  /* solver ticks enqueued between host status checks (>= 1) */
+  int32_t use_graph;       /* 1: replay the tick block as a captured HIP graph */
+  /* Attainable-accuracy floor (not in the paper): a residual evaluated in the
+   * working precision u carries rounding noise of about u sqrt(log2(nx ny))
+   * times the norm of the terms it is computed from, so a sub-solve also
+   * stops when ||residual|| <= floor_factor u sqrt(log2(nx ny)) *
+   * (||sigma|| for mechanics; ||d phi|| + kappa <|2 pi q|^2> ||phi|| + ||b||
+   * for the phase field, <.> the mean over the grid's modes).  0 disables it.
+   * Irrelevant in FP64 at the default tolerances; what lets FP32 solves
+   * terminate instead of iterating on rounding noise. */
+  double floor_factor;
+  int32_t stall_iters;     /* BCCG stops when its residual has not improved for this many iterations (0: off) */
+  int32_t pad_;
+} spff_config;
+
+/* Per-problem result of one load step (Sec. 3.2.1 quantities). */
+typedef struct spff_step_stats {
+  int32_t status;          /* spff_status of this problem's step */
+  int32_t am_iters;        /* alternating-minimisation iterations */
+  int32_t newton_iters;    /* mechanics Newton steps (sum over AM iterations) */
+  int32_t cg_iters;        /* mechanics CG iterations (sum) */
+  int32_t bccg_iters;      /* phase-field BCCG iterations (sum) */
+  int32_t ticks;           /* solver ticks the step took */
+  double dphi_l1;          /* last ||phi_n+1 - phi_n||_1 */
+  double mech_residual;    /* last ||G[sigma]||_2 */
+  double pf_residual;      /* last BCCG ||r||_2 */
+  double F_e, F_f;         /* elastic and fracture energy (pixel area 1) */
+  double sigma_bar[3];     /* mean stress (xx, yy, xy) */
+  double C_bar;            /* sigma_bar_ij / eps_bar_ij at the largest |eps_bar_ij| */
+  double phi_max, phi_mean;
+  int64_t crack_px;        /* pixels with phi > 0.9 */
+  double wall_ms;          /* host wall time from enqueueing the step to observing its end */
+} spff_step_stats;
+
+typedef struct spff_problem spff_problem; /* opaque: a batch of 1..B problems */
+
+/* Fill *cfg with defaults: 64x64, AT1, spectral split, crack-set (0.9),
+ * FP32, nu 0.2, ell 2, gc 1, tolerances 1e-6, tol_am -1 (1e-3 ell^2),
+ * caps cg 20000 / newton 50 / bccg 20000 / am 1000, ticks_per_sync 1,
+ * use_graph 0, floor_factor 2, stall_iters 200. */
+void spff_default_config(spff_config* cfg);
+
+/* Workspace bytes for a batch of nbatch problems with this configuration
+ * (resident state + solver scratch + FFT tables + control blocks). */
+spff_status spff_workspace_bytes(const spff_config* cfg, int32_t nbatch, size_t* bytes);
+
+/* Create a batch of nbatch independent problems sharing cfg.
+ *   E_dev:        device, real[nbatch][ny][nx], Young's modulus (> 0, finite);
+ *                 copied into the workspace (the caller may free it after).
+ *   phi_init_dev: device, real[nbatch][ny][nx] in [0,1] or NULL (phi = 0).
+ *                 If given, the phase field is first solved at zero strain
+ *                 with phi_con(phi_init) (Algorithm 2, first two lines).
+ *   workspace:    device, >= spff_workspace_bytes bytes, 256-byte aligned,
+ *                 owned by the caller and kept alive until destroy.
+ * Errors: SPFF_E_INVALID (config or E/phi_init values), SPFF_E_NOMEM
+ * (workspace too small), SPFF_E_DEVICE. */
+spff_status spff_create_batch(const spff_config* cfg, int32_t nbatch, const void* E_dev,
+                              const void* phi_init_dev, void* workspace, size_t workspace_bytes,
+                              void* stream, spff_problem** out);
+
+/* spff_create_batch with nbatch = 1. */
+spff_status spff_create_problem(const spff_config* cfg, const void* E_dev, const void* phi_init_dev,
+                                void* workspace, size_t workspace_bytes, void* stream,
+                                spff_problem** out);
+
+/* One load step (Algorithm 2 at macroscopic strain eps_bar) for every
+ * problem of the batch.
+ *   eps_bar: host, double[nbatch][3] (xx, yy, xy).
+ *   stats:   host, spff_step_stats[nbatch] or NULL.
+ * Returns the worst per-problem status (errors before warnings).  Blocks
+ * until the step has finished on the device. */
+spff_status spff_load_step_batch(spff_problem* p, const double* eps_bar, spff_step_stats* stats);
+
+/* Independent load-step sequences: problem b runs its own nsteps steps at
+ * eps_bar[b][0..nsteps-1][3] (host, double[nbatch][nsteps][3]); a problem
+ * that finishes a step starts its next one at the following status check
+ * without waiting for the others (problems never synchronise with each
+ * other).  stats: host spff_step_stats[nbatch][nsteps] or NULL.  Returns the
+ * worst status over all steps; blocks until every sequence is done. */
+spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps_bar, spff_step_stats* stats);
+
+/* spff_load_step_batch for a problem created with nbatch = 1. */
+spff_status spff_load_step(spff_problem* p, const double eps_bar[3], spff_step_stats* stats);
+
+/* Copy fields of problem `index` (0..nbatch-1), or of all problems when
+ * index = -1 (then each output is real[nbatch][planes][ny][nx]), into caller
+ * device buffers: dst[i] receives the i-th field selected by mask, in the
+ * bit order of the SPFF_FIELD_* enum.  Synchronises the stream. */
+spff_status spff_get_fields(spff_problem* p, int32_t index, uint32_t mask, void* const* dst);
+
+/* State = (eps*[3], phi, phi_ref) planes: real[nbatch][5][ny][nx] on the
+ * device, plus the macroscopic strain of the last step (host double[nbatch][3],
+ * may be NULL).  get copies out, set copies in (no validation of values
+ * beyond finiteness is made). */
+size_t spff_state_bytes(const spff_problem* p);
+spff_status spff_get_state(spff_problem* p, void* dst_dev, double* eps_bar_host);
+spff_status spff_set_state(spff_problem* p, const void* src_dev, const double* eps_bar_host);
+
+/* Spectral operators of the solver applied to caller fields of every problem
+ * of the batch, with the solver's own FFT kernels and the handle's scratch
+ * (not while a step runs):
+ *   SPFF_OP_PROJECT       out = G[in]: the compatibility projection of
+ *                         Sec. 3.1.1 (orthogonal projector onto compatible,
+ *                         zero-mean strain fields); in/out
+ *                         real[nbatch][3][ny][nx] (xx, yy, xy planes)
+ *   SPFF_OP_NEG_LAPLACIAN out = -lap_N in, the collocation Laplacian of
+ *                         Sec. 3.1.2 (true |2 pi q|^2 at Nyquist); in/out
+ *                         real[nbatch][ny][nx]
+ * in and out are device buffers owned by the caller and may alias.
+ * Synchronises the stream. */
+enum { SPFF_OP_PROJECT = 0, SPFF_OP_NEG_LAPLACIAN = 1 };
+spff_status spff_apply_operator(spff_problem* p, int32_t op, const void* in_dev, void* out_dev);
+
+/* Kernel profiling.  While enabled, every solver tick records HIP events on
+ * the handle's stream around each of its four kernels (row-forward FFT,
+ * column FFT, row-inverse FFT, controller), and the controller accumulates
+ * each kernel's algorithmic HBM bytes for the phase every problem executed
+ * (the bytes a fused implementation must move: inputs read once, outputs
+ * written once, half spectra round-tripped).  Enabling resets the totals. */
+typedef struct spff_profile {
+  double kernel_ms[4];     /* summed event time per kernel */
+  int64_t launches[4];     /* launches per kernel */
+  double alg_bytes[4];     /* summed algorithmic bytes per kernel */
+  int64_t ticks;
+} spff_profile;
+spff_status spff_profile_enable(spff_problem* p, int32_t enable);
+spff_status spff_profile_read(spff_problem* p, spff_profile* out);
+
+/* Number of problems, grid and precision of a handle. */
+spff_status spff_problem_info(const spff_problem* p, int32_t* nbatch, int32_t* nx, int32_t* ny,
+                              int32_t* precision);
+
+/* Release the host handle (the caller frees the workspace). */
+spff_status spff_destroy_problem(spff_problem* p);
+
+/* Thread-local message for the last non-OK status ("" if none). */
+const char* spff_last_error(void);
+
+/* Library version string. */
+const char* spff_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPFF_H */

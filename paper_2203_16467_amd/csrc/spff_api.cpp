@@ -1,0 +1,846 @@
+// C-ABI implementation: validation, workspace layout, FFT tables, the tick
+// loop and result readback.  See include/spff.h for the contract.
+#include "spff.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "spff_engine.hpp"
+#include "spff_launch.hpp"
+
+using namespace spff;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+spff_status fail(spff_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(SPFF_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr int THREADS = 256;
+constexpr int MAXE = 8;
+constexpr int PAD = 1;
+constexpr size_t LDS_TARGET = 60 * 1024;
+constexpr size_t LDS_MAX = 150 * 1024;
+
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+inline bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+struct Layout {
+  size_t ctl, prm, ptr, twx, twy, prow, pcol, pinv, list, bad, prof;
+  size_t slot0, slot_bytes;
+  // offsets inside a slot
+  size_t E, phi, phi_ref, eps, theta, rm, pm, spec;
+  size_t total;
+};
+
+spff_status check_config(const spff_config* c) {
+  if (!c) return fail(SPFF_E_INVALID, "config is NULL");
+  if (!pow2(c->nx) || !pow2(c->ny) || c->nx < 8 || c->ny < 8 || c->nx > 2048 || c->ny > 2048)
+    return fail(SPFF_E_INVALID, "nx, ny must be powers of two in [8, 2048] (got %d x %d)", c->nx, c->ny);
+  if (!(c->nu > -1.0 && c->nu < 0.5)) return fail(SPFF_E_INVALID, "nu must lie in (-1, 0.5)");
+  if (!(c->ell > 0.0) || !std::isfinite(c->ell)) return fail(SPFF_E_INVALID, "ell must be > 0");
+  if (!(c->gc > 0.0) || !std::isfinite(c->gc)) return fail(SPFF_E_INVALID, "gc must be > 0");
+  if (c->at != SPFF_AT1 && c->at != SPFF_AT2) return fail(SPFF_E_INVALID, "at must be 1 or 2");
+  if (c->split != SPFF_SPLIT_NONE && c->split != SPFF_SPLIT_SPECTRAL) return fail(SPFF_E_INVALID, "bad split");
+  if (c->irreversibility != SPFF_IRR_CRACK_SET && c->irreversibility != SPFF_IRR_DAMAGE)
+    return fail(SPFF_E_INVALID, "bad irreversibility");
+  if (c->precision != SPFF_FP32 && c->precision != SPFF_FP64) return fail(SPFF_E_INVALID, "bad precision");
+  if (!(c->k_res >= 0.0) || !(c->eta_over_dt >= 0.0)) return fail(SPFF_E_INVALID, "k_res, eta_over_dt >= 0");
+  if (!(c->tol_mech >= 0.0) || !(c->tol_pf >= 0.0) || !(c->tol_abs_mech >= 0.0) || !(c->tol_abs_pf >= 0.0))
+    return fail(SPFF_E_INVALID, "tolerances must be >= 0");
+  if (c->max_cg < 1 || c->max_newton < 1 || c->max_bccg < 1 || c->max_am < 1)
+    return fail(SPFF_E_INVALID, "iteration caps must be >= 1");
+  if (c->ticks_per_sync < 1 || c->ticks_per_sync > 4096) return fail(SPFF_E_INVALID, "ticks_per_sync in [1, 4096]");
+  if (!(c->floor_factor >= 0.0) || c->stall_iters < 0) return fail(SPFF_E_INVALID, "floor_factor, stall_iters >= 0");
+  return SPFF_OK;
+}
+
+// Launch geometry: rows per row work-group R and columns per column
+// work-group W are the largest powers of two whose LDS tiles (3 components,
+// padded) stay within LDS_TARGET (at least one row / column).
+LaunchGeom plan(const spff_config* c, int S, size_t csize) {
+  LaunchGeom G{};
+  G.nx = c->nx;
+  G.ny = c->ny;
+  G.S = S;
+  const int M = c->nx / 2;
+  // at least ~TARGET_WG work-groups per launch when the batch allows it
+  const long TARGET_WG = 1024;
+  int R = 1;
+  while (R * 2 <= c->ny && 3 * (size_t)(2 * R) * (M + PAD) * csize <= LDS_TARGET &&
+         (long)(c->ny / (2 * R)) * S >= TARGET_WG)
+    R *= 2;
+  int W = 1;
+  while (W * 2 <= M && 3 * (size_t)(2 * W) * (c->ny + PAD) * csize <= LDS_TARGET &&
+         (long)(M / (2 * W)) * S >= TARGET_WG)
+    W *= 2;
+  G.R = R;
+  G.ngr = c->ny / R;
+  G.W = W;
+  G.ngc = M / W;
+  G.lds_row = 3 * (size_t)R * (M + PAD) * csize;
+  G.lds_col = 3 * (size_t)W * (c->ny + PAD) * csize;
+  return G;
+}
+
+Layout layout(const spff_config* c, int S, size_t rsize) {
+  Layout L{};
+  const size_t n = (size_t)c->nx * c->ny;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.ctl = take(sizeof(SlotCtl) * S);
+  L.prm = take(sizeof(SlotParam) * S);
+  L.ptr = take(sizeof(SlotPtr<double>) * S);
+  L.twx = take(2 * rsize * c->nx);
+  L.twy = take(2 * rsize * c->ny);
+  // partial sums sized for the finest launch plan (one row / column per group)
+  L.prow = take(sizeof(double) * S * c->ny * NP_ROW);
+  L.pcol = take(sizeof(double) * S * (c->nx / 2) * NP_COL);
+  L.pinv = take(sizeof(double) * S * c->ny * NP_INV);
+  L.list = take(sizeof(int32_t) * S);
+  L.bad = take(64);
+  L.prof = take(sizeof(double) * 3 * S);
+  L.slot0 = off;
+  size_t so = 0;
+  auto stake = [&](size_t bytes) {
+    size_t o = so;
+    so = align_up(so + bytes);
+    return o;
+  };
+  L.E = stake(rsize * n);
+  L.phi = stake(rsize * n);
+  L.phi_ref = stake(rsize * n);
+  L.eps = stake(3 * rsize * n);
+  L.theta = stake(3 * rsize * n);
+  L.rm = stake(3 * rsize * n);
+  L.pm = stake(3 * rsize * n);
+  L.spec = stake(3 * 2 * rsize * (size_t)(c->nx / 2) * c->ny);
+  L.slot_bytes = so;
+  L.total = L.slot0 + (size_t)S * so;
+  return L;
+}
+
+}  // namespace
+
+struct spff_problem {
+  spff_config cfg;
+  int S;
+  size_t rsize;
+  Layout L;
+  unsigned char* ws;
+  hipStream_t stream;
+  hipStream_t cap_stream;
+  // launch plans by number of active slots: bucket b covers up to
+  // bucket_size[b] slots (powers of two, the last one = S)
+  std::vector<int> bucket_size;
+  std::vector<LaunchGeom> geoms;
+  std::vector<hipGraphExec_t> graphs;  // one captured tick block per bucket (lazy)
+  int cur_bucket = -1;
+  int32_t* host_list = nullptr;  // pinned staging of the device slot list
+  std::vector<int32_t> cur_list;
+  SlotCtl* host_ctl;  // pinned mirror
+  std::vector<SlotParam> prm;
+  std::vector<double> last_eps_bar;
+  // profiling
+  bool prof_on = false;
+  std::vector<hipEvent_t> events;  // 5 per tick of a block
+  double kernel_ms[4] = {0, 0, 0, 0};
+  int64_t launches[4] = {0, 0, 0, 0};
+  int64_t prof_ticks = 0;
+
+  SlotCtl* d_ctl() const { return reinterpret_cast<SlotCtl*>(ws + L.ctl); }
+  SlotParam* d_prm() const { return reinterpret_cast<SlotParam*>(ws + L.prm); }
+  void* d_ptr() const { return ws + L.ptr; }
+  double* d_prof() const { return reinterpret_cast<double*>(ws + L.prof); }
+  int32_t* d_list() const { return reinterpret_cast<int32_t*>(ws + L.list); }
+  unsigned char* slot(int s) const { return ws + L.slot0 + (size_t)s * L.slot_bytes; }
+  size_t n() const { return (size_t)cfg.nx * cfg.ny; }
+};
+
+namespace {
+
+template <typename real>
+hipError_t enqueue_tick(spff_problem* p, hipStream_t st, int i, int b) {
+  using C = typename HostCplx<real>::type;
+  hipEvent_t* ev = (p->prof_on && (size_t)(5 * i + 5) <= p->events.size()) ? &p->events[5 * i] : nullptr;
+  return launch_tick<real>(p->geoms[b], p->d_list(), reinterpret_cast<const SlotPtr<real>*>(p->d_ptr()),
+                           p->d_prm(), p->d_ctl(),
+                           reinterpret_cast<const C*>(p->ws + p->L.twx),
+                           reinterpret_cast<const C*>(p->ws + p->L.twy),
+                           reinterpret_cast<double*>(p->ws + p->L.prow),
+                           reinterpret_cast<double*>(p->ws + p->L.pcol),
+                           reinterpret_cast<double*>(p->ws + p->L.pinv), p->prof_on ? p->d_prof() : nullptr, ev,
+                           st);
+}
+
+hipError_t enqueue_ticks(spff_problem* p, int k, hipStream_t st, int b) {
+  for (int i = 0; i < k; ++i) {
+    hipError_t e =
+        p->cfg.precision == SPFF_FP64 ? enqueue_tick<double>(p, st, i, b) : enqueue_tick<float>(p, st, i, b);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// After a synchronised block of k ticks: fold the event times into the
+// profile totals.
+void collect_profile(spff_problem* p, int k) {
+  if (!p->prof_on) return;
+  for (int i = 0; i < k && (size_t)(5 * i + 5) <= p->events.size(); ++i) {
+    for (int j = 0; j < 4; ++j) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p->events[5 * i + j], p->events[5 * i + j + 1]) == hipSuccess) {
+        p->kernel_ms[j] += ms;
+        p->launches[j] += 1;
+      }
+    }
+    p->prof_ticks += 1;
+  }
+}
+
+spff_status build_graph(spff_problem* p, int b) {
+  const int K = p->cfg.ticks_per_sync;
+  if (p->graphs[b]) {
+    HIP_TRY(hipGraphExecDestroy(p->graphs[b]));
+    p->graphs[b] = nullptr;
+  }
+  if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  const bool prof = p->prof_on;
+  p->prof_on = false;  // event timings are taken from eager launches only
+  hipError_t e = enqueue_ticks(p, K, p->cap_stream, b);
+  p->prof_on = prof;
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
+  if (e != hipSuccess) return fail(SPFF_E_DEVICE, "tick capture failed: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(SPFF_E_DEVICE, "end capture failed: %s", hipGetErrorString(e2));
+  HIP_TRY(hipGraphInstantiate(&p->graphs[b], graph, nullptr, nullptr, 0));
+  HIP_TRY(hipGraphDestroy(graph));
+  return SPFF_OK;
+}
+
+void drop_graphs(spff_problem* p) {
+  for (auto& g : p->graphs)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Upload the slot list for `b` (active slots, padded with -1) if it changed.
+spff_status set_list(spff_problem* p, const std::vector<int32_t>& active, int b) {
+  std::vector<int32_t> lst(active);
+  lst.resize(p->bucket_size[b], -1);
+  if (lst == p->cur_list) return SPFF_OK;
+  // the previous upload was followed by a synchronisation, so the pinned
+  // staging buffer is free
+  std::copy(lst.begin(), lst.end(), p->host_list);
+  HIP_TRY(hipMemcpyAsync(p->d_list(), p->host_list, sizeof(int32_t) * lst.size(), hipMemcpyHostToDevice,
+                         p->stream));
+  p->cur_list.swap(lst);
+  return SPFF_OK;
+}
+
+int bucket_for(const spff_problem* p, int nactive) {
+  int b = 0;
+  while (p->bucket_size[b] < nactive) ++b;
+  return b;
+}
+
+// Enqueue one block of ticks over the slots that are not idle (host mirror)
+// with the launch plan of their count.  Returns SPFF_OK without launching
+// when no slot is active.
+spff_status launch_block(spff_problem* p, bool* launched, int* nticks) {
+  std::vector<int32_t> active;
+  for (int s = 0; s < p->S; ++s)
+    if (p->host_ctl[s].phase != PH_IDLE) active.push_back(s);
+  *launched = false;
+  *nticks = 0;
+  if (active.empty()) return SPFF_OK;
+  const int b = bucket_for(p, (int)active.size());
+  spff_status st = set_list(p, active, b);
+  if (st != SPFF_OK) return st;
+  const int K = p->cfg.ticks_per_sync;
+  if (p->cfg.use_graph && !p->prof_on) {
+    if (!p->graphs[b]) {
+      st = build_graph(p, b);
+      if (st != SPFF_OK) return st;
+    }
+    HIP_TRY(hipGraphLaunch(p->graphs[b], p->stream));
+  } else {
+    hipError_t e = enqueue_ticks(p, K, p->stream, b);
+    if (e != hipSuccess) return fail(SPFF_E_DEVICE, "tick launch failed: %s", hipGetErrorString(e));
+  }
+  *launched = true;
+  *nticks = K;
+  return SPFF_OK;
+}
+
+// Run ticks until every slot is idle.
+spff_status run_until_idle(spff_problem* p) {
+  const size_t cbytes = sizeof(SlotCtl) * p->S;
+  for (;;) {
+    bool launched;
+    int k;
+    spff_status st = launch_block(p, &launched, &k);
+    if (st != SPFF_OK) return st;
+    if (!launched) break;
+    HIP_TRY(hipMemcpyAsync(p->host_ctl, p->d_ctl(), cbytes, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    collect_profile(p, k);
+  }
+  return SPFF_OK;
+}
+
+template <typename real>
+void fill_twiddles(std::vector<unsigned char>& out, int n) {
+  using C = typename HostCplx<real>::type;
+  out.resize(sizeof(C) * n);
+  C* t = reinterpret_cast<C*>(out.data());
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int k = 0; k < n; ++k) {
+    const double a = -two_pi * (double)k / (double)n;
+    t[k].x = (real)std::cos(a);
+    t[k].y = (real)std::sin(a);
+  }
+}
+
+SlotParam make_param(const spff_config* c) {
+  SlotParam P{};
+  const double nu = c->nu;
+  P.lam_t = nu / (1.0 - nu - 2.0 * nu * nu);  // Sec. 2.1, per unit E
+  P.mu_t = 1.0 / (2.0 + 2.0 * nu);
+  P.ell = c->ell;
+  P.gc = c->gc;
+  const double cw = c->at == SPFF_AT1 ? 8.0 / 3.0 : 2.0;
+  P.cwl = c->gc / (cw * c->ell);
+  P.kappa = 2.0 * c->gc * c->ell / cw;
+  P.wpp = c->at == SPFF_AT1 ? 0.0 : 2.0;
+  P.dw0 = c->at == SPFF_AT1 ? 1.0 : 0.0;
+  P.eta_dt = c->eta_over_dt;
+  P.k_res = c->k_res;
+  P.threshold = c->crack_set_threshold;
+  P.tol_mech = c->tol_mech;
+  P.tol_abs_mech = c->tol_abs_mech;
+  P.tol_pf = c->tol_pf;
+  P.tol_abs_pf = c->tol_abs_pf;
+  P.tol_am = c->tol_am < 0.0 ? 1e-3 * c->ell * c->ell : c->tol_am;
+  const double u = c->precision == SPFF_FP64 ? 0x1p-53 : 0x1p-24;
+  P.floor_coef = c->floor_factor * u * std::sqrt(std::log2((double)c->nx * (double)c->ny));
+  // mean of |2 pi q|^2 over the grid's modes: rounding noise of the
+  // transforms is spread evenly over the spectrum
+  P.lap_rms = 4.0 * M_PI * M_PI / 6.0;
+  P.stall_iters = c->stall_iters;
+  P.at = c->at;
+  P.split = c->split;
+  P.irr = c->irreversibility;
+  P.max_cg = c->max_cg;
+  P.max_newton = c->max_newton;
+  P.max_bccg = c->max_bccg;
+  P.max_am = c->max_am;
+  return P;
+}
+
+template <typename real>
+spff_status init_device(spff_problem* p, const void* E_dev, const void* phi_init_dev) {
+  const size_t n = p->n();
+  const size_t rb = sizeof(real) * n;
+  std::vector<SlotPtr<real>> ptrs(p->S);
+  for (int s = 0; s < p->S; ++s) {
+    unsigned char* b = p->slot(s);
+    ptrs[s].E = reinterpret_cast<const real*>(b + p->L.E);
+    ptrs[s].phi = reinterpret_cast<real*>(b + p->L.phi);
+    ptrs[s].phi_ref = reinterpret_cast<real*>(b + p->L.phi_ref);
+    ptrs[s].eps = reinterpret_cast<real*>(b + p->L.eps);
+    ptrs[s].theta = reinterpret_cast<real*>(b + p->L.theta);
+    ptrs[s].rm = reinterpret_cast<real*>(b + p->L.rm);
+    ptrs[s].pm = reinterpret_cast<real*>(b + p->L.pm);
+    ptrs[s].spec = reinterpret_cast<void*>(b + p->L.spec);
+  }
+  HIP_TRY(hipMemcpyAsync(p->d_ptr(), ptrs.data(), sizeof(SlotPtr<real>) * p->S, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_prm(), p->prm.data(), sizeof(SlotParam) * p->S, hipMemcpyHostToDevice, p->stream));
+  std::vector<unsigned char> tw;
+  fill_twiddles<real>(tw, p->cfg.nx);
+  HIP_TRY(hipMemcpyAsync(p->ws + p->L.twx, tw.data(), tw.size(), hipMemcpyHostToDevice, p->stream));
+  fill_twiddles<real>(tw, p->cfg.ny);
+  HIP_TRY(hipMemcpyAsync(p->ws + p->L.twy, tw.data(), tw.size(), hipMemcpyHostToDevice, p->stream));
+  // the synchronous twiddle staging buffer is reused: wait for the copies
+  HIP_TRY(hipStreamSynchronize(p->stream));
+
+  // inputs and zeroed state
+  unsigned int* bad = reinterpret_cast<unsigned int*>(p->ws + p->L.bad);
+  HIP_TRY(hipMemsetAsync(bad, 0, 2 * sizeof(unsigned int), p->stream));
+  for (int s = 0; s < p->S; ++s) {
+    unsigned char* b = p->slot(s);
+    HIP_TRY(hipMemcpyAsync(b + p->L.E, static_cast<const unsigned char*>(E_dev) + s * rb, rb,
+                           hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemsetAsync(b + p->L.eps, 0, 3 * rb, p->stream));
+    HIP_TRY(hipMemsetAsync(b + p->L.theta, 0, 3 * rb, p->stream));
+    HIP_TRY(hipMemsetAsync(b + p->L.rm, 0, 3 * rb, p->stream));
+    HIP_TRY(hipMemsetAsync(b + p->L.pm, 0, 3 * rb, p->stream));
+    if (phi_init_dev) {
+      const unsigned char* src = static_cast<const unsigned char*>(phi_init_dev) + s * rb;
+      HIP_TRY(hipMemcpyAsync(b + p->L.phi, src, rb, hipMemcpyDeviceToDevice, p->stream));
+      HIP_TRY(hipMemcpyAsync(b + p->L.phi_ref, src, rb, hipMemcpyDeviceToDevice, p->stream));
+    } else {
+      HIP_TRY(hipMemsetAsync(b + p->L.phi, 0, rb, p->stream));
+      HIP_TRY(hipMemsetAsync(b + p->L.phi_ref, 0, rb, p->stream));
+    }
+    HIP_TRY(launch_validate<real>(reinterpret_cast<const real*>(b + p->L.E), n, 0.0, -1e300, 1e300, bad,
+                                  p->stream));
+    if (phi_init_dev)
+      HIP_TRY(launch_validate<real>(reinterpret_cast<const real*>(b + p->L.phi), n, -1e300, 0.0, 1.0, bad + 1,
+                                    p->stream));
+  }
+  unsigned int hbad[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (hbad[0]) return fail(SPFF_E_INVALID, "E has %u non-positive or non-finite entries", hbad[0]);
+  if (hbad[1]) return fail(SPFF_E_INVALID, "phi_init has %u entries outside [0, 1]", hbad[1]);
+  return SPFF_OK;
+}
+
+void reset_ctl(spff_problem* p, int s) {
+  SlotCtl& c = p->host_ctl[s];
+  std::memset(&c, 0, sizeof(SlotCtl));
+}
+
+spff_status slot_status(const SlotCtl& c) {
+  if (c.status < 0) return (spff_status)c.status;
+  if (c.flags & FL_NOT_CONVERGED) return SPFF_WARN_NOT_CONVERGED;
+  return SPFF_OK;
+}
+
+void fill_stats(const spff_problem* p, const SlotCtl& c, spff_step_stats& o, double wall_ms) {
+  std::memset(&o, 0, sizeof(o));
+  o.status = slot_status(c);
+  o.am_iters = c.am;
+  o.newton_iters = c.newton;
+  o.cg_iters = c.cg;
+  o.bccg_iters = c.bccg;
+  o.ticks = c.ticks;
+  o.dphi_l1 = c.dphi;
+  o.mech_residual = c.mech_res;
+  o.pf_residual = c.pf_res;
+  o.F_e = c.F_e;
+  o.F_f = c.F_f;
+  for (int k = 0; k < 3; ++k) o.sigma_bar[k] = c.sbar[k];
+  int kmax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (std::fabs(c.eps_bar[k]) > std::fabs(c.eps_bar[kmax])) kmax = k;
+  o.C_bar = c.eps_bar[kmax] != 0.0 ? c.sbar[kmax] / c.eps_bar[kmax] : NAN;
+  o.phi_max = c.phi_max;
+  o.phi_mean = c.phi_sum / (double)p->n();
+  o.crack_px = (int64_t)std::llround(c.crack_px);
+  o.wall_ms = wall_ms;
+}
+
+void start_step(spff_problem* p, int s, const double* eb) {
+  reset_ctl(p, s);
+  SlotCtl& c = p->host_ctl[s];
+  for (int k = 0; k < 3; ++k) c.eps_bar[k] = eb[k];
+  c.phase = PH_M_RES;
+  c.flags = FL_FIRST_OF_STEP;
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+void spff_default_config(spff_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->nx = c->ny = 64;
+  c->at = SPFF_AT1;
+  c->split = SPFF_SPLIT_SPECTRAL;
+  c->irreversibility = SPFF_IRR_CRACK_SET;
+  c->precision = SPFF_FP32;
+  c->nu = 0.2;
+  c->ell = 2.0;
+  c->gc = 1.0;
+  c->crack_set_threshold = 0.9;
+  c->k_res = 0.0;
+  c->eta_over_dt = 0.0;
+  c->tol_mech = 1e-6;
+  c->tol_abs_mech = 0.0;
+  c->tol_pf = 1e-6;
+  c->tol_abs_pf = 0.0;
+  c->tol_am = -1.0;
+  c->max_cg = 20000;
+  c->max_newton = 50;
+  c->max_bccg = 20000;
+  c->max_am = 1000;
+  c->ticks_per_sync = 1;
+  c->use_graph = 0;
+  c->floor_factor = 2.0;
+  c->stall_iters = 200;
+}
+
+spff_status spff_workspace_bytes(const spff_config* cfg, int32_t nbatch, size_t* bytes) {
+  spff_status st = check_config(cfg);
+  if (st != SPFF_OK) return st;
+  if (nbatch < 1) return fail(SPFF_E_INVALID, "nbatch must be >= 1");
+  if (!bytes) return fail(SPFF_E_INVALID, "bytes is NULL");
+  const size_t rsize = cfg->precision == SPFF_FP64 ? 8 : 4;
+  *bytes = layout(cfg, nbatch, rsize).total;
+  return SPFF_OK;
+}
+
+spff_status spff_create_batch(const spff_config* cfg, int32_t nbatch, const void* E_dev, const void* phi_init_dev,
+                              void* workspace, size_t workspace_bytes, void* stream, spff_problem** out) {
+  spff_status st = check_config(cfg);
+  if (st != SPFF_OK) return st;
+  if (!out) return fail(SPFF_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (nbatch < 1) return fail(SPFF_E_INVALID, "nbatch must be >= 1");
+  if (!E_dev) return fail(SPFF_E_INVALID, "E_dev is NULL");
+  if (!workspace) return fail(SPFF_E_INVALID, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return fail(SPFF_E_INVALID, "workspace must be 256-byte aligned");
+  const size_t rsize = cfg->precision == SPFF_FP64 ? 8 : 4;
+  std::vector<int> bsize;
+  for (int v = 1;; v *= 2) {
+    bsize.push_back(std::min(v, (int)nbatch));
+    if (v >= nbatch) break;
+  }
+  std::vector<LaunchGeom> geoms;
+  for (int v : bsize) {
+    LaunchGeom G = plan(cfg, v, 2 * rsize);
+    if (G.lds_row > LDS_MAX || G.lds_col > LDS_MAX) return fail(SPFF_E_INVALID, "grid too large for LDS tiles");
+    geoms.push_back(G);
+  }
+  if (cfg->nx / 2 > THREADS * MAXE || cfg->ny > THREADS * MAXE) return fail(SPFF_E_INVALID, "grid too large");
+  Layout L = layout(cfg, nbatch, rsize);
+  if (workspace_bytes < L.total)
+    return fail(SPFF_E_NOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, L.total);
+
+  spff_problem* p = new spff_problem();
+  p->cfg = *cfg;
+  p->S = nbatch;
+  p->rsize = rsize;
+  p->L = L;
+  p->ws = static_cast<unsigned char*>(workspace);
+  p->stream = static_cast<hipStream_t>(stream);
+  p->cap_stream = nullptr;
+  p->bucket_size = bsize;
+  p->geoms = geoms;
+  p->graphs.assign(bsize.size(), nullptr);
+  p->host_ctl = nullptr;
+  p->prm.assign(nbatch, make_param(cfg));
+  p->last_eps_bar.assign(3 * (size_t)nbatch, 0.0);
+  auto cleanup = [&](spff_status s) {
+    spff_destroy_problem(p);
+    return s;
+  };
+  if (hipHostMalloc(reinterpret_cast<void**>(&p->host_ctl), sizeof(SlotCtl) * nbatch, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&p->host_list), sizeof(int32_t) * nbatch, hipHostMallocDefault) !=
+          hipSuccess)
+    return cleanup(fail(SPFF_E_DEVICE, "pinned host allocation failed"));
+  for (int s = 0; s < nbatch; ++s) reset_ctl(p, s);
+  st = cfg->precision == SPFF_FP64 ? init_device<double>(p, E_dev, phi_init_dev)
+                                   : init_device<float>(p, E_dev, phi_init_dev);
+  if (st != SPFF_OK) return cleanup(st);
+  // control blocks: idle, or the zero-strain phase-field solve for phi_init
+  for (int s = 0; s < nbatch; ++s) {
+    reset_ctl(p, s);
+    if (phi_init_dev) {
+      p->host_ctl[s].phase = PH_PF_ASM;
+      p->host_ctl[s].flags = FL_INIT_SOLVE;
+    }
+  }
+  if (hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * nbatch, hipMemcpyHostToDevice, p->stream) !=
+      hipSuccess)
+    return cleanup(fail(SPFF_E_DEVICE, "control upload failed"));
+  if (phi_init_dev) {
+    st = run_until_idle(p);
+    if (st != SPFF_OK) return cleanup(st);
+  }
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return cleanup(fail(SPFF_E_DEVICE, "stream sync failed"));
+  *out = p;
+  return SPFF_OK;
+}
+
+spff_status spff_create_problem(const spff_config* cfg, const void* E_dev, const void* phi_init_dev,
+                                void* workspace, size_t workspace_bytes, void* stream, spff_problem** out) {
+  return spff_create_batch(cfg, 1, E_dev, phi_init_dev, workspace, workspace_bytes, stream, out);
+}
+
+spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps_bar, spff_step_stats* stats) {
+  if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
+  if (nsteps < 1) return fail(SPFF_E_INVALID, "nsteps must be >= 1");
+  if (!eps_bar) return fail(SPFF_E_INVALID, "eps_bar is NULL");
+  for (size_t i = 0; i < (size_t)3 * p->S * nsteps; ++i)
+    if (!std::isfinite(eps_bar[i])) return fail(SPFF_E_INVALID, "eps_bar must be finite");
+  const int S = p->S;
+  std::vector<int> next(S, 0);
+  std::vector<double> t0(S, 0.0);
+  const double tstart = now_ms();
+  for (int s = 0; s < S; ++s) {
+    start_step(p, s, eps_bar + 3 * (size_t)s * nsteps);
+    t0[s] = tstart;
+  }
+  HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * S, hipMemcpyHostToDevice, p->stream));
+  spff_status worst = SPFF_OK;
+  int remaining = S;
+  const size_t cbytes = sizeof(SlotCtl) * S;
+  while (remaining > 0) {
+    bool launched;
+    int k;
+    spff_status bst = launch_block(p, &launched, &k);
+    if (bst != SPFF_OK) return bst;
+    HIP_TRY(hipMemcpyAsync(p->host_ctl, p->d_ctl(), cbytes, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    collect_profile(p, k);
+    const double t = now_ms();
+    bool dirty = false;
+    for (int s = 0; s < S; ++s) {
+      if (next[s] >= nsteps || p->host_ctl[s].phase != PH_IDLE) continue;
+      const SlotCtl& c = p->host_ctl[s];
+      const spff_status ss = slot_status(c);
+      if (ss < 0 && (worst >= 0 || ss < worst)) worst = ss;
+      if (ss > 0 && worst == SPFF_OK) worst = ss;
+      if (stats) fill_stats(p, c, stats[(size_t)s * nsteps + next[s]], t - t0[s]);
+      for (int k = 0; k < 3; ++k) p->last_eps_bar[3 * s + k] = c.eps_bar[k];
+      ++next[s];
+      if (next[s] < nsteps && ss >= 0) {
+        start_step(p, s, eps_bar + 3 * ((size_t)s * nsteps + next[s]));
+        t0[s] = t;
+        dirty = true;
+      } else {
+        if (ss < 0) next[s] = nsteps;  // a failed problem stops its sequence
+        --remaining;
+      }
+    }
+    // the device is idle here (synchronised), so the whole mirror is current
+    if (dirty) HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, cbytes, hipMemcpyHostToDevice, p->stream));
+  }
+  if (worst < 0) g_last_error = "a problem of the batch failed (see per-problem status)";
+  return worst;
+}
+
+spff_status spff_load_step_batch(spff_problem* p, const double* eps_bar, spff_step_stats* stats) {
+  return spff_run_sequence(p, 1, eps_bar, stats);
+}
+
+spff_status spff_load_step(spff_problem* p, const double eps_bar[3], spff_step_stats* stats) {
+  if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
+  if (p->S != 1) return fail(SPFF_E_INVALID, "spff_load_step needs nbatch == 1; use spff_load_step_batch");
+  return spff_load_step_batch(p, eps_bar, stats);
+}
+
+spff_status spff_get_fields(spff_problem* p, int32_t index, uint32_t mask, void* const* dst) {
+  if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
+  if (index < -1 || index >= p->S) return fail(SPFF_E_INVALID, "index out of range");
+  if (mask & ~0x3Fu) return fail(SPFF_E_INVALID, "unknown field bits");
+  if (mask && !dst) return fail(SPFF_E_INVALID, "dst is NULL");
+  const size_t n = p->n(), rb = p->rsize * n;
+  const int s0 = index < 0 ? 0 : index, s1 = index < 0 ? p->S : index + 1;
+  int k = 0;
+  void* out[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int b = 0; b < 6; ++b)
+    if (mask & (1u << b)) {
+      if (!dst[k]) return fail(SPFF_E_INVALID, "dst[%d] is NULL", k);
+      out[b] = dst[k++];
+    }
+  const size_t planes[6] = {1, 1, 3, 3, 1, 3};
+  for (int s = s0; s < s1; ++s) {
+    const int j = s - s0;
+    unsigned char* b = p->slot(s);
+    auto at = [&](int f) { return static_cast<unsigned char*>(out[f]) + (size_t)j * planes[f] * rb; };
+    if (out[0]) HIP_TRY(hipMemcpyAsync(at(0), b + p->L.phi, rb, hipMemcpyDeviceToDevice, p->stream));
+    if (out[1]) HIP_TRY(hipMemcpyAsync(at(1), b + p->L.phi_ref, rb, hipMemcpyDeviceToDevice, p->stream));
+    if (out[5]) HIP_TRY(hipMemcpyAsync(at(5), b + p->L.eps, 3 * rb, hipMemcpyDeviceToDevice, p->stream));
+    if (out[2] || out[3] || out[4]) {
+      hipError_t e;
+      if (p->cfg.precision == SPFF_FP64)
+        e = launch_fields<double>(reinterpret_cast<const SlotPtr<double>*>(p->d_ptr()), p->d_prm(), p->d_ctl(), s,
+                                  (int)n, reinterpret_cast<double*>(out[2] ? at(2) : nullptr),
+                                  reinterpret_cast<double*>(out[3] ? at(3) : nullptr),
+                                  reinterpret_cast<double*>(out[4] ? at(4) : nullptr), p->stream);
+      else
+        e = launch_fields<float>(reinterpret_cast<const SlotPtr<float>*>(p->d_ptr()), p->d_prm(), p->d_ctl(), s,
+                                 (int)n, reinterpret_cast<float*>(out[2] ? at(2) : nullptr),
+                                 reinterpret_cast<float*>(out[3] ? at(3) : nullptr),
+                                 reinterpret_cast<float*>(out[4] ? at(4) : nullptr), p->stream);
+      if (e != hipSuccess) return fail(SPFF_E_DEVICE, "field kernel failed: %s", hipGetErrorString(e));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return SPFF_OK;
+}
+
+size_t spff_state_bytes(const spff_problem* p) { return p ? (size_t)p->S * 5 * p->rsize * p->n() : 0; }
+
+spff_status spff_get_state(spff_problem* p, void* dst_dev, double* eps_bar_host) {
+  if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
+  if (!dst_dev) return fail(SPFF_E_INVALID, "dst is NULL");
+  const size_t rb = p->rsize * p->n();
+  for (int s = 0; s < p->S; ++s) {
+    unsigned char* d = static_cast<unsigned char*>(dst_dev) + (size_t)s * 5 * rb;
+    unsigned char* b = p->slot(s);
+    HIP_TRY(hipMemcpyAsync(d, b + p->L.eps, 3 * rb, hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(d + 3 * rb, b + p->L.phi, rb, hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(d + 4 * rb, b + p->L.phi_ref, rb, hipMemcpyDeviceToDevice, p->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (eps_bar_host) std::copy(p->last_eps_bar.begin(), p->last_eps_bar.end(), eps_bar_host);
+  return SPFF_OK;
+}
+
+spff_status spff_set_state(spff_problem* p, const void* src_dev, const double* eps_bar_host) {
+  if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
+  if (!src_dev) return fail(SPFF_E_INVALID, "src is NULL");
+  const size_t rb = p->rsize * p->n();
+  for (int s = 0; s < p->S; ++s) {
+    const unsigned char* d = static_cast<const unsigned char*>(src_dev) + (size_t)s * 5 * rb;
+    unsigned char* b = p->slot(s);
+    HIP_TRY(hipMemcpyAsync(b + p->L.eps, d, 3 * rb, hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(b + p->L.phi, d + 3 * rb, rb, hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(b + p->L.phi_ref, d + 4 * rb, rb, hipMemcpyDeviceToDevice, p->stream));
+  }
+  if (eps_bar_host) {
+    std::copy(eps_bar_host, eps_bar_host + 3 * p->S, p->last_eps_bar.begin());
+    for (int s = 0; s < p->S; ++s)
+      for (int k = 0; k < 3; ++k) p->host_ctl[s].eps_bar[k] = eps_bar_host[3 * s + k];
+    HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * p->S, hipMemcpyHostToDevice, p->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return SPFF_OK;
+}
+
+spff_status spff_apply_operator(spff_problem* p, int32_t op, const void* in_dev, void* out_dev) {
+  if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
+  if (op != SPFF_OP_PROJECT && op != SPFF_OP_NEG_LAPLACIAN) return fail(SPFF_E_INVALID, "unknown operator");
+  if (!in_dev || !out_dev) return fail(SPFF_E_INVALID, "in/out is NULL");
+  const int planes = op == SPFF_OP_PROJECT ? 3 : 1;
+  const size_t rb = p->rsize * p->n();
+  for (int s = 0; s < p->S; ++s) {
+    if (p->host_ctl[s].phase != PH_IDLE) return fail(SPFF_E_BUSY, "slot %d is not idle", s);
+    HIP_TRY(hipMemcpyAsync(p->slot(s) + p->L.theta, static_cast<const unsigned char*>(in_dev) + s * planes * rb,
+                           planes * rb, hipMemcpyDeviceToDevice, p->stream));
+  }
+  std::vector<SlotCtl> saved(p->host_ctl, p->host_ctl + p->S);
+  for (int s = 0; s < p->S; ++s) p->host_ctl[s].phase = op == SPFF_OP_PROJECT ? PH_X_PROJ : PH_X_LAP;
+  HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * p->S, hipMemcpyHostToDevice, p->stream));
+  std::vector<int32_t> all(p->S);
+  for (int s = 0; s < p->S; ++s) all[s] = s;
+  const int ball = (int)p->bucket_size.size() - 1;
+  spff_status lst = set_list(p, all, ball);
+  if (lst != SPFF_OK) return lst;
+  const bool prof = p->prof_on;
+  p->prof_on = false;
+  hipError_t e = enqueue_ticks(p, 1, p->stream, ball);
+  p->prof_on = prof;
+  if (e != hipSuccess) return fail(SPFF_E_DEVICE, "operator launch failed: %s", hipGetErrorString(e));
+  for (int s = 0; s < p->S; ++s)
+    HIP_TRY(hipMemcpyAsync(static_cast<unsigned char*>(out_dev) + s * planes * rb, p->slot(s) + p->L.rm,
+                           planes * rb, hipMemcpyDeviceToDevice, p->stream));
+  // the pinned mirror is the source of the pending upload above: wait before
+  // reusing it, then restore the control blocks (step statistics stay readable)
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  std::copy(saved.begin(), saved.end(), p->host_ctl);
+  HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * p->S, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return SPFF_OK;
+}
+
+spff_status spff_profile_enable(spff_problem* p, int32_t enable) {
+  if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const size_t need = 5 * (size_t)p->cfg.ticks_per_sync;
+  if (enable && p->events.size() < need) {
+    while (p->events.size() < need) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      p->events.push_back(e);
+    }
+  }
+  p->prof_on = enable != 0;
+  for (int j = 0; j < 4; ++j) {
+    p->kernel_ms[j] = 0.0;
+    p->launches[j] = 0;
+  }
+  p->prof_ticks = 0;
+  HIP_TRY(hipMemsetAsync(p->d_prof(), 0, sizeof(double) * 3 * p->S, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  // the byte counters are compiled into the captured blocks: recapture lazily
+  drop_graphs(p);
+  return SPFF_OK;
+}
+
+spff_status spff_profile_read(spff_problem* p, spff_profile* out) {
+  if (!p || !out) return fail(SPFF_E_INVALID, "NULL argument");
+  std::vector<double> b(3 * (size_t)p->S);
+  HIP_TRY(hipMemcpyAsync(b.data(), p->d_prof(), sizeof(double) * b.size(), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  std::memset(out, 0, sizeof(*out));
+  for (int s = 0; s < p->S; ++s)
+    for (int j = 0; j < 3; ++j) out->alg_bytes[j] += b[3 * s + j];
+  for (int j = 0; j < 4; ++j) {
+    out->kernel_ms[j] = p->kernel_ms[j];
+    out->launches[j] = p->launches[j];
+  }
+  out->ticks = p->prof_ticks;
+  return SPFF_OK;
+}
+
+spff_status spff_problem_info(const spff_problem* p, int32_t* nbatch, int32_t* nx, int32_t* ny,
+                              int32_t* precision) {
+  if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
+  if (nbatch) *nbatch = p->S;
+  if (nx) *nx = p->cfg.nx;
+  if (ny) *ny = p->cfg.ny;
+  if (precision) *precision = p->cfg.precision;
+  return SPFF_OK;
+}
+
+spff_status spff_destroy_problem(spff_problem* p) {
+  if (!p) return SPFF_OK;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  drop_graphs(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->host_ctl) (void)hipHostFree(p->host_ctl);
+  if (p->host_list) (void)hipHostFree(p->host_list);
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+  delete p;
+  return SPFF_OK;
+}
+
+const char* spff_last_error(void) { return g_last_error.c_str(); }
+
+const char* spff_version(void) { return "spff 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Engine structures shared by the device kernels and the host driver.
+//
+// Execution model.  A handle owns S "slots"; a slot holds one problem (its
+// resident state and its solver scratch).  Every slot runs its own state
+// machine for one load step of alternating minimisation (Algorithm 2):
+//
+//   M_RES   mechanics residual R = G[sigma(eps_bar + eps*)] (Newton start)
+//   M_CG    one CG iteration on G[C_m : theta] = -R (Sec. 3.1.1)
+//   PF_ASM  phase-field assembly (d, b) and BCCG initial residual
+//   PF_PQ   BCCG step length: p update, p.Jp via Parseval (Alg. 1)
+//   PF_R    BCCG update phi <- clip(phi + alpha p), new residual (Alg. 1)
+//   AM_CHK  ||phi_n+1 - phi_n||_1 (Sec. 3.2.1)
+//   STATS   energies, mean stress, phi statistics
+//
+// The host advances all slots together in "ticks": one tick launches the
+// row-forward, column and row-inverse FFT kernels (each does the part of the
+// current phase that belongs to it, or nothing) and the controller kernel,
+// which reduces the partial sums of the tick in a fixed order, computes the
+// FP64 scalars (alpha, beta, norms) and moves the slot to its next phase.
+// Ticks contain no host round trip, so blocks of ticks can be replayed as a
+// captured HIP graph; the host polls phases between blocks.
+#pragma once
+#include <stdint.h>
+
+namespace spff {
+
+enum Phase : int32_t {
+  PH_IDLE = 0,
+  PH_M_RES = 1,
+  PH_M_CG = 2,
+  PH_PF_ASM = 3,
+  PH_PF_PQ = 4,
+  PH_PF_R = 5,
+  PH_AM_CHK = 6,
+  PH_STATS = 7,
+  PH_X_PROJ = 8,  // diagnostic: rm = G[theta] (3 planes)
+  PH_X_LAP = 9,   // diagnostic: rm[0] = -lap theta[0]
+};
+
+// ctl.flags bits
+enum : int32_t {
+  FL_FIRST_OF_STEP = 1,   // next M_RES copies phi -> phi_ref
+  FL_THETA_PENDING = 2,   // next M_RES applies eps* += theta
+  FL_CG_FIRST = 4,        // next M_CG is the first of a Newton step
+  FL_INIT_SOLVE = 8,      // phase-field solve at zero strain (phi_init)
+  FL_MECH_STARTED = 16,   // reference norm of the current mechanics solve set
+  FL_NOT_CONVERGED = 32,  // an iteration cap was hit during the step
+  FL_NONFINITE = 64,      // a reduction was NaN/Inf
+  FL_PF_FIRST = 128,      // next PF_PQ is the first BCCG iteration (beta = 0)
+  FL_STALLED = 256,       // BCCG residual stopped improving (stall guard)
+};
+
+// Per-slot physical and solver parameters (read-only during a step).
+struct SlotParam {
+  double lam_t, mu_t;      // Lame constants per unit E (plane strain)
+  double ell, gc;
+  double cwl;              // G_c / (c_w ell)
+  double kappa;            // 2 G_c ell / c_w   (coefficient of -lap in F_phi)
+  double wpp;              // w'' (0 for AT1, 2 for AT2)
+  double dw0;              // w'(0) (1 for AT1, 0 for AT2)
+  double eta_dt, k_res, threshold;
+  double tol_mech, tol_abs_mech, tol_pf, tol_abs_pf, tol_am;
+  // attainable-accuracy floor of a residual computed in the working
+  // precision: floor = floor_coef * (norm of the terms the residual is
+  // computed from); floor_coef = floor_factor * u * sqrt(log2(nx ny))
+  double floor_coef;
+  double lap_rms;          // mean |2 pi q|^2 over the grid's modes (2 pi^2 / 3)
+  int32_t at, split, irr, stall_iters;
+  int32_t max_cg, max_newton, max_bccg, max_am;
+};
+
+// Per-slot control block (written by the controller kernel; the host writes
+// it only while the slot is idle).
+struct SlotCtl {
+  int32_t phase, flags;
+  int32_t am, newton, cg, bccg;     // counters of the current load step
+  int32_t cg_newton, pf_it;         // CG iterations of the current Newton step, BCCG of the current solve
+  int32_t newton_solve, pad0;       // Newton steps of the current mechanics solve
+  int32_t ticks, status;
+  double eps_bar[3];
+  // mechanics
+  double mech_ref, mech_target, mech_res, rr, inner_tol, alpha_m, beta_m;
+  // phase field
+  double pf_ref, pf_target, pf_res, rr_pf, alpha_pf, beta_pf, pq, rp;
+  double pf_bnorm, pf_best, mech_floor, pf_floor;
+  int32_t pf_best_it, pad1;
+  // alternating minimisation
+  double dphi;
+  // statistics of the finished step
+  double F_e, F_f, sbar[3], phi_sum, phi_max, crack_px;
+};
+
+// Per-slot device pointers (resident state + scratch).  Scratch planes are
+// shared between the mechanics and phase-field phases, which never overlap:
+//   theta[0..2] (mech update)      | d, b, phi_am   (phase field)
+//   rm[0..2]    (mech residual)    | r_pf = rm[0]
+//   pm[0..2]    (mech direction)   | p_pf = pm[0], mask = bytes of pm[1]
+template <typename real>
+struct SlotPtr {
+  const real* E;
+  real* phi;
+  real* phi_ref;
+  real* eps;     // eps* planes xx, yy, xy  ([3][n])
+  real* theta;   // [3][n]
+  real* rm;      // [3][n]
+  real* pm;      // [3][n]
+  void* spec;    // complex [3][nx/2][ny]  (half spectrum, transposed)
+};
+
+// Number of FP64 partials per work-group written by each kernel.
+constexpr int NP_ROW = 8;
+constexpr int NP_COL = 2;
+constexpr int NP_INV = 4;
+
+}  // namespace spff

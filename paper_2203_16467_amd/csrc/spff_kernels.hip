@@ -1,0 +1,1015 @@
+// Solver kernels for gfx950.  One tick = k_rowfwd -> k_col -> k_rowinv ->
+// k_ctrl over all slots of a handle; every kernel looks up the phase of its
+// slot and does that phase's share of the work (or returns).
+//
+// Data layout (per slot, real = float or double):
+//   real planes [ny][nx]; tensors as 3 planes (xx, yy, xy)
+//   spectrum: complex [C][nx/2][ny] -- the half spectrum of each plane,
+//             stored transposed (one contiguous run of ny per kx) so the
+//             column kernel reads and writes whole columns; kx = 0 holds
+//             X[0] + i X[nx/2] (both columns of a real row transform are
+//             real-valued per row, so they share one complex column).
+//
+// Row kernels: a work-group owns R consecutive rows of one slot and all C
+// components; a column kernel work-group owns W consecutive kx columns.
+#include <hip/hip_runtime.h>
+
+#include "spff_device.hpp"
+#include "spff_engine.hpp"
+#include "spff_launch.hpp"
+
+namespace spff {
+
+constexpr int THREADS = 256;
+constexpr int MAXE = 8;   // FFT elements per thread per chunk: M <= 2048
+constexpr int PAD = 1;    // complex padding per LDS row (bank spread)
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+__device__ __forceinline__ int phase_comps_row(int phase) {
+  switch (phase) {
+    case PH_M_RES:
+    case PH_M_CG:
+    case PH_X_PROJ:
+      return 3;
+    case PH_PF_ASM:
+    case PH_PF_PQ:
+    case PH_PF_R:
+    case PH_STATS:
+    case PH_X_LAP:
+      return 1;
+    default:
+      return 0;
+  }
+}
+
+template <typename real>
+struct V2 {
+  real a, b;
+};
+
+template <typename real>
+__device__ __forceinline__ V2<real> ld2(const real* p) {
+  using C = cplx<real>;
+  const C v = *reinterpret_cast<const C*>(p);
+  return {v.x, v.y};
+}
+template <typename real>
+__device__ __forceinline__ void st2(real* p, real a, real b) {
+  using C = cplx<real>;
+  *reinterpret_cast<C*>(p) = mk<C>(a, b);
+}
+
+template <typename real>
+__device__ __forceinline__ real lower_bound(real pref, const SlotParam& P) {
+  if (P.irr == 1) return pref;
+  return pref >= real(P.threshold) ? pref : real(0);
+}
+
+// ===========================================================================
+// Row-forward kernel: prologue (per phase) -> R2C row FFTs -> transposed
+// store of the half spectra; FP64 partial sums per work-group.
+// ===========================================================================
+template <typename real>
+__global__ __launch_bounds__(THREADS) void k_rowfwd(const int* __restrict__ list,
+                                                    const SlotPtr<real>* __restrict__ ptrs,
+                                                    const SlotParam* __restrict__ prms,
+                                                    const SlotCtl* __restrict__ ctls,
+                                                    const cplx<real>* __restrict__ twx, double* __restrict__ part,
+                                                    int nx, int ny, int R, int ngr) {
+  using C = cplx<real>;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[(THREADS / 64) * NP_ROW];
+  const int s = list[blockIdx.y], g = blockIdx.x;
+  if (s < 0) return;
+  const SlotCtl& ctl = ctls[s];
+  const int phase = ctl.phase;
+  const int ncomp = phase_comps_row(phase);
+  if (phase != PH_AM_CHK && ncomp == 0) return;
+  const SlotParam& P = prms[s];
+  const SlotPtr<real> F = ptrs[s];
+  const int flags = ctl.flags;
+  const int M = nx >> 1, stride = M + PAD;
+  const int y0 = g * R;
+  const int n = nx * ny;
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  double acc[NP_ROW];
+#pragma unroll
+  for (int i = 0; i < NP_ROW; ++i) acc[i] = 0.0;
+  if (phase == PH_STATS) acc[3] = -1.0e300;
+
+  const real lt = real(P.lam_t), mt = real(P.mu_t), kres = real(P.k_res);
+  const real eb0 = real(ctl.eps_bar[0]), eb1 = real(ctl.eps_bar[1]), eb2 = real(ctl.eps_bar[2]);
+  const int split = P.split;
+
+  for (int idx = threadIdx.x; idx < R * M; idx += blockDim.x) {
+    const int r = idx / M, h = idx - r * M;
+    const int o = (y0 + r) * nx + 2 * h;
+    const int li = r * stride + h;  // LDS index of component 0
+    real val[3][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) val[0][q] = val[1][q] = val[2][q] = real(0);
+
+    switch (phase) {
+      case PH_M_RES: {
+        const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
+        if (flags & FL_FIRST_OF_STEP) st2(F.phi_ref + o, ph.a, ph.b);
+        V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
+        if (flags & FL_THETA_PENDING) {
+          const V2<real> tx = ld2(F.theta + o), ty = ld2(F.theta + n + o), txy = ld2(F.theta + 2 * n + o);
+          ex = {ex.a + tx.a, ex.b + tx.b};
+          ey = {ey.a + ty.a, ey.b + ty.b};
+          exy = {exy.a + txy.a, exy.b + txy.b};
+          st2(F.eps + o, ex.a, ex.b);
+          st2(F.eps + n + o, ey.a, ey.b);
+          st2(F.eps + 2 * n + o, exy.a, exy.b);
+        }
+        const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
+        const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const real lam = lt * Ev[q], mu = mt * Ev[q];
+          const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
+          const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
+          const Sym<real> sg = stress(e, lam, mu, hk, split);
+          const Sym<real> eh = {eb0, eb1, eb2};
+          const Sym<real> sh = stress(eh, lam, mu, hk, split);
+          acc[0] += double(ddot(sh, sh));
+          acc[1] += double(ddot(sg, sg));
+          val[0][q] = sg.xx;
+          val[1][q] = sg.yy;
+          val[2][q] = sg.xy;
+        }
+        break;
+      }
+      case PH_M_CG: {
+        const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
+        V2<real> px = ld2(F.rm + o), py = ld2(F.rm + n + o), pxy = ld2(F.rm + 2 * n + o);
+        if (!(flags & FL_CG_FIRST)) {
+          const real bt = real(ctl.beta_m);
+          const V2<real> qx = ld2(F.pm + o), qy = ld2(F.pm + n + o), qxy = ld2(F.pm + 2 * n + o);
+          px = {px.a + bt * qx.a, px.b + bt * qx.b};
+          py = {py.a + bt * qy.a, py.b + bt * qy.b};
+          pxy = {pxy.a + bt * qxy.a, pxy.b + bt * qxy.b};
+        }
+        st2(F.pm + o, px.a, px.b);
+        st2(F.pm + n + o, py.a, py.b);
+        st2(F.pm + 2 * n + o, pxy.a, pxy.b);
+        V2<real> ex = {0, 0}, ey = {0, 0}, exy = {0, 0};
+        if (split != 0) {
+          ex = ld2(F.eps + o);
+          ey = ld2(F.eps + n + o);
+          exy = ld2(F.eps + 2 * n + o);
+        }
+        const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
+        const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
+        const real pxv[2] = {px.a, px.b}, pyv[2] = {py.a, py.b}, psv[2] = {pxy.a, pxy.b};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const real lam = lt * Ev[q], mu = mt * Ev[q];
+          const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
+          const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
+          const Sym<real> p = {pxv[q], pyv[q], psv[q]};
+          const Sym<real> cp = tangent(e, p, lam, mu, hk, split);
+          acc[0] += double(ddot(p, cp));
+          val[0][q] = cp.xx;
+          val[1][q] = cp.yy;
+          val[2][q] = cp.xy;
+        }
+        break;
+      }
+      case PH_PF_ASM: {
+        const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o), pr = ld2(F.phi_ref + o);
+        const V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
+        const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b}, rv[2] = {pr.a, pr.b};
+        const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
+        real dv[2], bv[2], cv[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const real lam = lt * Ev[q], mu = mt * Ev[q];
+          const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
+          real pp, pm;
+          energies(e, lam, mu, split, &pp, &pm);
+          dv[q] = real(2) * pp + real(P.cwl * P.wpp + P.eta_dt);
+          bv[q] = real(2) * pp - real(P.cwl * P.dw0) + real(P.eta_dt) * rv[q];
+          const real lo = lower_bound(rv[q], P);
+          cv[q] = fmin(fmax(pv[q], lo), real(1));
+          acc[0] += double(bv[q]) * double(bv[q]);
+          val[0][q] = cv[q];
+        }
+        st2(F.theta + o, dv[0], dv[1]);
+        st2(F.theta + n + o, bv[0], bv[1]);
+        st2(F.theta + 2 * n + o, ph.a, ph.b);  // phi at the start of this PF solve
+        st2(F.phi + o, cv[0], cv[1]);
+        break;
+      }
+      case PH_PF_PQ: {
+        const V2<real> r = ld2(F.rm + o), d = ld2(F.theta + o);
+        V2<real> p;
+        if (flags & FL_PF_FIRST) {
+          p = {-r.a, -r.b};
+        } else {
+          const V2<real> po = ld2(F.pm + o);
+          const real bt = real(ctl.beta_pf);
+          p = {-r.a + bt * po.a, -r.b + bt * po.b};
+        }
+        const unsigned char* mask = reinterpret_cast<const unsigned char*>(F.pm + n);
+        if (mask[o]) p.a = real(0);
+        if (mask[o + 1]) p.b = real(0);
+        st2(F.pm + o, p.a, p.b);
+        acc[0] += double(d.a) * double(p.a) * double(p.a) + double(d.b) * double(p.b) * double(p.b);
+        acc[1] += double(r.a) * double(p.a) + double(r.b) * double(p.b);
+        val[0][0] = p.a;
+        val[0][1] = p.b;
+        break;
+      }
+      case PH_PF_R: {
+        const V2<real> ph = ld2(F.phi + o), p = ld2(F.pm + o), pr = ld2(F.phi_ref + o);
+        const real al = real(ctl.alpha_pf);
+        const real a0 = fmin(fmax(ph.a + al * p.a, lower_bound(pr.a, P)), real(1));
+        const real a1 = fmin(fmax(ph.b + al * p.b, lower_bound(pr.b, P)), real(1));
+        st2(F.phi + o, a0, a1);
+        val[0][0] = a0;
+        val[0][1] = a1;
+        break;
+      }
+      case PH_AM_CHK: {
+        const V2<real> ph = ld2(F.phi + o), pa = ld2(F.theta + 2 * n + o);
+        acc[0] += fabs(double(ph.a) - double(pa.a)) + fabs(double(ph.b) - double(pa.b));
+        break;
+      }
+      case PH_STATS: {
+        const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
+        const V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
+        const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
+        const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const real lam = lt * Ev[q], mu = mt * Ev[q];
+          const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
+          const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
+          real pp, pm;
+          energies(e, lam, mu, split, &pp, &pm);
+          const Sym<real> sg = stress(e, lam, mu, hk, split);
+          acc[0] += double(hk) * double(pp) + double(pm);
+          acc[1] += P.at == 1 ? double(pv[q]) : double(pv[q]) * double(pv[q]);
+          acc[2] += double(pv[q]);
+          acc[3] = fmax(acc[3], double(pv[q]));
+          acc[4] += pv[q] > real(0.9) ? 1.0 : 0.0;
+          acc[5] += double(sg.xx);
+          acc[6] += double(sg.yy);
+          acc[7] += double(sg.xy);
+          val[0][q] = pv[q];
+        }
+        break;
+      }
+      case PH_X_PROJ:
+      case PH_X_LAP: {
+        for (int c = 0; c < ncomp; ++c) {
+          const V2<real> t = ld2(F.theta + c * n + o);
+          val[c][0] = t.a;
+          val[c][1] = t.b;
+        }
+        break;
+      }
+      default:
+        break;
+    }
+    if (ncomp > 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (c < ncomp) buf[c * R * stride + li] = mk<C>(val[c][0], val[c][1]);
+    }
+  }
+  if (ncomp > 0) {
+    __syncthreads();
+    fft_lds<real, false, MAXE>(buf, M, ncomp * R, stride, twx, 2);
+    r2c_post<real>(buf, M, ncomp * R, stride, twx);
+    // transposed store: spec[c][kx][y0 + r]
+    C* spec = reinterpret_cast<C*>(F.spec);
+    const int tot = ncomp * M * R;
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+      const int r = idx % R;
+      const int rest = idx / R;
+      const int kx = rest % M, c = rest / M;
+      spec[(size_t)(c * M + kx) * ny + y0 + r] = buf[(c * R + r) * stride + kx];
+    }
+  }
+  block_reduce_store<NP_ROW>(acc, red, part + ((size_t)s * ngr + g) * NP_ROW, phase == PH_STATS ? 3 : -1);
+}
+
+// ===========================================================================
+// Column kernel: forward column FFTs -> per-mode operator -> inverse column
+// FFTs (or a Parseval reduction only).  Normalisation 1/(nx ny) is applied
+// with the operator.
+// ===========================================================================
+template <typename real>
+__device__ __forceinline__ void project3(real* a, real fx, real fy) {
+  // G^:A = A - (t.A.t) t(x)t, t = (-fy, fx)/|f|; G^ = 0 at f = 0.
+  const real n2 = fx * fx + fy * fy;
+  if (n2 == real(0)) {
+    a[0] = a[1] = a[2] = real(0);
+    return;
+  }
+  const real inv = real(1) / n2;
+  const real txx = fy * fy * inv, tyy = fx * fx * inv, txy = -fx * fy * inv;
+  const real sdot = txx * a[0] + tyy * a[1] + real(2) * txy * a[2];
+  a[0] -= sdot * txx;
+  a[1] -= sdot * tyy;
+  a[2] -= sdot * txy;
+}
+
+template <typename real>
+__global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                                 const SlotParam* __restrict__ prms,
+                                                 const SlotCtl* __restrict__ ctls,
+                                                 const cplx<real>* __restrict__ twy, double* __restrict__ part,
+                                                 int nx, int ny, int W, int ngc) {
+  using C = cplx<real>;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[(THREADS / 64) * NP_COL];
+  const int s = list[blockIdx.y], g = blockIdx.x;
+  if (s < 0) return;
+  const int phase = ctls[s].phase;
+  int ncomp, mode;  // mode 0: projection, 1: Laplacian, 2: Parseval reduction
+  switch (phase) {
+    case PH_M_RES:
+    case PH_M_CG:
+    case PH_X_PROJ:
+      ncomp = 3;
+      mode = 0;
+      break;
+    case PH_X_LAP:
+      ncomp = 1;
+      mode = 1;
+      break;
+    case PH_PF_ASM:
+    case PH_PF_R:
+      ncomp = 1;
+      mode = 1;
+      break;
+    case PH_PF_PQ:
+    case PH_STATS:
+      ncomp = 1;
+      mode = 2;
+      break;
+    default:
+      return;
+  }
+  const SlotParam& P = prms[s];
+  const SlotPtr<real> F = ptrs[s];
+  const int M = nx >> 1, stride = ny + PAD;
+  const int kx0 = g * W;
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  C* spec = reinterpret_cast<C*>(F.spec);
+  const real inv_n = real(1.0 / (double(nx) * double(ny)));
+  const real two_pi = real(TWO_PI);
+
+  // load W columns of each component
+  const int tot = ncomp * W * ny;
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int y = idx % ny, rest = idx / ny;
+    const int w = rest % W, c = rest / W;
+    buf[(c * W + w) * stride + y] = spec[(size_t)(c * M + kx0 + w) * ny + y];
+  }
+  __syncthreads();
+  fft_lds<real, false, MAXE>(buf, ny, ncomp * W, stride, twy, 1);
+
+  double acc[NP_COL] = {0.0, 0.0};
+  const real lap_scale = (phase == PH_X_LAP ? real(1) : real(P.kappa)) * inv_n;
+  // per-mode operator; thread owns mode (w, ky); for the packed column kx = 0
+  // threads with ky <= ny/2 own the pair (ky, ny - ky)
+  for (int idx = threadIdx.x; idx < W * ny; idx += blockDim.x) {
+    const int w = idx / ny, ky = idx - w * ny;
+    const int kx = kx0 + w;
+    const int kys = ky < ny / 2 ? ky : ky - ny;
+    const real fy_true = real(kys) / real(ny);
+    const real fy_grad = (2 * ky == ny) ? real(0) : fy_true;
+    if (kx > 0) {
+      const real fx = real(kx) / real(nx);
+      if (mode == 0) {
+        C* a0 = buf + (0 * W + w) * stride + ky;
+        C* a1 = buf + (1 * W + w) * stride + ky;
+        C* a2 = buf + (2 * W + w) * stride + ky;
+        real re[3] = {a0->x, a1->x, a2->x}, im[3] = {a0->y, a1->y, a2->y};
+        project3(re, fx, fy_grad);
+        project3(im, fx, fy_grad);
+        *a0 = mk<C>(re[0] * inv_n, im[0] * inv_n);
+        *a1 = mk<C>(re[1] * inv_n, im[1] * inv_n);
+        *a2 = mk<C>(re[2] * inv_n, im[2] * inv_n);
+      } else {
+        const real L = two_pi * two_pi * (fx * fx + fy_true * fy_true);
+        C* a = buf + w * stride + ky;
+        if (mode == 1) {
+          *a = cscale(*a, L * lap_scale);
+        } else {
+          const C v = *a;
+          acc[0] += 2.0 * double(L) * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
+        }
+      }
+    } else {
+      if (2 * ky > ny) continue;  // partner handled by ky' = ny - ky
+      const int km = (ny - ky) & (ny - 1);
+      const bool self = (km == ky);
+      // split packed column into A (kx = 0 column) and B (kx = nx/2 column)
+      const real fxN_true = real(0.5);
+      if (mode == 0) {
+        C Aa[3], Bb[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C cp = buf[(c * W + w) * stride + ky];
+          const C cm = cconj(buf[(c * W + w) * stride + km]);
+          Aa[c] = cscale(cadd(cp, cm), real(0.5));
+          Bb[c] = cscale(cmulni(csub(cp, cm)), real(0.5));
+        }
+        real ar[3] = {Aa[0].x, Aa[1].x, Aa[2].x}, ai[3] = {Aa[0].y, Aa[1].y, Aa[2].y};
+        real br[3] = {Bb[0].x, Bb[1].x, Bb[2].x}, bi[3] = {Bb[0].y, Bb[1].y, Bb[2].y};
+        project3(ar, real(0), fy_grad);
+        project3(ai, real(0), fy_grad);
+        // kx = nx/2: gradient wavevector x-component is zero (Nyquist)
+        project3(br, real(0), fy_grad);
+        project3(bi, real(0), fy_grad);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C A = mk<C>(ar[c] * inv_n, ai[c] * inv_n), B = mk<C>(br[c] * inv_n, bi[c] * inv_n);
+          buf[(c * W + w) * stride + ky] = cadd(A, cmuli(B));
+          if (!self) buf[(c * W + w) * stride + km] = cadd(cconj(A), cmuli(cconj(B)));
+        }
+      } else {
+        const C cp = buf[w * stride + ky];
+        const C cm = cconj(buf[w * stride + km]);
+        const C A = cscale(cadd(cp, cm), real(0.5));
+        const C B = cscale(cmulni(csub(cp, cm)), real(0.5));
+        const real L0 = two_pi * two_pi * (fy_true * fy_true);
+        const real LN = two_pi * two_pi * (fxN_true * fxN_true + fy_true * fy_true);
+        if (mode == 1) {
+          const C A2 = cscale(A, L0 * lap_scale), B2 = cscale(B, LN * lap_scale);
+          buf[w * stride + ky] = cadd(A2, cmuli(B2));
+          if (!self) buf[w * stride + km] = cadd(cconj(A2), cmuli(cconj(B2)));
+        } else {
+          const double wgt = self ? 1.0 : 2.0;
+          acc[0] += wgt * (double(L0) * (double(A.x) * double(A.x) + double(A.y) * double(A.y)) +
+                           double(LN) * (double(B.x) * double(B.x) + double(B.y) * double(B.y)));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (mode != 2) {
+    fft_lds<real, true, MAXE>(buf, ny, ncomp * W, stride, twy, 1);
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+      const int y = idx % ny, rest = idx / ny;
+      const int w = rest % W, c = rest / W;
+      spec[(size_t)(c * M + kx0 + w) * ny + y] = buf[(c * W + w) * stride + y];
+    }
+  }
+  block_reduce_store<NP_COL>(acc, red, part + ((size_t)s * ngc + g) * NP_COL);
+}
+
+// ===========================================================================
+// Row-inverse kernel: transposed load -> C2R row FFTs -> epilogue (per
+// phase); FP64 partial sums per work-group.
+// ===========================================================================
+template <typename real>
+__global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list,
+                                                    const SlotPtr<real>* __restrict__ ptrs,
+                                                    const SlotParam* __restrict__ prms,
+                                                    const SlotCtl* __restrict__ ctls,
+                                                    const cplx<real>* __restrict__ twx,
+                                                    const double* __restrict__ part_row,
+                                                    double* __restrict__ part, int nx, int ny, int R, int ngr) {
+  using C = cplx<real>;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[(THREADS / 64) * NP_INV];
+  __shared__ double scal[1];
+  const int s = list[blockIdx.y], g = blockIdx.x;
+  if (s < 0) return;
+  const SlotCtl& ctl = ctls[s];
+  const int phase = ctl.phase;
+  int ncomp;
+  switch (phase) {
+    case PH_M_RES:
+    case PH_M_CG:
+    case PH_X_PROJ:
+      ncomp = 3;
+      break;
+    case PH_PF_ASM:
+    case PH_PF_R:
+    case PH_X_LAP:
+      ncomp = 1;
+      break;
+    default:
+      return;
+  }
+  const SlotParam& P = prms[s];
+  const SlotPtr<real> F = ptrs[s];
+  const int flags = ctl.flags;
+  const int M = nx >> 1, stride = M + PAD;
+  const int y0 = g * R;
+  const int n = nx * ny;
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const C* spec = reinterpret_cast<const C*>(F.spec);
+
+  // CG step length from this tick's row-forward partials (same fixed-order
+  // reduction as the controller).
+  real alpha = 0;
+  if (phase == PH_M_CG) {
+    if (threadIdx.x < 64) {
+      const double pcp = wave_reduce_partials(part_row + (size_t)s * ngr * NP_ROW, ngr, NP_ROW);
+      if (threadIdx.x == 0) scal[0] = (pcp > 0.0 && isfinite(pcp)) ? ctl.rr / pcp : 0.0;
+    }
+    __syncthreads();
+    alpha = real(scal[0]);
+  }
+
+  const int tot = ncomp * M * R;
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int r = idx % R;
+    const int rest = idx / R;
+    const int kx = rest % M, c = rest / M;
+    buf[(c * R + r) * stride + kx] = spec[(size_t)(c * M + kx) * ny + y0 + r];
+  }
+  __syncthreads();
+  c2r_pre<real>(buf, M, ncomp * R, stride, twx);
+  fft_lds<real, true, MAXE>(buf, M, ncomp * R, stride, twx, 2);
+
+  double acc[NP_INV] = {0.0, 0.0, 0.0, 0.0};
+  for (int idx = threadIdx.x; idx < R * M; idx += blockDim.x) {
+    const int r = idx / M, h = idx - r * M;
+    const int o = (y0 + r) * nx + 2 * h;
+    const int li = r * stride + h;
+    switch (phase) {
+      case PH_M_RES: {
+        const C q0 = buf[li], q1 = buf[R * stride + li], q2 = buf[2 * R * stride + li];
+        st2(F.rm + o, -q0.x, -q0.y);
+        st2(F.rm + n + o, -q1.x, -q1.y);
+        st2(F.rm + 2 * n + o, -q2.x, -q2.y);
+        acc[0] += double(q0.x) * q0.x + double(q0.y) * q0.y + double(q1.x) * q1.x + double(q1.y) * q1.y +
+                  2.0 * (double(q2.x) * q2.x + double(q2.y) * q2.y);
+        break;
+      }
+      case PH_M_CG: {
+        const C q[3] = {buf[li], buf[R * stride + li], buf[2 * R * stride + li]};
+        const bool first = flags & FL_CG_FIRST;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const V2<real> p = ld2(F.pm + c * n + o);
+          V2<real> r2 = ld2(F.rm + c * n + o);
+          V2<real> th = first ? V2<real>{0, 0} : ld2(F.theta + c * n + o);
+          th = {th.a + alpha * p.a, th.b + alpha * p.b};
+          r2 = {r2.a - alpha * q[c].x, r2.b - alpha * q[c].y};
+          st2(F.theta + c * n + o, th.a, th.b);
+          st2(F.rm + c * n + o, r2.a, r2.b);
+          const double wc = c == 2 ? 2.0 : 1.0;
+          acc[0] += wc * (double(r2.a) * r2.a + double(r2.b) * r2.b);
+        }
+        break;
+      }
+      case PH_PF_ASM:
+      case PH_PF_R: {
+        const C lap = buf[li];
+        const V2<real> ph = ld2(F.phi + o), d = ld2(F.theta + o), b = ld2(F.theta + n + o);
+        const V2<real> pr = ld2(F.phi_ref + o);
+        const real rr0 = d.a * ph.a + lap.x - b.a;
+        const real rr1 = d.b * ph.b + lap.y - b.b;
+        const real lo0 = lower_bound(pr.a, P), lo1 = lower_bound(pr.b, P);
+        const bool a0 = (ph.a <= lo0 && rr0 > real(0)) || (ph.a >= real(1) && rr0 < real(0));
+        const bool a1 = (ph.b <= lo1 && rr1 > real(0)) || (ph.b >= real(1) && rr1 < real(0));
+        const real r0 = a0 ? real(0) : rr0, r1 = a1 ? real(0) : rr1;
+        if (phase == PH_PF_R) {
+          const V2<real> ro = ld2(F.rm + o);
+          acc[1] += double(r0) * ro.a + double(r1) * ro.b;
+        }
+        st2(F.rm + o, r0, r1);
+        unsigned char* mask = reinterpret_cast<unsigned char*>(F.pm + n);
+        mask[o] = a0 ? 1 : 0;
+        mask[o + 1] = a1 ? 1 : 0;
+        acc[0] += double(r0) * r0 + double(r1) * r1;
+        acc[2] += double(ph.a) * ph.a + double(ph.b) * ph.b;
+        acc[3] += double(d.a * ph.a) * double(d.a * ph.a) + double(d.b * ph.b) * double(d.b * ph.b);
+        break;
+      }
+      case PH_X_PROJ:
+      case PH_X_LAP: {
+        for (int c = 0; c < ncomp; ++c) {
+          const C q = buf[c * R * stride + li];
+          st2(F.rm + c * n + o, q.x, q.y);
+        }
+        break;
+      }
+      default:
+        break;
+    }
+  }
+  block_reduce_store<NP_INV>(acc, red, part + ((size_t)s * ngr + g) * NP_INV);
+}
+
+// Algorithmic HBM bytes per pixel moved by the row-forward, column and
+// row-inverse kernels for the phase a slot executed (r = sizeof(real)):
+// every input plane read once, every output plane written once, half spectra
+// (2r bytes per pixel per component) written by the row-forward kernel, read
+// and written by the column kernel, read by the row-inverse kernel.
+__device__ inline void phase_bytes(int phase, int flags, int split, double r, double* b) {
+  const double sp = 2.0 * r;  // half spectrum, per pixel per component
+  b[0] = b[1] = b[2] = 0.0;
+  switch (phase) {
+    case PH_M_RES:
+      b[0] = r * 5 + 3 * sp + ((flags & FL_THETA_PENDING) ? 6 * r : 0) + ((flags & FL_FIRST_OF_STEP) ? r : 0);
+      b[1] = 6 * sp;
+      b[2] = 3 * sp + 3 * r;
+      break;
+    case PH_M_CG:
+      b[0] = r * (2 + 3 + ((flags & FL_CG_FIRST) ? 0 : 3) + (split ? 3 : 0) + 3) + 3 * sp;
+      b[1] = 6 * sp;
+      b[2] = 3 * sp + r * (3 + 3 + ((flags & FL_CG_FIRST) ? 0 : 3) + 6);
+      break;
+    case PH_PF_ASM:
+      b[0] = r * (6 + 4) + sp;
+      b[1] = 2 * sp;
+      b[2] = sp + r * (4 + 1) + 1;
+      break;
+    case PH_PF_PQ:
+      b[0] = r * (2 + ((flags & FL_PF_FIRST) ? 0 : 1) + 1) + 1 + sp;
+      b[1] = sp;
+      break;
+    case PH_PF_R:
+      b[0] = r * (3 + 1) + sp;
+      b[1] = 2 * sp;
+      b[2] = sp + r * (5 + 1) + 1;
+      break;
+    case PH_AM_CHK:
+      b[0] = 2 * r;
+      break;
+    case PH_STATS:
+      b[0] = r * 5 + sp;
+      b[1] = sp;
+      break;
+    default:
+      break;
+  }
+}
+
+// ===========================================================================
+// Controller: one wavefront per slot.  Reduces the tick's partials in a fixed
+// order, updates FP64 scalars and moves the slot's state machine.
+// ===========================================================================
+template <typename real>
+__global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const SlotParam* __restrict__ prms,
+                                             SlotCtl* __restrict__ ctls,
+                                             const double* __restrict__ prow, const double* __restrict__ pcol,
+                                             const double* __restrict__ pinv, double* __restrict__ prof,
+                                             int nx, int ny, int ngr, int ngc) {
+  const int s = list[blockIdx.x];
+  if (s < 0) return;
+  SlotCtl& C = ctls[s];
+  const int phase = C.phase;
+  if (phase == PH_IDLE) return;
+  const SlotParam& P = prms[s];
+  if (prof && threadIdx.x == 0) {
+    double b[3];
+    phase_bytes(phase, C.flags, P.split, double(sizeof(real)), b);
+    const double npx = double(nx) * double(ny);
+    prof[3 * s + 0] += b[0] * npx;
+    prof[3 * s + 1] += b[1] * npx;
+    prof[3 * s + 2] += b[2] * npx;
+  }
+  const double* pr = prow + (size_t)s * ngr * NP_ROW;
+  const double* pc = pcol + (size_t)s * ngc * NP_COL;
+  const double* pi = pinv + (size_t)s * ngr * NP_INV;
+  const double inv_n = 1.0 / (double(nx) * double(ny));
+  // all lanes compute the same values; lane 0 writes
+  double v[8];
+  int nphase = phase;
+  int flags = C.flags;
+  int cg = C.cg, cg_newton = C.cg_newton, newton = C.newton, bccg = C.bccg, pf_it = C.pf_it, am = C.am;
+  int newton_solve = C.newton_solve;
+  int status = C.status;
+  double mech_ref = C.mech_ref, mech_target = C.mech_target, mech_res = C.mech_res, rr = C.rr;
+  double inner_tol = C.inner_tol, alpha_m = C.alpha_m, beta_m = C.beta_m;
+  double pf_ref = C.pf_ref, pf_target = C.pf_target, pf_res = C.pf_res, rr_pf = C.rr_pf;
+  double alpha_pf = C.alpha_pf, beta_pf = C.beta_pf, pq = C.pq, rp = C.rp, dphi = C.dphi;
+  double pf_bnorm = C.pf_bnorm, pf_best = C.pf_best, mech_floor = C.mech_floor, pf_floor = C.pf_floor;
+  int pf_best_it = C.pf_best_it;
+  bool bad = false;
+  auto pf_done = [&]() {
+    if (flags & FL_INIT_SOLVE) {
+      flags &= ~FL_INIT_SOLVE;
+      nphase = PH_IDLE;
+    } else {
+      nphase = PH_AM_CHK;
+    }
+  };
+  switch (phase) {
+    case PH_M_RES: {
+      const double sh2 = wave_reduce_partials(pr, ngr, NP_ROW);
+      const double sg2 = wave_reduce_partials(pr + 1, ngr, NP_ROW);
+      const double r2 = wave_reduce_partials(pi, ngr, NP_INV);
+      bad = !isfinite(sh2) || !isfinite(r2) || !isfinite(sg2);
+      mech_res = sqrt(r2);
+      // G[sigma] cannot be evaluated more accurately than the rounding of
+      // sigma and of the transforms: below that floor the solve is done
+      mech_floor = P.floor_coef * sqrt(sg2);
+      if (!(flags & FL_MECH_STARTED)) {
+        // first residual of this mechanics solve fixes the reference norm
+        mech_ref = fmax(sqrt(sh2), mech_res);
+        mech_target = P.tol_mech * mech_ref + P.tol_abs_mech;
+        flags |= FL_MECH_STARTED;
+        newton_solve = 0;
+      }
+      flags &= ~(FL_FIRST_OF_STEP | FL_THETA_PENDING);
+      if (mech_res <= fmax(mech_target, mech_floor)) {
+        nphase = PH_PF_ASM;
+      } else if (newton_solve >= P.max_newton) {
+        flags |= FL_NOT_CONVERGED;
+        nphase = PH_PF_ASM;
+      } else {
+        rr = r2;
+        inner_tol = (P.split == 0) ? fmax(mech_target, mech_floor)
+                                   : fmax(0.1 * mech_res, fmax(mech_target, mech_floor));
+        cg_newton = 0;
+        flags |= FL_CG_FIRST;
+        nphase = PH_M_CG;
+      }
+      if (nphase == PH_PF_ASM) flags &= ~FL_MECH_STARTED;
+      break;
+    }
+    case PH_M_CG: {
+      const double pcp = wave_reduce_partials(pr, ngr, NP_ROW);
+      const double r2 = wave_reduce_partials(pi, ngr, NP_INV);
+      bad = !isfinite(pcp) || !isfinite(r2);
+      alpha_m = (pcp > 0.0) ? rr / pcp : 0.0;
+      ++cg;
+      ++cg_newton;
+      flags &= ~FL_CG_FIRST;
+      beta_m = (rr > 0.0) ? r2 / rr : 0.0;
+      rr = r2;
+      if (sqrt(r2) <= inner_tol || cg_newton >= P.max_cg || pcp <= 0.0) {
+        if (sqrt(r2) > inner_tol) flags |= FL_NOT_CONVERGED;
+        ++newton;
+        ++newton_solve;
+        flags |= FL_THETA_PENDING;
+        nphase = PH_M_RES;
+      }
+      break;
+    }
+    case PH_PF_ASM: {
+      const double b2 = wave_reduce_partials(pr, ngr, NP_ROW);
+      const double r2 = wave_reduce_partials(pi, ngr, NP_INV);
+      const double x2 = wave_reduce_partials(pi + 2, ngr, NP_INV);
+      const double dx2 = wave_reduce_partials(pi + 3, ngr, NP_INV);
+      bad = !isfinite(b2) || !isfinite(r2);
+      pf_res = sqrt(r2);
+      pf_bnorm = sqrt(b2);
+      pf_ref = fmax(pf_bnorm, pf_res);
+      pf_target = P.tol_pf * pf_ref + P.tol_abs_pf;
+      // attainable accuracy of r = J phi - b in the working precision
+      pf_floor = P.floor_coef * (sqrt(dx2) + P.kappa * P.lap_rms * sqrt(x2) + pf_bnorm);
+      rr_pf = r2;
+      pf_it = 0;
+      pf_best = pf_res;
+      pf_best_it = 0;
+      if (pf_res <= fmax(pf_target, pf_floor)) {
+        pf_done();
+      } else {
+        flags |= FL_PF_FIRST;
+        nphase = PH_PF_PQ;
+      }
+      break;
+    }
+    case PH_PF_PQ: {
+      v[0] = wave_reduce_partials(pr, ngr, NP_ROW);      // sum d p^2
+      v[1] = wave_reduce_partials(pr + 1, ngr, NP_ROW);  // sum r p
+      v[2] = wave_reduce_partials(pc, ngc, NP_COL);      // sum L |p^|^2
+      bad = !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
+      pq = v[0] + P.kappa * inv_n * v[2];
+      rp = v[1];
+      flags &= ~FL_PF_FIRST;
+      if (!(pq > 0.0)) {
+        flags |= FL_NOT_CONVERGED;
+        pf_done();
+      } else {
+        alpha_pf = -rp / pq;
+        nphase = PH_PF_R;
+      }
+      break;
+    }
+    case PH_PF_R: {
+      const double r2 = wave_reduce_partials(pi, ngr, NP_INV);
+      const double rro = wave_reduce_partials(pi + 1, ngr, NP_INV);
+      const double x2 = wave_reduce_partials(pi + 2, ngr, NP_INV);
+      const double dx2 = wave_reduce_partials(pi + 3, ngr, NP_INV);
+      bad = !isfinite(r2) || !isfinite(rro);
+      beta_pf = (r2 - rro) / (alpha_pf * pq);
+      rr_pf = r2;
+      pf_res = sqrt(r2);
+      pf_floor = P.floor_coef * (sqrt(dx2) + P.kappa * P.lap_rms * sqrt(x2) + pf_bnorm);
+      ++pf_it;
+      ++bccg;
+      if (pf_res < pf_best) {
+        pf_best = pf_res;
+        pf_best_it = pf_it;
+      }
+      if (pf_res <= fmax(pf_target, pf_floor)) {
+        pf_done();
+      } else if (P.stall_iters > 0 && pf_it - pf_best_it >= P.stall_iters) {
+        flags |= FL_STALLED;
+        pf_done();
+      } else if (pf_it >= P.max_bccg) {
+        flags |= FL_NOT_CONVERGED;
+        pf_done();
+      } else {
+        nphase = PH_PF_PQ;
+      }
+      break;
+    }
+    case PH_AM_CHK: {
+      dphi = wave_reduce_partials(pr, ngr, NP_ROW);
+      bad = !isfinite(dphi);
+      ++am;
+      if (dphi <= P.tol_am) {
+        nphase = PH_STATS;
+      } else if (am >= P.max_am) {
+        flags |= FL_NOT_CONVERGED;
+        nphase = PH_STATS;
+      } else {
+        nphase = PH_M_RES;
+      }
+      break;
+    }
+    case PH_X_PROJ:
+    case PH_X_LAP:
+      nphase = PH_IDLE;
+      break;
+    case PH_STATS: {
+      for (int i = 0; i < 8; ++i) v[i] = wave_reduce_partials(pr + i, ngr, NP_ROW, i == 3);
+      const double lg = wave_reduce_partials(pc, ngc, NP_COL);
+      bad = false;
+      for (int i = 0; i < 8; ++i) bad |= !isfinite(v[i]);
+      if (threadIdx.x == 0) {
+        C.F_e = v[0];
+        C.F_f = P.cwl * (v[1] + P.ell * P.ell * inv_n * lg);
+        C.phi_sum = v[2];
+        C.phi_max = v[3];
+        C.crack_px = v[4];
+        C.sbar[0] = v[5] * inv_n;
+        C.sbar[1] = v[6] * inv_n;
+        C.sbar[2] = v[7] * inv_n;
+      }
+      nphase = PH_IDLE;
+      break;
+    }
+    default:
+      break;
+  }
+  if (bad) {
+    flags |= FL_NONFINITE;
+    status = -4;
+    nphase = PH_IDLE;
+  }
+  if (threadIdx.x == 0) {
+    C.phase = nphase;
+    C.flags = flags;
+    C.cg = cg;
+    C.cg_newton = cg_newton;
+    C.newton = newton;
+    C.bccg = bccg;
+    C.pf_it = pf_it;
+    C.newton_solve = newton_solve;
+    C.am = am;
+    C.status = status;
+    C.mech_ref = mech_ref;
+    C.mech_target = mech_target;
+    C.mech_res = mech_res;
+    C.rr = rr;
+    C.inner_tol = inner_tol;
+    C.alpha_m = alpha_m;
+    C.beta_m = beta_m;
+    C.pf_ref = pf_ref;
+    C.pf_target = pf_target;
+    C.pf_res = pf_res;
+    C.rr_pf = rr_pf;
+    C.alpha_pf = alpha_pf;
+    C.beta_pf = beta_pf;
+    C.pq = pq;
+    C.rp = rp;
+    C.dphi = dphi;
+    C.pf_bnorm = pf_bnorm;
+    C.pf_best = pf_best;
+    C.pf_best_it = pf_best_it;
+    C.mech_floor = mech_floor;
+    C.pf_floor = pf_floor;
+    C.ticks = C.ticks + 1;
+  }
+}
+
+// ===========================================================================
+// Small utility kernels
+// ===========================================================================
+// Count non-finite or non-positive entries (E validation).
+template <typename real>
+__global__ void k_validate(const real* __restrict__ a, size_t n, real lo_excl, real lo_incl, real hi_incl,
+                           unsigned int* __restrict__ bad) {
+  unsigned int cnt = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const real v = a[i];
+    const bool ok = isfinite(v) && v > lo_excl && v >= lo_incl && v <= hi_incl;
+    cnt += ok ? 0u : 1u;
+  }
+  if (cnt) atomicAdd(bad, cnt);
+}
+
+// Pointwise output fields of one slot (see SPFF_FIELD_*).
+template <typename real>
+__global__ void k_fields(const SlotPtr<real>* __restrict__ ptrs, const SlotParam* __restrict__ prms,
+                         const SlotCtl* __restrict__ ctls, int slot, int n, real* __restrict__ strain,
+                         real* __restrict__ stress_out, real* __restrict__ psi_out) {
+  const SlotPtr<real> F = ptrs[slot];
+  const SlotParam& P = prms[slot];
+  const SlotCtl& C = ctls[slot];
+  const real lt = real(P.lam_t), mt = real(P.mu_t), kres = real(P.k_res);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const Sym<real> e = {real(C.eps_bar[0]) + F.eps[i], real(C.eps_bar[1]) + F.eps[n + i],
+                         real(C.eps_bar[2]) + F.eps[2 * n + i]};
+    const real E = F.E[i], ph = F.phi[i];
+    const real lam = lt * E, mu = mt * E, hk = (real(1) - ph) * (real(1) - ph) + kres;
+    if (strain) {
+      strain[i] = e.xx;
+      strain[n + i] = e.yy;
+      strain[2 * n + i] = e.xy;
+    }
+    if (stress_out) {
+      const Sym<real> sg = stress(e, lam, mu, hk, P.split);
+      stress_out[i] = sg.xx;
+      stress_out[n + i] = sg.yy;
+      stress_out[2 * n + i] = sg.xy;
+    }
+    if (psi_out) {
+      real pp, pm;
+      energies(e, lam, mu, P.split, &pp, &pm);
+      psi_out[i] = pp;
+    }
+  }
+}
+
+// ===========================================================================
+// Host-side launchers (called from the C-ABI implementation).
+// ===========================================================================
+
+template <typename real>
+hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>* ptrs, const SlotParam* prms,
+                       SlotCtl* ctls, const typename HostCplx<real>::type* twx,
+                       const typename HostCplx<real>::type* twy, double* prow, double* pcol, double* pinv,
+                       double* prof, hipEvent_t* ev, hipStream_t st) {
+  dim3 grow(G.ngr, G.S), gcol(G.ngc, G.S);
+  if (ev) (void)hipEventRecord(ev[0], st);
+  hipLaunchKernelGGL(k_rowfwd<real>, grow, dim3(THREADS), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, G.nx,
+                     G.ny, G.R, G.ngr);
+  if (ev) (void)hipEventRecord(ev[1], st);
+  hipLaunchKernelGGL(k_col<real>, gcol, dim3(THREADS), G.lds_col, st, list, ptrs, prms, ctls, twy, pcol, G.nx,
+                     G.ny, G.W, G.ngc);
+  if (ev) (void)hipEventRecord(ev[2], st);
+  hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(THREADS), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, pinv,
+                     G.nx, G.ny, G.R, G.ngr);
+  if (ev) (void)hipEventRecord(ev[3], st);
+  hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(64), 0, st, list, prms, ctls, prow, pcol, pinv, prof, G.nx,
+                     G.ny, G.ngr, G.ngc);
+  if (ev) (void)hipEventRecord(ev[4], st);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_validate(const real* a, size_t n, double lo_excl, double lo_incl, double hi_incl,
+                           unsigned int* bad, hipStream_t st) {
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_validate<real>, dim3(blocks), dim3(256), 0, st, a, n, real(lo_excl), real(lo_incl),
+                     real(hi_incl), bad);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_fields(const SlotPtr<real>* ptrs, const SlotParam* prms, const SlotCtl* ctls, int slot, int n,
+                         real* strain, real* stress_out, real* psi, hipStream_t st) {
+  int blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fields<real>, dim3(blocks), dim3(256), 0, st, ptrs, prms, ctls, slot, n, strain,
+                     stress_out, psi);
+  return hipGetLastError();
+}
+
+template hipError_t launch_tick<float>(const LaunchGeom&, const int*, const SlotPtr<float>*, const SlotParam*,
+                                       SlotCtl*, const float2*, const float2*, double*, double*, double*, double*,
+                                       hipEvent_t*, hipStream_t);
+template hipError_t launch_tick<double>(const LaunchGeom&, const int*, const SlotPtr<double>*, const SlotParam*,
+                                        SlotCtl*, const double2*, const double2*, double*, double*, double*,
+                                        double*, hipEvent_t*, hipStream_t);
+template hipError_t launch_validate<float>(const float*, size_t, double, double, double, unsigned int*,
+                                           hipStream_t);
+template hipError_t launch_validate<double>(const double*, size_t, double, double, double, unsigned int*,
+                                            hipStream_t);
+template hipError_t launch_fields<float>(const SlotPtr<float>*, const SlotParam*, const SlotCtl*, int, int,
+                                         float*, float*, float*, hipStream_t);
+template hipError_t launch_fields<double>(const SlotPtr<double>*, const SlotParam*, const SlotCtl*, int, int,
+                                          double*, double*, double*, hipStream_t);
+
+}  // namespace spff

@@ -1,0 +1,36 @@
+// Host-visible declarations of the kernel launchers defined in
+// spff_kernels.hip (explicitly instantiated there for float and double).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "spff_engine.hpp"
+
+namespace spff {
+
+template <typename real> struct HostCplx;
+template <> struct HostCplx<float> { using type = float2; };
+template <> struct HostCplx<double> { using type = double2; };
+
+struct LaunchGeom {
+  int nx, ny, S;
+  int R, ngr;  // rows per row work-group, row groups per slot
+  int W, ngc;  // columns per column work-group, column groups per slot
+  size_t lds_row, lds_col;
+};
+
+// One solver tick over the slots list[0..G.S) (entries < 0 are padding).
+template <typename real>
+hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>* ptrs, const SlotParam* prms,
+                       SlotCtl* ctls, const typename HostCplx<real>::type* twx,
+                       const typename HostCplx<real>::type* twy, double* prow, double* pcol, double* pinv,
+                       double* prof, hipEvent_t* ev, hipStream_t st);
+
+template <typename real>
+hipError_t launch_validate(const real* a, size_t n, double lo_excl, double lo_incl, double hi_incl,
+                           unsigned int* bad, hipStream_t st);
+
+template <typename real>
+hipError_t launch_fields(const SlotPtr<real>* ptrs, const SlotParam* prms, const SlotCtl* ctls, int slot, int n,
+                         real* strain, real* stress_out, real* psi, hipStream_t st);
+
+}  // namespace spff

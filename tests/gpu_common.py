@@ -1,0 +1,87 @@
+"""Helpers shared by the GPU tests: configuration, field conversion between
+the library's (xx, yy, xy) planes and the oracle's 2x2 tensors, error
+metrics of the parity contract."""
+
+import numpy as np
+import torch  # noqa: F401  (imported at collection: the first import can be slow)
+
+import oracle
+from oracle import constitutive as ocm
+from paper_2203_16467_amd import spff
+
+SPLITS = {"none": spff.SPLIT_NONE, "spectral": spff.SPLIT_SPECTRAL}
+IRRS = {"crack_set": spff.IRR_CRACK_SET, "damage": spff.IRR_DAMAGE}
+
+
+def device():
+    import torch
+    return torch.device("cuda:0")
+
+
+def cfg_for(nx, ny=None, precision="fp32", at=1, split="spectral", irr="crack_set", ell=2.0, gc=1.0, nu=0.2,
+            tol=None, **kw):
+    ny = nx if ny is None else ny
+    tol = (1e-10 if precision == "fp64" else 1e-6) if tol is None else tol
+    cfg = spff.default_config(nx=nx, ny=ny, at=at, split=SPLITS[split], irreversibility=IRRS[irr], ell=ell, gc=gc,
+                              nu=nu, precision=spff.FP64 if precision == "fp64" else spff.FP32, tol_mech=tol,
+                              tol_pf=tol)
+    # caps keep a runaway case short; the cases here converge well inside them
+    cfg.max_cg = kw.pop("max_cg", 4000)
+    cfg.max_bccg = kw.pop("max_bccg", 4000)
+    cfg.max_am = kw.pop("max_am", 200)
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def oracle_for(E, cfg, tol=1e-10, **kw):
+    split = "none" if cfg.split == spff.SPLIT_NONE else "spectral"
+    irr = "crack_set" if cfg.irreversibility == spff.IRR_CRACK_SET else "damage"
+    args = dict(nu=cfg.nu, ell=cfg.ell, gc=cfg.gc, at=cfg.at, split=split, irreversibility=irr,
+                threshold=cfg.crack_set_threshold, k_res=cfg.k_res, tol_mech=tol, tol_pf=tol,
+                max_am=cfg.max_am)
+    args.update(kw)
+    return oracle.Problem(np.asarray(E, dtype=np.float64), **args)
+
+
+def planes_to_tensor(p):
+    """(3, ny, nx) planes xx, yy, xy -> (ny, nx, 2, 2)."""
+    p = np.asarray(p, dtype=np.float64)
+    return ocm.sym_tensor(p[0], p[1], p[2])
+
+
+def tensor_to_planes(t):
+    return np.stack([t[..., 0, 0], t[..., 1, 1], t[..., 0, 1]])
+
+
+def rel_l2(a, b):
+    """||a - b|| / ||b|| with the A:B weight for tensor planes if 3 planes."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_fields(prob, index=0):
+    mask = spff.FIELD_PHI | spff.FIELD_PHI_REF | spff.FIELD_STRAIN | spff.FIELD_STRESS | spff.FIELD_PSI_PLUS | \
+        spff.FIELD_EPS_STAR
+    f = prob.get_fields(mask, index=index)
+    return {k: v.double().cpu().numpy() for k, v in f.items()}
+
+
+def oracle_fields(o):
+    return {"phi": o.phi.copy(), "phi_ref": o.phi_ref.copy(), "strain": tensor_to_planes(o.strain()),
+            "stress": tensor_to_planes(o.stress()), "psi_plus": o.psi_plus(),
+            "eps_star": tensor_to_planes(o.eps_star)}
+
+
+def set_oracle_from_gpu(o, prob, index=0):
+    st, eb = prob.get_state()
+    s = st[index].double().cpu().numpy()
+    o.set_state({"eps_star": planes_to_tensor(s[0:3]), "phi": s[3], "phi_ref": s[4],
+                 "eps_bar": ocm.sym_tensor(*eb[index])})
+
+
+def crack_xor_fraction(phi_a, phi_b, thr=0.9):
+    a = np.asarray(phi_a) > thr
+    b = np.asarray(phi_b) > thr
+    return float(np.count_nonzero(a ^ b)) / a.size

@@ -1,0 +1,84 @@
+"""The C-ABI library loads and exports every entry point that include/spff.h
+declares; host-side validation works without a GPU (no compute calls)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2203_16467_amd import spff
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spff.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spff_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for required in ("spff_create_problem", "spff_load_step", "spff_get_fields", "spff_create_batch",
+                     "spff_load_step_batch", "spff_workspace_bytes", "spff_destroy_problem"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = spff.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding knows all of them
+    assert set(declared_functions()) <= set(spff._SIGS)
+
+
+def test_version_and_defaults():
+    assert "gfx950" in spff.version()
+    cfg = spff.default_config()
+    assert (cfg.nx, cfg.ny, cfg.at, cfg.split, cfg.irreversibility, cfg.precision) == (64, 64, 1, 1, 0, 0)
+    assert cfg.nu == 0.2 and cfg.ell == 2.0 and cfg.crack_set_threshold == 0.9
+
+
+def test_workspace_bytes_scales_with_batch():
+    cfg = spff.default_config(nx=256, ny=256)
+    one = spff.workspace_bytes(cfg, 1)
+    four = spff.workspace_bytes(cfg, 4)
+    n = 256 * 256
+    # 18 real planes per problem (state + scratch + spectrum) at minimum
+    assert one >= 18 * 4 * n
+    assert four - one >= 3 * 18 * 4 * n
+    cfg64 = spff.default_config(nx=256, ny=256, precision=spff.FP64)
+    assert spff.workspace_bytes(cfg64, 1) > 1.9 * one
+
+
+@pytest.mark.parametrize("field,value", [("nx", 100), ("ny", 4), ("nx", 4096), ("nu", 0.5), ("nu", -1.0),
+                                         ("ell", 0.0), ("gc", -1.0), ("at", 3), ("split", 2),
+                                         ("irreversibility", 5), ("precision", 2), ("max_cg", 0),
+                                         ("ticks_per_sync", 0), ("tol_pf", -1.0), ("k_res", -0.1)])
+def test_invalid_config_rejected(field, value):
+    cfg = spff.default_config()
+    setattr(cfg, field, value)
+    out = ctypes.c_size_t(0)
+    st = spff.lib().spff_workspace_bytes(ctypes.byref(cfg), 1, ctypes.byref(out))
+    assert st == spff.E_INVALID
+    assert spff.last_error()
+
+
+def test_create_rejects_null_arguments_without_device():
+    cfg = spff.default_config()
+    h = ctypes.c_void_p()
+    L = spff.lib()
+    assert L.spff_create_batch(ctypes.byref(cfg), 1, None, None, None, 0, None, ctypes.byref(h)) == spff.E_INVALID
+    assert L.spff_create_batch(ctypes.byref(cfg), 0, ctypes.c_void_p(256), None, ctypes.c_void_p(256), 0, None,
+                               ctypes.byref(h)) == spff.E_INVALID
+    # misaligned workspace
+    assert L.spff_create_batch(ctypes.byref(cfg), 1, ctypes.c_void_p(256), None, ctypes.c_void_p(257), 1 << 30,
+                               None, ctypes.byref(h)) == spff.E_INVALID
+    # too small workspace
+    assert L.spff_create_batch(ctypes.byref(cfg), 1, ctypes.c_void_p(256), None, ctypes.c_void_p(512), 16, None,
+                               ctypes.byref(h)) == spff.E_NOMEM
+    assert L.spff_load_step(None, None, None) == spff.E_INVALID
+    assert L.spff_get_fields(None, 0, 1, None) == spff.E_INVALID
+    assert L.spff_destroy_problem(None) == spff.OK

@@ -1,0 +1,301 @@
+"""GPU solver parity against the FP64 oracle (same seeded inputs).
+
+Contract for the FP32-bulk path (fields FP32, reductions FP64): strain /
+stress / eps* relative L2 <= 1e-4, phi max-abs <= 1e-3, crack set {phi > 0.9}
+differing in <= 0.5% of pixels, energies relative <= 1e-4.  The FP64 path is
+held to 1e-7 (solver tolerances 1e-10 on both sides; what remains is the
+different operation order of the two FFT implementations and reductions).
+
+Trajectories are compared step by step where crack nucleation makes the
+alternating minimisation path-sensitive (the oracle then starts the step
+from the GPU's state promoted to FP64)."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import spff_inputs as si
+from gpu_common import (cfg_for, crack_xor_fraction, device, gpu_fields, oracle_fields, oracle_for, rel_l2,
+                        set_oracle_from_gpu)
+from paper_2203_16467_amd import spff
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "strength_closed_forms.json")))
+
+
+def torch_E(E, precision, B=1):
+    import torch
+    t = torch.as_tensor(np.asarray(E), device=device())
+    t = t.double() if precision == "fp64" else t.float()
+    return t.expand(B, *t.shape[-2:]).contiguous() if t.dim() == 2 else t
+
+
+def tol_fields(precision):
+    return 1e-7 if precision == "fp64" else 1e-4
+
+
+def compare(gf, of, precision, phi_tol=None, what=("strain", "stress", "eps_star", "psi_plus")):
+    t = tol_fields(precision)
+    out = {}
+    for k in what:
+        scale = max(np.abs(of[k]).max(), 1e-30)
+        if k == "eps_star" and scale < 1e-12:
+            err = float(np.abs(gf[k] - of[k]).max())
+            assert err < 1e-6, (k, err)
+        else:
+            err = rel_l2(gf[k], of[k])
+            assert err <= t, (k, err)
+        out[k] = err
+    pt = phi_tol if phi_tol is not None else (1e-7 if precision == "fp64" else 1e-3)
+    e = float(np.abs(gf["phi"] - of["phi"]).max())
+    assert e <= pt, ("phi", e)
+    assert crack_xor_fraction(gf["phi"], of["phi"]) <= 0.005
+    out["phi"] = e
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("split", ["none", "spectral"])
+def test_homogeneous_strength_closed_form(precision, split):
+    """Sec. 3.3 printed values: homogeneous AT1 under uniaxial strain,
+    onset at eps_M = 0.005809, peak sigma_M = 64.55 G_c/l."""
+    g = GOLDEN["uniaxial_strain_AT1"]
+    n = 16
+    cfg = cfg_for(n, precision=precision, split=split, ell=g["ell"], gc=g["gc"], nu=g["nu"])
+    p = spff.Problem(torch_E(np.full((n, n), g["E0"]), precision), cfg)
+    lam = g["E0"] * g["nu"] / (1 - g["nu"] - 2 * g["nu"] ** 2)
+    mu = g["E0"] / (2 + 2 * g["nu"])
+    for f in (0.99, 1.0, 1.01, 1.2):
+        st, stats = p.load_step((0.0, f * g["eps_M"], 0.0))
+        s = stats[0]
+        psi = 0.5 * (lam + 2 * mu) * (f * g["eps_M"]) ** 2
+        want = max(0.0, 1 - 3 * g["gc"] / (16 * g["ell"] * psi))
+        phi = p.get_fields(spff.FIELD_PHI, 0)["phi"].double().cpu().numpy()
+        tol = 1e-9 if precision == "fp64" else 2e-5
+        if f == 1.0:
+            tol = 3e-3
+        assert np.abs(phi - want).max() <= tol, (f, np.abs(phi - want).max(), want)
+        if f == 1.0:
+            assert s["sigma_bar"][1] == pytest.approx(g["sigma_M"], abs=0.05)
+    p.close()
+
+
+def _c1_inputs(n=64):
+    E = si.young_modulus(n, 4.0, 0.1, 1000)
+    ramp = si.uniaxial_ramp(20, 0.2, 2.0)
+    return E, ramp
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("split", ["none", "spectral"])
+def test_mechanics_step_parity(precision, split):
+    """One load step below the AT1 onset: a pure mechanics solve on the
+    64x64 heterogeneous input (workload recipe of the plain CPU-sized case)."""
+    E, ramp = _c1_inputs()
+    cfg = cfg_for(64, precision=precision, split=split)
+    p = spff.Problem(torch_E(E, precision), cfg)
+    o = oracle_for(E, cfg)
+    for s in (4, 5):
+        st, stats = p.load_step(ramp[s])
+        ost = o.load_step(ramp[s])
+        assert st == spff.OK
+        cmp = compare(gpu_fields(p), oracle_fields(o), precision)
+        print(s, cmp, stats[0]["cg_iters"], ost["cg"])
+        assert stats[0]["F_e"] == pytest.approx(ost["F_e"], rel=tol_fields(precision))
+        for k in range(3):
+            assert stats[0]["sigma_bar"][k] == pytest.approx(ost["sigma_bar"][k], rel=tol_fields(precision),
+                                                             abs=1e-12)
+    p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("split", ["none", "spectral"])
+def test_at2_step_parity(precision, split):
+    """AT2 evolves phi from the first load (active BCCG every step)."""
+    E, ramp = _c1_inputs()
+    cfg = cfg_for(64, precision=precision, split=split, at=2)
+    p = spff.Problem(torch_E(E, precision), cfg)
+    o = oracle_for(E, cfg)
+    for s in (6, 10):
+        set_oracle_from_gpu(o, p)
+        st, stats = p.load_step(ramp[s])
+        ost = o.load_step(ramp[s])
+        cmp = compare(gpu_fields(p), oracle_fields(o), precision)
+        print(s, cmp, stats[0]["am_iters"], ost["am"], stats[0]["bccg_iters"], ost["bccg"])
+        assert stats[0]["F_f"] == pytest.approx(ost["F_f"], rel=10 * tol_fields(precision))
+        assert stats[0]["F_e"] == pytest.approx(ost["F_e"], rel=10 * tol_fields(precision))
+    p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_c1_trajectory_before_nucleation(precision):
+    """Whole-trajectory parity of the CPU-sized case (64x64, AT1, spectral,
+    crack set) over the load steps before the first crack."""
+    E, ramp = _c1_inputs()
+    cfg = cfg_for(64, precision=precision)
+    p = spff.Problem(torch_E(E, precision), cfg)
+    o = oracle_for(E, cfg)
+    for s in range(11):
+        st, stats = p.load_step(ramp[s])
+        ost = o.load_step(ramp[s])
+        assert stats[0]["phi_max"] == 0.0 and ost["phi_max"] == 0.0
+    compare(gpu_fields(p), oracle_fields(o), precision)
+    p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("irr", ["crack_set", "damage"])
+def test_nucleation_step_parity(precision, irr):
+    """Step-wise parity at the nucleation load step (AM capped at 3
+    iterations so the oracle stays quick): both sides start from the GPU
+    state after the previous step."""
+    E, ramp = _c1_inputs()
+    cfg = cfg_for(64, precision=precision, irr=irr, max_am=3)
+    p = spff.Problem(torch_E(E, precision), cfg)
+    for s in range(12):
+        p.load_step(ramp[s])
+    o = oracle_for(E, cfg, max_am=3)
+    set_oracle_from_gpu(o, p)
+    st, stats = p.load_step(ramp[12])
+    ost = o.load_step(ramp[12])
+    print(stats[0], ost)
+    assert stats[0]["phi_max"] > 0.0
+    cmp = compare(gpu_fields(p), oracle_fields(o), precision,
+                  phi_tol=1e-6 if precision == "fp64" else 1e-3)
+    print(cmp)
+    assert stats[0]["am_iters"] == ost["am"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_initial_crack_solve(precision):
+    """Algorithm 2, first two lines: a phi_init edge crack is relaxed at zero
+    strain under phi_con(phi_init)."""
+    import torch
+    n = 64
+    phi0 = si.edge_crack(n, n, 2.0, 32.0)
+    E = np.ones((n, n), dtype=np.float32)
+    cfg = cfg_for(n, precision=precision)
+    p = spff.Problem(torch_E(E, precision), cfg, phi_init=torch.as_tensor(phi0, device=device()))
+    o = oracle_for(E, cfg, phi_init=phi0.astype(np.float64))
+    g = gpu_fields(p)
+    assert np.abs(g["phi"] - o.phi).max() <= (1e-7 if precision == "fp64" else 1e-4)
+    p.close()
+
+
+def test_batch_equals_single_bitwise():
+    """Problems in a batch do not interact: each result is bitwise the one
+    of the same problem run alone."""
+    E, ramp = _c1_inputs()
+    Es = np.stack([E, si.young_modulus(64, 4.0, 0.1, 1001), si.young_modulus(64, 4.0, 0.2, 1002)])
+    cfg = cfg_for(64, at=2)
+    pb = spff.Problem(torch_E(Es, "fp32"), cfg)
+    for s in (8, 10):
+        pb.load_step(ramp[s])
+    fb = [gpu_fields(pb, i) for i in range(3)]
+    for i in range(3):
+        ps = spff.Problem(torch_E(Es[i], "fp32"), cfg)
+        for s in (8, 10):
+            ps.load_step(ramp[s])
+        fs = gpu_fields(ps)
+        for k in fb[i]:
+            assert np.array_equal(fb[i][k], fs[k]), (i, k)
+        ps.close()
+    pb.close()
+
+
+def test_graph_replay_matches_eager():
+    E, ramp = _c1_inputs()
+    base = dict(at=2)
+    a = spff.Problem(torch_E(E, "fp32"), cfg_for(64, **base))
+    b = spff.Problem(torch_E(E, "fp32"), cfg_for(64, use_graph=1, ticks_per_sync=8, **base))
+    for s in (8, 9, 10):
+        sa = a.load_step(ramp[s])[1][0]
+        sb = b.load_step(ramp[s])[1][0]
+        assert sa["cg_iters"] == sb["cg_iters"] and sa["bccg_iters"] == sb["bccg_iters"]
+    fa, fb = gpu_fields(a), gpu_fields(b)
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_state_roundtrip():
+    E, ramp = _c1_inputs()
+    cfg = cfg_for(64, at=2)
+    a = spff.Problem(torch_E(E, "fp32"), cfg)
+    for s in (6, 8, 10):
+        a.load_step(ramp[s])
+    b = spff.Problem(torch_E(E, "fp32"), cfg)
+    b.load_step(ramp[6])
+    st, eb = b.get_state()
+    c = spff.Problem(torch_E(E, "fp32"), cfg)
+    c.set_state(st, eb)
+    for s in (8, 10):
+        c.load_step(ramp[s])
+    fa, fc = gpu_fields(a), gpu_fields(c)
+    for k in fa:
+        assert np.array_equal(fa[k], fc[k]), k
+
+
+def test_invalid_inputs_rejected_on_device():
+    import torch
+    n = 32
+    E = np.ones((n, n), dtype=np.float32)
+    E[3, 4] = -1.0
+    with pytest.raises(spff.SpffError) as ei:
+        spff.Problem(torch_E(E, "fp32"), cfg_for(n))
+    assert ei.value.status == spff.E_INVALID
+    E[3, 4] = np.nan
+    with pytest.raises(spff.SpffError):
+        spff.Problem(torch_E(E, "fp32"), cfg_for(n))
+    E[3, 4] = 1.0
+    phi0 = np.zeros((n, n), dtype=np.float32)
+    phi0[0, 0] = 1.5
+    with pytest.raises(spff.SpffError):
+        spff.Problem(torch_E(E, "fp32"), cfg_for(n), phi_init=torch.as_tensor(phi0, device=device()))
+
+
+def test_iteration_cap_warns_and_keeps_fields_valid():
+    E, ramp = _c1_inputs()
+    cfg = cfg_for(64, max_cg=2)
+    p = spff.Problem(torch_E(E, "fp32"), cfg)
+    st, stats = p.load_step(ramp[5])
+    assert st == spff.WARN_NOT_CONVERGED and stats[0]["status"] == spff.WARN_NOT_CONVERGED
+    g = gpu_fields(p)
+    assert all(np.all(np.isfinite(v)) for v in g.values())
+
+
+def test_run_sequence_matches_single_problem_steps():
+    """Independent progression: problems of a batch run their own load-step
+    sequences (different ramps); each equals the same problem stepped alone."""
+    E, ramp = _c1_inputs()
+    Es = np.stack([E, si.young_modulus(64, 4.0, 0.2, 1002)])
+    seqs = np.stack([ramp[8:12], 1.1 * ramp[6:10]])
+    cfg = cfg_for(64, at=2, use_graph=1, ticks_per_sync=4)
+    pb = spff.Problem(torch_E(Es, "fp32"), cfg)
+    st, stats = pb.run_sequence(seqs)
+    assert st >= 0
+    fb = [gpu_fields(pb, i) for i in range(2)]
+    for i in range(2):
+        ps = spff.Problem(torch_E(Es[i], "fp32"), cfg_for(64, at=2))
+        for k in range(seqs.shape[1]):
+            _, s1 = ps.load_step(seqs[i, k])
+            assert s1[0]["cg_iters"] == stats[i][k]["cg_iters"]
+            assert s1[0]["bccg_iters"] == stats[i][k]["bccg_iters"]
+        fs = gpu_fields(ps)
+        for key in fb[i]:
+            assert np.array_equal(fb[i][key], fs[key]), (i, key)
+        ps.close()
+    pb.close()
+
+
+def test_profile_counters():
+    E, ramp = _c1_inputs()
+    p = spff.Problem(torch_E(E, "fp32"), cfg_for(64, use_graph=1, ticks_per_sync=4))
+    p.profile_enable(True)
+    p.run_sequence(ramp[3:6])
+    prof = p.profile_read()
+    assert prof["ticks"] > 0 and all(v > 0 for v in prof["launches"].values())
+    assert prof["alg_bytes"]["rowfwd"] > 0 and prof["alg_bytes"]["col"] > 0
+    assert all(v > 0 for v in prof["kernel_ms"].values())
