@@ -104,7 +104,11 @@ typedef struct spff_config {
    * terminate instead of iterating on rounding noise. */
   double floor_factor;
   int32_t stall_iters;     /* BCCG stops when its residual has not improved for this many iterations (0: off) */
-  int32_t pad_;
+  /* Launch-plan overrides for every bucket of active problems (0 = the
+   * built-in heuristic; set by the autotuner): rows per row-FFT work-group,
+   * columns per column-FFT work-group (powers of two), threads per
+   * work-group (64, 128 or 256; threads * 8 >= max(nx/2, ny)). */
+  int32_t plan_rows, plan_cols, plan_threads;
 } spff_config;
 
 /* Per-problem result of one load step (Sec. 3.2.1 quantities). */
@@ -226,6 +230,63 @@ spff_status spff_problem_info(const spff_problem* p, int32_t* nbatch, int32_t* n
 
 /* Release the host handle (the caller frees the workspace). */
 spff_status spff_destroy_problem(spff_problem* p);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of load-step requests over resident problems.
+ *
+ * A server owns a caller-provided device arena.  Each registered problem keeps
+ * its resident state there (E, phi, phi_ref, eps*: 6 planes) for the life of
+ * the server.  Problems are grouped in size classes (nx, ny, precision); each
+ * class has one solver engine with a fixed number of scratch slots (12 planes
+ * each: CG/BCCG vectors and half spectra) on its own stream, so classes run
+ * concurrently on the device.  The scratch budget sets the slot counts
+ * (admission by HBM footprint).  A request is one load step (Algorithm 2) of
+ * one problem; requests of one problem run in submission order, one at a time.
+ * spff_server_progress admits queued requests into free slots between tick
+ * blocks, so requests that arrive while others run join the batch as slots
+ * free up (their work overlaps on the device).  A problem's result does not
+ * depend on what else runs (fixed-order reductions); with fixed launch-plan
+ * overrides it is bitwise identical to running the problem alone.
+ * ------------------------------------------------------------------------- */
+typedef struct spff_server spff_server;
+
+/* arena_dev: device memory owned by the caller (256-byte aligned), used for
+ * resident state and class engines.  scratch_budget_bytes: upper bound on
+ * engine scratch over all classes (0 = no bound beyond the arena).
+ * ticks_per_sync / use_graph as in spff_config.  stream is unused (each class
+ * creates its own non-blocking stream of default priority). */
+spff_status spff_server_create(void* arena_dev, size_t arena_bytes, size_t scratch_budget_bytes,
+                               int32_t ticks_per_sync, int32_t use_graph, spff_server** out);
+
+/* Register a problem (copies E, real[ny][nx] on the device, into the arena;
+ * phi = eps* = 0).  cfg->nx, ny, precision pick the class; the physical and
+ * solver fields are per problem.  Fails with SPFF_E_NOMEM when the arena is
+ * full.  Problems may be registered while others run. */
+spff_status spff_server_register(spff_server* sv, const spff_config* cfg, const void* E_dev, int32_t* id);
+
+/* Queue one load step of problem id at eps_bar (host double[3]). */
+spff_status spff_server_submit(spff_server* sv, int32_t id, const double eps_bar[3], uint64_t* ticket);
+
+/* Drive the device: up to max_rounds rounds of (admit, launch one tick block
+ * per busy class, collect finished requests).  *completed receives the number
+ * of requests finished during the call, *pending the number still queued or
+ * running. */
+spff_status spff_server_progress(spff_server* sv, int32_t max_rounds, int32_t* completed, int32_t* pending);
+
+/* Result of a request: SPFF_OK and *out filled when done (wall_ms = submit to
+ * completion), SPFF_E_BUSY while pending, SPFF_E_INVALID for an unknown or
+ * already collected ticket. */
+spff_status spff_server_poll(spff_server* sv, uint64_t ticket, spff_step_stats* out);
+
+/* Resident fields of a problem (mask of SPFF_FIELD_PHI, SPFF_FIELD_PHI_REF,
+ * SPFF_FIELD_EPS_STAR) into caller device buffers; only between requests of
+ * that problem (SPFF_E_BUSY otherwise). */
+spff_status spff_server_get_fields(spff_server* sv, int32_t id, uint32_t mask, void* const* dst);
+
+/* Scratch slots per class and bytes used in the arena. */
+spff_status spff_server_info(const spff_server* sv, int32_t* nclasses, int32_t* total_slots, size_t* arena_used);
+
+spff_status spff_server_destroy(spff_server* sv);
 
 /* Thread-local message for the last non-OK status ("" if none). */
 const char* spff_last_error(void);

@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <deque>
+#include <unordered_map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -76,6 +78,17 @@ spff_status check_config(const spff_config* c) {
     return fail(SPFF_E_INVALID, "iteration caps must be >= 1");
   if (c->ticks_per_sync < 1 || c->ticks_per_sync > 4096) return fail(SPFF_E_INVALID, "ticks_per_sync in [1, 4096]");
   if (!(c->floor_factor >= 0.0) || c->stall_iters < 0) return fail(SPFF_E_INVALID, "floor_factor, stall_iters >= 0");
+  if (c->plan_rows < 0 || (c->plan_rows > 0 && (!pow2(c->plan_rows) || c->plan_rows > c->ny)))
+    return fail(SPFF_E_INVALID, "plan_rows must be 0 or a power of two <= ny");
+  if (c->plan_cols < 0 || (c->plan_cols > 0 && (!pow2(c->plan_cols) || c->plan_cols > c->nx / 2)))
+    return fail(SPFF_E_INVALID, "plan_cols must be 0 or a power of two <= nx/2");
+  if (c->plan_threads != 0 && c->plan_threads != 64 && c->plan_threads != 128 && c->plan_threads != 256)
+    return fail(SPFF_E_INVALID, "plan_threads must be 0, 64, 128 or 256");
+  {
+    const int T = c->plan_threads > 0 ? c->plan_threads : THREADS;
+    if (T * MAXE < c->nx / 2 || T * MAXE < c->ny)
+      return fail(SPFF_E_INVALID, "plan_threads * 8 must cover nx/2 and ny");
+  }
   return SPFF_OK;
 }
 
@@ -98,6 +111,9 @@ LaunchGeom plan(const spff_config* c, int S, size_t csize) {
   while (W * 2 <= M && 3 * (size_t)(2 * W) * (c->ny + PAD) * csize <= LDS_TARGET &&
          (long)(M / (2 * W)) * S >= TARGET_WG)
     W *= 2;
+  if (c->plan_rows > 0) R = c->plan_rows;
+  if (c->plan_cols > 0) W = c->plan_cols;
+  G.threads = c->plan_threads > 0 ? c->plan_threads : THREADS;
   G.R = R;
   G.ngr = c->ny / R;
   G.W = W;
@@ -107,7 +123,9 @@ LaunchGeom plan(const spff_config* c, int S, size_t csize) {
   return G;
 }
 
-Layout layout(const spff_config* c, int S, size_t rsize) {
+// scratch_only: slots hold solver scratch only; the resident planes
+// (E, phi, phi_ref, eps*) of the problem bound to a slot live elsewhere.
+Layout layout(const spff_config* c, int S, size_t rsize, bool scratch_only = false) {
   Layout L{};
   const size_t n = (size_t)c->nx * c->ny;
   size_t off = 0;
@@ -135,10 +153,12 @@ Layout layout(const spff_config* c, int S, size_t rsize) {
     so = align_up(so + bytes);
     return o;
   };
-  L.E = stake(rsize * n);
-  L.phi = stake(rsize * n);
-  L.phi_ref = stake(rsize * n);
-  L.eps = stake(3 * rsize * n);
+  if (!scratch_only) {
+    L.E = stake(rsize * n);
+    L.phi = stake(rsize * n);
+    L.phi_ref = stake(rsize * n);
+    L.eps = stake(3 * rsize * n);
+  }
   L.theta = stake(3 * rsize * n);
   L.rm = stake(3 * rsize * n);
   L.pm = stake(3 * rsize * n);
@@ -169,6 +189,8 @@ struct spff_problem {
   SlotCtl* host_ctl;  // pinned mirror
   std::vector<SlotParam> prm;
   std::vector<double> last_eps_bar;
+  bool scratch_only = false;
+  std::vector<SlotPtr<double>> host_ptrs;  // layout-identical for float and double
   // profiling
   bool prof_on = false;
   std::vector<hipEvent_t> events;  // 5 per tick of a block
@@ -373,19 +395,25 @@ template <typename real>
 spff_status init_device(spff_problem* p, const void* E_dev, const void* phi_init_dev) {
   const size_t n = p->n();
   const size_t rb = sizeof(real) * n;
-  std::vector<SlotPtr<real>> ptrs(p->S);
+  static_assert(sizeof(SlotPtr<real>) == sizeof(SlotPtr<double>), "pointer tables differ");
+  p->host_ptrs.assign(p->S, SlotPtr<double>{});
   for (int s = 0; s < p->S; ++s) {
     unsigned char* b = p->slot(s);
-    ptrs[s].E = reinterpret_cast<const real*>(b + p->L.E);
-    ptrs[s].phi = reinterpret_cast<real*>(b + p->L.phi);
-    ptrs[s].phi_ref = reinterpret_cast<real*>(b + p->L.phi_ref);
-    ptrs[s].eps = reinterpret_cast<real*>(b + p->L.eps);
-    ptrs[s].theta = reinterpret_cast<real*>(b + p->L.theta);
-    ptrs[s].rm = reinterpret_cast<real*>(b + p->L.rm);
-    ptrs[s].pm = reinterpret_cast<real*>(b + p->L.pm);
-    ptrs[s].spec = reinterpret_cast<void*>(b + p->L.spec);
+    SlotPtr<real> e{};
+    if (!p->scratch_only) {
+      e.E = reinterpret_cast<const real*>(b + p->L.E);
+      e.phi = reinterpret_cast<real*>(b + p->L.phi);
+      e.phi_ref = reinterpret_cast<real*>(b + p->L.phi_ref);
+      e.eps = reinterpret_cast<real*>(b + p->L.eps);
+    }
+    e.theta = reinterpret_cast<real*>(b + p->L.theta);
+    e.rm = reinterpret_cast<real*>(b + p->L.rm);
+    e.pm = reinterpret_cast<real*>(b + p->L.pm);
+    e.spec = reinterpret_cast<void*>(b + p->L.spec);
+    std::memcpy(&p->host_ptrs[s], &e, sizeof(e));
   }
-  HIP_TRY(hipMemcpyAsync(p->d_ptr(), ptrs.data(), sizeof(SlotPtr<real>) * p->S, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_ptr(), p->host_ptrs.data(), sizeof(SlotPtr<real>) * p->S, hipMemcpyHostToDevice,
+                         p->stream));
   HIP_TRY(hipMemcpyAsync(p->d_prm(), p->prm.data(), sizeof(SlotParam) * p->S, hipMemcpyHostToDevice, p->stream));
   std::vector<unsigned char> tw;
   fill_twiddles<real>(tw, p->cfg.nx);
@@ -395,6 +423,14 @@ spff_status init_device(spff_problem* p, const void* E_dev, const void* phi_init
   // the synchronous twiddle staging buffer is reused: wait for the copies
   HIP_TRY(hipStreamSynchronize(p->stream));
 
+  if (p->scratch_only) {
+    for (int s = 0; s < p->S; ++s) {
+      unsigned char* b = p->slot(s);
+      HIP_TRY(hipMemsetAsync(b + p->L.theta, 0, 9 * rb, p->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return SPFF_OK;
+  }
   // inputs and zeroed state
   unsigned int* bad = reinterpret_cast<unsigned int*>(p->ws + p->L.bad);
   HIP_TRY(hipMemsetAsync(bad, 0, 2 * sizeof(unsigned int), p->stream));
@@ -519,14 +555,19 @@ spff_status spff_workspace_bytes(const spff_config* cfg, int32_t nbatch, size_t*
   return SPFF_OK;
 }
 
-spff_status spff_create_batch(const spff_config* cfg, int32_t nbatch, const void* E_dev, const void* phi_init_dev,
-                              void* workspace, size_t workspace_bytes, void* stream, spff_problem** out) {
+}  // extern "C"
+
+namespace {
+
+spff_status engine_create(const spff_config* cfg, int32_t nbatch, const void* E_dev, const void* phi_init_dev,
+                          void* workspace, size_t workspace_bytes, void* stream, bool scratch_only,
+                          spff_problem** out) {
   spff_status st = check_config(cfg);
   if (st != SPFF_OK) return st;
   if (!out) return fail(SPFF_E_INVALID, "out is NULL");
   *out = nullptr;
   if (nbatch < 1) return fail(SPFF_E_INVALID, "nbatch must be >= 1");
-  if (!E_dev) return fail(SPFF_E_INVALID, "E_dev is NULL");
+  if (!E_dev && !scratch_only) return fail(SPFF_E_INVALID, "E_dev is NULL");
   if (!workspace) return fail(SPFF_E_INVALID, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return fail(SPFF_E_INVALID, "workspace must be 256-byte aligned");
   const size_t rsize = cfg->precision == SPFF_FP64 ? 8 : 4;
@@ -541,12 +582,12 @@ spff_status spff_create_batch(const spff_config* cfg, int32_t nbatch, const void
     if (G.lds_row > LDS_MAX || G.lds_col > LDS_MAX) return fail(SPFF_E_INVALID, "grid too large for LDS tiles");
     geoms.push_back(G);
   }
-  if (cfg->nx / 2 > THREADS * MAXE || cfg->ny > THREADS * MAXE) return fail(SPFF_E_INVALID, "grid too large");
-  Layout L = layout(cfg, nbatch, rsize);
+  Layout L = layout(cfg, nbatch, rsize, scratch_only);
   if (workspace_bytes < L.total)
     return fail(SPFF_E_NOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, L.total);
 
   spff_problem* p = new spff_problem();
+  p->scratch_only = scratch_only;
   p->cfg = *cfg;
   p->S = nbatch;
   p->rsize = rsize;
@@ -591,6 +632,15 @@ spff_status spff_create_batch(const spff_config* cfg, int32_t nbatch, const void
   if (hipStreamSynchronize(p->stream) != hipSuccess) return cleanup(fail(SPFF_E_DEVICE, "stream sync failed"));
   *out = p;
   return SPFF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spff_status spff_create_batch(const spff_config* cfg, int32_t nbatch, const void* E_dev, const void* phi_init_dev,
+                              void* workspace, size_t workspace_bytes, void* stream, spff_problem** out) {
+  return engine_create(cfg, nbatch, E_dev, phi_init_dev, workspace, workspace_bytes, stream, false, out);
 }
 
 spff_status spff_create_problem(const spff_config* cfg, const void* E_dev, const void* phi_init_dev,
@@ -842,5 +892,342 @@ spff_status spff_destroy_problem(spff_problem* p) {
 const char* spff_last_error(void) { return g_last_error.c_str(); }
 
 const char* spff_version(void) { return "spff 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving: continuous batching over resident problems (see include/spff.h).
+// ===========================================================================
+namespace {
+
+struct SrvRequest {
+  uint64_t ticket;
+  double eb[3];
+  double t_submit;
+};
+
+struct SrvProblem {
+  int cls;
+  spff_config cfg;
+  unsigned char *E, *phi, *phi_ref, *eps;  // resident planes in the arena
+  std::deque<SrvRequest> queue;            // submitted, not yet admitted
+  bool running = false;
+  double t_submit = 0.0;
+  uint64_t ticket = 0;
+};
+
+struct SrvClass {
+  int nx, ny, precision;
+  spff_problem* eng = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done_ev = nullptr;
+  std::vector<int> owner;  // problem id per slot, -1 free
+  std::deque<int> ready;   // problems with a request waiting for a slot
+  bool inflight = false;
+  std::vector<int> members;
+};
+
+}  // namespace
+
+struct spff_server {
+  unsigned char* arena;
+  size_t arena_bytes, used;
+  size_t scratch_budget, scratch_used;
+  int ticks_per_sync, use_graph;
+  hipStream_t setup;
+  std::vector<SrvProblem> probs;
+  std::vector<SrvClass> classes;
+  std::unordered_map<uint64_t, spff_step_stats> done;
+  std::unordered_map<uint64_t, int> live;  // ticket -> problem (queued or running)
+  uint64_t next_ticket = 1;
+};
+
+namespace {
+
+unsigned char* arena_take(spff_server* sv, size_t bytes) {
+  const size_t off = align_up(sv->used);
+  if (off + bytes > sv->arena_bytes) return nullptr;
+  sv->used = off + bytes;
+  return sv->arena + off;
+}
+
+// Create the engine of a class: as many scratch slots as the budget share of
+// the class allows (at least one, at most its number of problems).
+spff_status class_start(spff_server* sv, int c) {
+  SrvClass& C = sv->classes[c];
+  const spff_config& cfg0 = sv->probs[C.members[0]].cfg;
+  spff_config ec = cfg0;
+  ec.ticks_per_sync = sv->ticks_per_sync;
+  ec.use_graph = sv->use_graph;
+  const size_t rsize = ec.precision == SPFF_FP64 ? 8 : 4;
+  const size_t one = layout(&ec, 1, rsize, true).total;
+  const size_t two = layout(&ec, 2, rsize, true).total;
+  const size_t per_slot = two - one;
+  // budget share proportional to the class's pixels over all classes
+  double px_all = 0.0, px_c = 0.0;
+  for (const SrvClass& K : sv->classes) px_all += (double)K.nx * K.ny * K.members.size();
+  px_c = (double)C.nx * C.ny * C.members.size();
+  size_t budget = sv->scratch_budget ? (size_t)(sv->scratch_budget * (px_c / px_all)) : sv->arena_bytes;
+  int S = (int)std::min<size_t>(C.members.size(), budget > one ? 1 + (budget - one) / per_slot : 1);
+  S = std::max(1, std::min(S, 1024));
+  for (;;) {
+    const size_t bytes = layout(&ec, S, rsize, true).total;
+    const size_t off = align_up(sv->used);
+    if (off + bytes <= sv->arena_bytes) break;
+    if (S == 1) return fail(SPFF_E_NOMEM, "arena too small for a class engine");
+    S = S / 2;
+  }
+  const size_t bytes = layout(&ec, S, rsize, true).total;
+  unsigned char* ws = arena_take(sv, bytes);
+  HIP_TRY(hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&C.done_ev, hipEventDisableTiming));
+  spff_status st = engine_create(&ec, S, nullptr, nullptr, ws, bytes, C.stream, true, &C.eng);
+  if (st != SPFF_OK) return st;
+  sv->scratch_used += bytes;
+  C.owner.assign(S, -1);
+  return SPFF_OK;
+}
+
+// Bind problem `id` to slot s of its class engine and start its next request.
+spff_status class_admit(spff_server* sv, SrvClass& C, int s, int id) {
+  SrvProblem& P = sv->probs[id];
+  spff_problem* e = C.eng;
+  SrvRequest rq = P.queue.front();
+  P.queue.pop_front();
+  P.running = true;
+  P.ticket = rq.ticket;
+  P.t_submit = rq.t_submit;
+  C.owner[s] = id;
+  SlotPtr<double>& ptr = e->host_ptrs[s];
+  ptr.E = reinterpret_cast<const double*>(P.E);
+  ptr.phi = reinterpret_cast<double*>(P.phi);
+  ptr.phi_ref = reinterpret_cast<double*>(P.phi_ref);
+  ptr.eps = reinterpret_cast<double*>(P.eps);
+  e->prm[s] = make_param(&P.cfg);
+  HIP_TRY(hipMemcpyAsync(static_cast<unsigned char*>(e->d_ptr()) + s * sizeof(SlotPtr<double>), &ptr,
+                         sizeof(SlotPtr<double>), hipMemcpyHostToDevice, C.stream));
+  HIP_TRY(hipMemcpyAsync(e->d_prm() + s, &e->prm[s], sizeof(SlotParam), hipMemcpyHostToDevice, C.stream));
+  start_step(e, s, rq.eb);
+  return SPFF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spff_status spff_server_create(void* arena_dev, size_t arena_bytes, size_t scratch_budget_bytes,
+                               int32_t ticks_per_sync, int32_t use_graph, spff_server** out) {
+  if (!out) return fail(SPFF_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!arena_dev || reinterpret_cast<uintptr_t>(arena_dev) % ALIGN)
+    return fail(SPFF_E_INVALID, "arena must be a 256-byte aligned device pointer");
+  if (ticks_per_sync < 1 || ticks_per_sync > 4096) return fail(SPFF_E_INVALID, "ticks_per_sync in [1, 4096]");
+  spff_server* sv = new spff_server();
+  sv->arena = static_cast<unsigned char*>(arena_dev);
+  sv->arena_bytes = arena_bytes;
+  sv->used = 0;
+  sv->scratch_budget = scratch_budget_bytes;
+  sv->scratch_used = 0;
+  sv->ticks_per_sync = ticks_per_sync;
+  sv->use_graph = use_graph;
+  if (hipStreamCreateWithFlags(&sv->setup, hipStreamNonBlocking) != hipSuccess) {
+    delete sv;
+    return fail(SPFF_E_DEVICE, "stream creation failed");
+  }
+  *out = sv;
+  return SPFF_OK;
+}
+
+spff_status spff_server_register(spff_server* sv, const spff_config* cfg, const void* E_dev, int32_t* id) {
+  if (!sv || !cfg || !E_dev || !id) return fail(SPFF_E_INVALID, "NULL argument");
+  spff_status st = check_config(cfg);
+  if (st != SPFF_OK) return st;
+  const size_t rsize = cfg->precision == SPFF_FP64 ? 8 : 4;
+  const size_t rb = rsize * (size_t)cfg->nx * cfg->ny;
+  int c = -1;
+  for (size_t k = 0; k < sv->classes.size(); ++k)
+    if (sv->classes[k].nx == cfg->nx && sv->classes[k].ny == cfg->ny && sv->classes[k].precision == cfg->precision)
+      c = (int)k;
+  const size_t used0 = sv->used;
+  SrvProblem P;
+  P.cfg = *cfg;
+  P.E = arena_take(sv, rb);
+  P.phi = arena_take(sv, rb);
+  P.phi_ref = arena_take(sv, rb);
+  P.eps = arena_take(sv, 3 * rb);
+  unsigned char* bad = arena_take(sv, 64);
+  if (!P.E || !P.phi || !P.phi_ref || !P.eps || !bad) {
+    sv->used = used0;
+    return fail(SPFF_E_NOMEM, "arena full");
+  }
+  HIP_TRY(hipMemcpyAsync(P.E, E_dev, rb, hipMemcpyDeviceToDevice, sv->setup));
+  HIP_TRY(hipMemsetAsync(P.phi, 0, rb, sv->setup));
+  HIP_TRY(hipMemsetAsync(P.phi_ref, 0, rb, sv->setup));
+  HIP_TRY(hipMemsetAsync(P.eps, 0, 3 * rb, sv->setup));
+  HIP_TRY(hipMemsetAsync(bad, 0, 64, sv->setup));
+  const size_t n = (size_t)cfg->nx * cfg->ny;
+  hipError_t e = cfg->precision == SPFF_FP64
+                     ? launch_validate<double>(reinterpret_cast<const double*>(P.E), n, 0.0, -1e300, 1e300,
+                                               reinterpret_cast<unsigned int*>(bad), sv->setup)
+                     : launch_validate<float>(reinterpret_cast<const float*>(P.E), n, 0.0, -1e300, 1e300,
+                                              reinterpret_cast<unsigned int*>(bad), sv->setup);
+  if (e != hipSuccess) return fail(SPFF_E_DEVICE, "validation launch failed: %s", hipGetErrorString(e));
+  unsigned int hbad = 0;
+  HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, sv->setup));
+  HIP_TRY(hipStreamSynchronize(sv->setup));
+  if (hbad) {
+    sv->used = used0;
+    return fail(SPFF_E_INVALID, "E has %u non-positive or non-finite entries", hbad);
+  }
+  if (c < 0) {
+    SrvClass C;
+    C.nx = cfg->nx;
+    C.ny = cfg->ny;
+    C.precision = cfg->precision;
+    sv->classes.push_back(C);
+    c = (int)sv->classes.size() - 1;
+  }
+  P.cls = c;
+  sv->probs.push_back(P);
+  *id = (int32_t)sv->probs.size() - 1;
+  sv->classes[c].members.push_back(*id);
+  return SPFF_OK;
+}
+
+spff_status spff_server_submit(spff_server* sv, int32_t id, const double eps_bar[3], uint64_t* ticket) {
+  if (!sv || !eps_bar || !ticket) return fail(SPFF_E_INVALID, "NULL argument");
+  if (id < 0 || id >= (int32_t)sv->probs.size()) return fail(SPFF_E_INVALID, "unknown problem id");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(eps_bar[k])) return fail(SPFF_E_INVALID, "eps_bar must be finite");
+  SrvProblem& P = sv->probs[id];
+  SrvRequest rq;
+  rq.ticket = sv->next_ticket++;
+  for (int k = 0; k < 3; ++k) rq.eb[k] = eps_bar[k];
+  rq.t_submit = now_ms();
+  const bool was_idle = !P.running && P.queue.empty();
+  P.queue.push_back(rq);
+  if (was_idle) sv->classes[P.cls].ready.push_back(id);
+  sv->live[rq.ticket] = id;
+  *ticket = rq.ticket;
+  return SPFF_OK;
+}
+
+spff_status spff_server_progress(spff_server* sv, int32_t max_rounds, int32_t* completed, int32_t* pending) {
+  if (!sv) return fail(SPFF_E_INVALID, "server is NULL");
+  int done_count = 0;
+  for (int round = 0; round < max_rounds; ++round) {
+    bool any = false;
+    // 1. admit and launch, class by class (each on its own stream)
+    for (size_t c = 0; c < sv->classes.size(); ++c) {
+      SrvClass& C = sv->classes[c];
+      if (C.ready.empty() && (!C.eng || std::all_of(C.owner.begin(), C.owner.end(), [](int o) { return o < 0; })))
+        continue;
+      if (!C.eng) {
+        spff_status st = class_start(sv, (int)c);
+        if (st != SPFF_OK) return st;
+      }
+      spff_problem* e = C.eng;
+      bool dirty = false;
+      for (int s = 0; s < e->S && !C.ready.empty(); ++s) {
+        if (C.owner[s] >= 0) continue;
+        const int id = C.ready.front();
+        C.ready.pop_front();
+        spff_status st = class_admit(sv, C, s, id);
+        if (st != SPFF_OK) return st;
+        dirty = true;
+      }
+      if (dirty)
+        HIP_TRY(hipMemcpyAsync(e->d_ctl(), e->host_ctl, sizeof(SlotCtl) * e->S, hipMemcpyHostToDevice, C.stream));
+      bool launched;
+      int k;
+      spff_status st = launch_block(e, &launched, &k);
+      if (st != SPFF_OK) return st;
+      if (!launched) continue;
+      HIP_TRY(hipMemcpyAsync(e->host_ctl, e->d_ctl(), sizeof(SlotCtl) * e->S, hipMemcpyDeviceToHost, C.stream));
+      HIP_TRY(hipEventRecord(C.done_ev, C.stream));
+      C.inflight = true;
+      any = true;
+    }
+    if (!any) break;
+    // 2. collect finished requests
+    const double t = now_ms();
+    for (SrvClass& C : sv->classes) {
+      if (!C.inflight) continue;
+      HIP_TRY(hipEventSynchronize(C.done_ev));
+      C.inflight = false;
+      spff_problem* e = C.eng;
+      for (int s = 0; s < e->S; ++s) {
+        const int id = C.owner[s];
+        if (id < 0 || e->host_ctl[s].phase != PH_IDLE) continue;
+        SrvProblem& P = sv->probs[id];
+        spff_step_stats o;
+        fill_stats(e, e->host_ctl[s], o, t - P.t_submit);
+        sv->done[P.ticket] = o;
+        sv->live.erase(P.ticket);
+        P.running = false;
+        C.owner[s] = -1;
+        ++done_count;
+        if (!P.queue.empty()) C.ready.push_back(id);
+      }
+    }
+  }
+  if (completed) *completed = done_count;
+  if (pending) *pending = (int32_t)sv->live.size();
+  return SPFF_OK;
+}
+
+spff_status spff_server_poll(spff_server* sv, uint64_t ticket, spff_step_stats* out) {
+  if (!sv) return fail(SPFF_E_INVALID, "server is NULL");
+  auto it = sv->done.find(ticket);
+  if (it == sv->done.end()) {
+    if (sv->live.count(ticket)) return SPFF_E_BUSY;
+    return fail(SPFF_E_INVALID, "unknown ticket");
+  }
+  if (out) *out = it->second;
+  sv->done.erase(it);
+  return SPFF_OK;
+}
+
+spff_status spff_server_get_fields(spff_server* sv, int32_t id, uint32_t mask, void* const* dst) {
+  if (!sv) return fail(SPFF_E_INVALID, "server is NULL");
+  if (id < 0 || id >= (int32_t)sv->probs.size()) return fail(SPFF_E_INVALID, "unknown problem id");
+  if (mask & ~(uint32_t)(SPFF_FIELD_PHI | SPFF_FIELD_PHI_REF | SPFF_FIELD_EPS_STAR))
+    return fail(SPFF_E_INVALID, "only phi, phi_ref and eps* are resident fields");
+  SrvProblem& P = sv->probs[id];
+  if (P.running || !P.queue.empty()) return fail(SPFF_E_BUSY, "problem has pending requests");
+  const size_t rb = (P.cfg.precision == SPFF_FP64 ? 8 : 4) * (size_t)P.cfg.nx * P.cfg.ny;
+  int k = 0;
+  if (mask && !dst) return fail(SPFF_E_INVALID, "dst is NULL");
+  if (mask & SPFF_FIELD_PHI) HIP_TRY(hipMemcpyAsync(dst[k++], P.phi, rb, hipMemcpyDeviceToDevice, sv->setup));
+  if (mask & SPFF_FIELD_PHI_REF)
+    HIP_TRY(hipMemcpyAsync(dst[k++], P.phi_ref, rb, hipMemcpyDeviceToDevice, sv->setup));
+  if (mask & SPFF_FIELD_EPS_STAR)
+    HIP_TRY(hipMemcpyAsync(dst[k++], P.eps, 3 * rb, hipMemcpyDeviceToDevice, sv->setup));
+  HIP_TRY(hipStreamSynchronize(sv->setup));
+  return SPFF_OK;
+}
+
+spff_status spff_server_info(const spff_server* sv, int32_t* nclasses, int32_t* total_slots, size_t* arena_used) {
+  if (!sv) return fail(SPFF_E_INVALID, "server is NULL");
+  int slots = 0;
+  for (const SrvClass& C : sv->classes) slots += C.eng ? C.eng->S : 0;
+  if (nclasses) *nclasses = (int32_t)sv->classes.size();
+  if (total_slots) *total_slots = slots;
+  if (arena_used) *arena_used = sv->used;
+  return SPFF_OK;
+}
+
+spff_status spff_server_destroy(spff_server* sv) {
+  if (!sv) return SPFF_OK;
+  for (SrvClass& C : sv->classes) {
+    if (C.stream) (void)hipStreamSynchronize(C.stream);
+    if (C.eng) spff_destroy_problem(C.eng);
+    if (C.done_ev) (void)hipEventDestroy(C.done_ev);
+    if (C.stream) (void)hipStreamDestroy(C.stream);
+  }
+  if (sv->setup) (void)hipStreamDestroy(sv->setup);
+  delete sv;
+  return SPFF_OK;
+}
 
 }  // extern "C"

@@ -961,13 +961,13 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
                        double* prof, hipEvent_t* ev, hipStream_t st) {
   dim3 grow(G.ngr, G.S), gcol(G.ngc, G.S);
   if (ev) (void)hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL(k_rowfwd<real>, grow, dim3(THREADS), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, G.nx,
+  hipLaunchKernelGGL(k_rowfwd<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, G.nx,
                      G.ny, G.R, G.ngr);
   if (ev) (void)hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL(k_col<real>, gcol, dim3(THREADS), G.lds_col, st, list, ptrs, prms, ctls, twy, pcol, G.nx,
+  hipLaunchKernelGGL(k_col<real>, gcol, dim3(G.threads), G.lds_col, st, list, ptrs, prms, ctls, twy, pcol, G.nx,
                      G.ny, G.W, G.ngc);
   if (ev) (void)hipEventRecord(ev[2], st);
-  hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(THREADS), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, pinv,
+  hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, pinv,
                      G.nx, G.ny, G.R, G.ngr);
   if (ev) (void)hipEventRecord(ev[3], st);
   hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(64), 0, st, list, prms, ctls, prow, pcol, pinv, prof, G.nx,

@@ -15,6 +15,7 @@ struct LaunchGeom {
   int nx, ny, S;
   int R, ngr;  // rows per row work-group, row groups per slot
   int W, ngc;  // columns per column work-group, column groups per slot
+  int threads;  // threads per FFT work-group
   size_t lds_row, lds_col;
 };
 

@@ -51,7 +51,8 @@ class Config(ctypes.Structure):
         ("tol_pf", ctypes.c_double), ("tol_abs_pf", ctypes.c_double), ("tol_am", ctypes.c_double),
         ("max_cg", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("max_bccg", ctypes.c_int32),
         ("max_am", ctypes.c_int32), ("ticks_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-        ("floor_factor", ctypes.c_double), ("stall_iters", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("floor_factor", ctypes.c_double), ("stall_iters", ctypes.c_int32),
+        ("plan_rows", ctypes.c_int32), ("plan_cols", ctypes.c_int32), ("plan_threads", ctypes.c_int32),
     ]
 
 
@@ -105,6 +106,18 @@ _SIGS = {
     "spff_apply_operator": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     "spff_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "spff_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(Profile)]),
+    "spff_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(_P)]),
+    "spff_server_register": (ctypes.c_int, [_P, ctypes.POINTER(Config), _P, ctypes.POINTER(ctypes.c_int32)]),
+    "spff_server_submit": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "spff_server_progress": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "spff_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(StepStats)]),
+    "spff_server_get_fields": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(_P)]),
+    "spff_server_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "spff_server_destroy": (ctypes.c_int, [_P]),
     "spff_problem_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "spff_destroy_problem": (ctypes.c_int, [_P]),
@@ -322,3 +335,78 @@ class Problem:
             eb = np.ascontiguousarray(np.broadcast_to(np.asarray(eps_bar, np.float64), (self.B, 3)))
             ebp = eb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         _check(lib().spff_set_state(self.handle, ctypes.c_void_p(state.data_ptr()), ebp))
+
+
+class Server:
+    """Continuous-batching server over resident problems (spff_server_*).
+
+    arena_bytes of device memory are allocated once with torch; the library
+    sub-allocates resident state and class engines from it."""
+
+    def __init__(self, arena_bytes, scratch_budget_bytes=0, ticks_per_sync=8, use_graph=1, device="cuda:0"):
+        torch = _torch()
+        self.device = torch.device(device)
+        self._arena, ptr = _aligned_workspace(int(arena_bytes), self.device)
+        h = ctypes.c_void_p()
+        _check(lib().spff_server_create(ctypes.c_void_p(ptr), int(arena_bytes), int(scratch_budget_bytes),
+                                        int(ticks_per_sync), int(use_graph), ctypes.byref(h)))
+        self.handle = h
+        self.cfgs = []
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().spff_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def register(self, cfg, E):
+        """spff_server_register: E device tensor [ny, nx] of the config's real type."""
+        E = E.to(device=self.device, dtype=_real_dtype(cfg)).contiguous()
+        out = ctypes.c_int32()
+        _check(lib().spff_server_register(self.handle, ctypes.byref(cfg), ctypes.c_void_p(E.data_ptr()),
+                                          ctypes.byref(out)))
+        self.cfgs.append(cfg)
+        return out.value
+
+    def submit(self, pid, eps_bar):
+        eb = (ctypes.c_double * 3)(*[float(v) for v in eps_bar])
+        t = ctypes.c_uint64()
+        _check(lib().spff_server_submit(self.handle, int(pid), eb, ctypes.byref(t)))
+        return t.value
+
+    def progress(self, max_rounds=1):
+        c, p = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().spff_server_progress(self.handle, int(max_rounds), ctypes.byref(c), ctypes.byref(p)))
+        return c.value, p.value
+
+    def poll(self, ticket):
+        """Stats dict when done, None while pending."""
+        out = StepStats()
+        st = lib().spff_server_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(out))
+        if st == E_BUSY:
+            return None
+        _check(st)
+        return out.to_dict()
+
+    def get_fields(self, pid, mask):
+        torch = _torch()
+        cfg = self.cfgs[pid]
+        outs, ptrs = {}, []
+        for bit in (FIELD_PHI, FIELD_PHI_REF, FIELD_EPS_STAR):
+            if mask & bit:
+                t = torch.empty((FIELD_PLANES[bit], cfg.ny, cfg.nx), dtype=_real_dtype(cfg), device=self.device)
+                outs[FIELD_NAMES[bit]] = t
+                ptrs.append(t.data_ptr())
+        arr = (ctypes.c_void_p * max(1, len(ptrs)))(*ptrs)
+        _check(lib().spff_server_get_fields(self.handle, int(pid), int(mask), arr))
+        return outs
+
+    def info(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check(lib().spff_server_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"classes": a.value, "slots": b.value, "arena_used": c.value}

@@ -1,0 +1,128 @@
+"""GPU: continuous-batching server.  Each result is the same alone and in
+the mix (bitwise with fixed launch plans, within the FP32 contract without),
+admission respects the scratch budget, requests of one problem run in order."""
+
+import numpy as np
+import pytest
+
+import spff_inputs as si
+from gpu_common import device
+from paper_2203_16467_amd import serving, spff
+
+pytestmark = pytest.mark.gpu
+
+PLAN = dict(plan_rows=2, plan_cols=1, plan_threads=256)
+
+
+def _problems():
+    """(cfg kwargs, E) for a small mixed population: two grid sizes, AT1 and
+    AT2, different seeds."""
+    out = []
+    for i, (n, at) in enumerate([(64, 1), (64, 2), (128, 1), (64, 1), (128, 2), (64, 2)]):
+        E = si.young_modulus(n, 4.0 if n == 64 else 8.0, 0.2, 4000 + i)
+        out.append((dict(nx=n, ny=n, at=at), E))
+    return out
+
+
+def _ramp(n_steps=4, first=8):
+    return si.uniaxial_ramp(20, 0.2, 2.0)[first:first + n_steps]
+
+
+def _alone(kw, E, ramp, plan):
+    import torch
+    cfg = spff.default_config(**kw, **plan)
+    p = spff.Problem(torch.as_tensor(E, device=device()), cfg)
+    stats = [p.load_step(eb)[1][0] for eb in ramp]
+    f = p.get_fields(spff.FIELD_PHI | spff.FIELD_EPS_STAR, 0)
+    out = {k: v.double().cpu().numpy() for k, v in f.items()}
+    p.close()
+    return stats, out
+
+
+@pytest.mark.parametrize("fixed_plan", [True, False])
+def test_alone_equals_mix(fixed_plan):
+    import torch
+    plan = PLAN if fixed_plan else {}
+    probs = _problems()
+    ramp = _ramp()
+    # scratch for about two slots per class: forces queueing and admission
+    sv = spff.Server(arena_bytes=256 << 20, scratch_budget_bytes=3 * (128 * 128 * 48 + 64 * 64 * 48) * 2,
+                     ticks_per_sync=4, use_graph=1)
+    ids = [sv.register(spff.default_config(**kw, **plan), torch.as_tensor(E, device=device())) for kw, E in probs]
+    # interleaved submissions: step k of every problem before step k+1
+    tickets = {i: [] for i in ids}
+    for k in range(len(ramp)):
+        for i in ids:
+            tickets[i].append(sv.submit(i, ramp[k]))
+    while True:
+        done, pending = sv.progress(4)
+        if pending == 0:
+            break
+    info = sv.info()
+    assert info["classes"] == 2 and info["slots"] >= 2
+    for i, (kw, E) in zip(ids, probs):
+        mix = [sv.poll(t) for t in tickets[i]]
+        assert all(m is not None for m in mix)
+        stats, alone = _alone(kw, E, ramp, plan)
+        f = sv.get_fields(i, spff.FIELD_PHI | spff.FIELD_EPS_STAR)
+        phi = f["phi"].double().cpu().numpy()[0]
+        eps = f["eps_star"].double().cpu().numpy()
+        assert phi.shape == alone["phi"][0].shape and eps.shape == alone["eps_star"].shape
+        if fixed_plan:
+            assert np.array_equal(phi, alone["phi"][0]), (i, np.abs(phi - alone["phi"][0]).max())
+            assert np.array_equal(eps, alone["eps_star"]), i
+            for a, b in zip(mix, stats):
+                assert (a["cg_iters"], a["bccg_iters"], a["am_iters"]) == \
+                    (b["cg_iters"], b["bccg_iters"], b["am_iters"])
+        else:
+            assert np.abs(phi - alone["phi"][0]).max() <= 1e-3
+            assert np.linalg.norm(eps - alone["eps_star"]) <= 1e-4 * np.linalg.norm(alone["eps_star"]) + 1e-12
+    sv.close()
+
+
+def test_requests_of_one_problem_run_in_order_and_poll_semantics():
+    import torch
+    kw, E = _problems()[1]
+    sv = spff.Server(arena_bytes=64 << 20, ticks_per_sync=2)
+    pid = sv.register(spff.default_config(**kw), torch.as_tensor(E, device=device()))
+    ramp = _ramp(3)
+    ts = [sv.submit(pid, eb) for eb in ramp]
+    assert sv.poll(ts[-1]) is None  # pending
+    while sv.progress(8)[1] > 0:
+        pass
+    got = [sv.poll(t) for t in ts]
+    stats, _ = _alone(kw, E, ramp, {})
+    assert [g["sigma_bar"][1] for g in got] == pytest.approx([s["sigma_bar"][1] for s in stats], rel=1e-5)
+    with pytest.raises(spff.SpffError):
+        sv.poll(ts[0])  # already collected
+    with pytest.raises(spff.SpffError):
+        sv.poll(10 ** 9)
+    sv.close()
+
+
+def test_register_validates_and_arena_bounds():
+    import torch
+    sv = spff.Server(arena_bytes=1 << 20)
+    E = np.ones((64, 64), np.float32)
+    E[1, 1] = 0.0
+    with pytest.raises(spff.SpffError) as ei:
+        sv.register(spff.default_config(nx=64, ny=64), torch.as_tensor(E, device=device()))
+    assert ei.value.status == spff.E_INVALID
+    with pytest.raises(spff.SpffError) as ei:
+        sv.register(spff.default_config(nx=512, ny=512), torch.ones((512, 512), device=device()))
+    assert ei.value.status == spff.E_NOMEM
+    sv.close()
+
+
+def test_poisson_driver_smoke():
+    import torch
+    sv = spff.Server(arena_bytes=128 << 20, ticks_per_sync=4)
+    ramps = {}
+    for kw, E in _problems()[:4]:
+        pid = sv.register(spff.default_config(**kw), torch.as_tensor(E, device=device()))
+        ramps[pid] = si.uniaxial_ramp(20, 0.2, 2.0)
+    rate, lat, wall, _ = serving.run_closed(sv, ramps, 2)
+    assert rate > 0 and len(lat) == 8
+    thr, lat2, offered = serving.run_poisson(sv, ramps, 2, rate=0.5 * rate, n_requests=12, seed=1)
+    assert len(lat2) == 12 and thr > 0
+    sv.close()
