@@ -19,6 +19,9 @@ Also reported on the same line:
                 (HIP events on the solver stream during the timed steps)
   plain_gpu     the plain single-instance path (256x256, one problem,
                 host check after every tick) over its full 200-step ramp
+  serving       continuous batching of load-step requests over resident
+                problems of mixed grid sizes: saturation rate, then p50/p99
+                latency and throughput under Poisson arrivals
   cpu_baseline  the FP64 NumPy oracle on one host core, on a bounded sample
 """
 
@@ -111,6 +114,54 @@ def plain_leg(args):
             "seconds": dt, "cg_iters": cg, "bccg_iters": pf}
 
 
+def serving_leg(args):
+    """Serving workload: resident microstructures with grid sizes drawn
+    uniformly from {128, 256, 512, 1024}^2, AT1/AT2 half and half, requests =
+    the next load step of a problem's 200-step ramp; closed-loop saturation
+    run, then Poisson arrivals at fractions of the saturation rate."""
+    import numpy as np
+    import torch
+
+    import spff_inputs as si
+    from paper_2203_16467_amd import serving, spff
+
+    rng = np.random.default_rng(4000)
+    sizes = rng.choice([128, 256, 512, 1024], size=args.serve_problems)
+    ats = np.arange(args.serve_problems) % 2 + 1
+    sv = spff.Server(arena_bytes=int(args.serve_arena_gb * (1 << 30)),
+                     scratch_budget_bytes=int(args.serve_scratch_gb * (1 << 30)), ticks_per_sync=8, use_graph=1)
+    ramps = {}
+    t = time.time()
+    for i, (n, at) in enumerate(zip(sizes, ats)):
+        E = si.young_modulus(int(n), 8.0, 0.1, 4000 + i)
+        pid = sv.register(spff.default_config(nx=int(n), ny=int(n), at=int(at)), torch.as_tensor(E, device="cuda:0"))
+        ramps[pid] = si.uniaxial_ramp(200, 0.2, 2.0)
+    info = sv.info()
+    log(f"[bench] serving: registered {len(ramps)} problems in {time.time() - t:.1f}s")
+    # saturation: two steps of every problem submitted at once
+    sat, lat0, wall0, res0 = serving.run_closed(sv, ramps, 2)
+    info = sv.info()
+    log(f"[bench] serving: saturation {sat:.1f} req/s ({len(lat0)} requests in {wall0:.1f}s), "
+        f"{info['slots']} slots in {info['classes']} classes")
+    loads = []
+    for k, f in enumerate(args.serve_loads):
+        thr, lat, offered = serving.run_poisson(sv, ramps, 2, rate=f * sat, n_requests=args.serve_requests,
+                                                seed=k, warmup=max(10, args.serve_requests // 20))
+        lat = np.asarray(lat)
+        loads.append({"load": f, "offered_req_per_s": offered, "throughput_req_per_s": thr,
+                      "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                      "requests": int(lat.size)})
+        log(f"[bench] serving load {f}: {thr:.1f} req/s, p50 {loads[-1]['p50_ms']:.1f} ms, "
+            f"p99 {loads[-1]['p99_ms']:.1f} ms")
+    sv.close()
+    return {"workload": f"serving: {args.serve_problems} resident problems, grid uniform over "
+                        f"{{128,256,512,1024}}^2 (E = max(1+0.1z,0.5), corr 8 px), AT1/AT2 alternating, "
+                        f"strain-spectral, crack set; request = next load step of the problem's 200-step ramp; "
+                        f"scratch budget {args.serve_scratch_gb:g} GB (admission by footprint)",
+            "saturation_req_per_s": sat, "slots": info["slots"], "classes": info["classes"],
+            "loads": loads}
+
+
 def cpu_leg(res, budget_s):
     """The FP64 oracle on one host core, realization 0 of the workload, for as
     many load steps as fit the budget (at least one)."""
@@ -161,6 +212,12 @@ def main():
     ap.add_argument("--no-plain", dest="plain", action="store_false")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-serving", dest="serving", action="store_false")
+    ap.add_argument("--serve-problems", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
+    ap.add_argument("--serve-arena-gb", type=float, default=8.0)
+    ap.add_argument("--serve-scratch-gb", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs one process on one MI355X "
@@ -201,6 +258,7 @@ def main():
         "breakdown": {"cg_iters": res["cg"], "bccg_iters": res["pf"], "seconds": res["dt"],
                       "realizations_cracked": res["ncrack"], "status": res["status"],
                       "kernel_ms": prof["kernel_ms"], "kernel_launches": prof["launches"],
+                      "kernel_alg_bytes": prof["alg_bytes"],
                       "alg_GBs_all_fft_kernels": all_b / (all_ms * 1e-3) / 1e9 if all_ms > 0 else None},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
@@ -209,6 +267,8 @@ def main():
         pl = plain_leg(args)
         out["plain_gpu"] = pl
         out["vs_plain"] = value / pl["value"]
+    if args.serving:
+        out["serving"] = serving_leg(args)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_leg(res, args.cpu_budget)
     print(json.dumps(out), flush=True)

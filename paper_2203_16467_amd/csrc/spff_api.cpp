@@ -52,7 +52,7 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 inline bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 struct Layout {
-  size_t ctl, prm, ptr, twx, twy, prow, pcol, pinv, list, bad, prof;
+  size_t ctl, prm, ptr, twx, twy, prow, pcol, pinv, list, bad, prof, seq, rec, kt, ktsum;
   size_t slot0, slot_bytes;
   // offsets inside a slot
   size_t E, phi, phi_ref, eps, theta, rm, pm, spec;
@@ -146,6 +146,10 @@ Layout layout(const spff_config* c, int S, size_t rsize, bool scratch_only = fal
   L.list = take(sizeof(int32_t) * S);
   L.bad = take(64);
   L.prof = take(sizeof(double) * 3 * S);
+  L.seq = take(sizeof(SlotSeq) * S);
+  L.kt = take(sizeof(KTime) * 4);
+  L.ktsum = take(sizeof(unsigned long long) * 4);
+  L.rec = take(sizeof(StepRec) * SEQ_MAX * S);
   L.slot0 = off;
   size_t so = 0;
   auto stake = [&](size_t bytes) {
@@ -193,8 +197,6 @@ struct spff_problem {
   std::vector<SlotPtr<double>> host_ptrs;  // layout-identical for float and double
   // profiling
   bool prof_on = false;
-  std::vector<hipEvent_t> events;  // 5 per tick of a block
-  double kernel_ms[4] = {0, 0, 0, 0};
   int64_t launches[4] = {0, 0, 0, 0};
   int64_t prof_ticks = 0;
 
@@ -203,6 +205,11 @@ struct spff_problem {
   void* d_ptr() const { return ws + L.ptr; }
   double* d_prof() const { return reinterpret_cast<double*>(ws + L.prof); }
   int32_t* d_list() const { return reinterpret_cast<int32_t*>(ws + L.list); }
+  SlotSeq* d_seq() const { return reinterpret_cast<SlotSeq*>(ws + L.seq); }
+  StepRec* d_rec() const { return reinterpret_cast<StepRec*>(ws + L.rec); }
+  KTime* d_kt() const { return reinterpret_cast<KTime*>(ws + L.kt); }
+  unsigned long long* d_ktsum() const { return reinterpret_cast<unsigned long long*>(ws + L.ktsum); }
+  double clock_khz = 0.0;
   unsigned char* slot(int s) const { return ws + L.slot0 + (size_t)s * L.slot_bytes; }
   size_t n() const { return (size_t)cfg.nx * cfg.ny; }
 };
@@ -210,42 +217,33 @@ struct spff_problem {
 namespace {
 
 template <typename real>
-hipError_t enqueue_tick(spff_problem* p, hipStream_t st, int i, int b) {
+hipError_t enqueue_tick(spff_problem* p, hipStream_t st, int b) {
   using C = typename HostCplx<real>::type;
-  hipEvent_t* ev = (p->prof_on && (size_t)(5 * i + 5) <= p->events.size()) ? &p->events[5 * i] : nullptr;
   return launch_tick<real>(p->geoms[b], p->d_list(), reinterpret_cast<const SlotPtr<real>*>(p->d_ptr()),
                            p->d_prm(), p->d_ctl(),
                            reinterpret_cast<const C*>(p->ws + p->L.twx),
                            reinterpret_cast<const C*>(p->ws + p->L.twy),
                            reinterpret_cast<double*>(p->ws + p->L.prow),
                            reinterpret_cast<double*>(p->ws + p->L.pcol),
-                           reinterpret_cast<double*>(p->ws + p->L.pinv), p->prof_on ? p->d_prof() : nullptr, ev,
-                           st);
+                           reinterpret_cast<double*>(p->ws + p->L.pinv), p->prof_on ? p->d_prof() : nullptr,
+                           p->d_seq(), p->d_rec(), p->prof_on ? p->d_kt() : nullptr,
+                           p->prof_on ? p->d_ktsum() : nullptr, st);
 }
 
 hipError_t enqueue_ticks(spff_problem* p, int k, hipStream_t st, int b) {
   for (int i = 0; i < k; ++i) {
-    hipError_t e =
-        p->cfg.precision == SPFF_FP64 ? enqueue_tick<double>(p, st, i, b) : enqueue_tick<float>(p, st, i, b);
+    hipError_t e = p->cfg.precision == SPFF_FP64 ? enqueue_tick<double>(p, st, b) : enqueue_tick<float>(p, st, b);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-// After a synchronised block of k ticks: fold the event times into the
-// profile totals.
+// After a synchronised block of k ticks: count the launches (the kernel
+// times are accumulated on the device).
 void collect_profile(spff_problem* p, int k) {
   if (!p->prof_on) return;
-  for (int i = 0; i < k && (size_t)(5 * i + 5) <= p->events.size(); ++i) {
-    for (int j = 0; j < 4; ++j) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, p->events[5 * i + j], p->events[5 * i + j + 1]) == hipSuccess) {
-        p->kernel_ms[j] += ms;
-        p->launches[j] += 1;
-      }
-    }
-    p->prof_ticks += 1;
-  }
+  for (int j = 0; j < 4; ++j) p->launches[j] += k;
+  p->prof_ticks += k;
 }
 
 spff_status build_graph(spff_problem* p, int b) {
@@ -256,10 +254,7 @@ spff_status build_graph(spff_problem* p, int b) {
   }
   if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-  const bool prof = p->prof_on;
-  p->prof_on = false;  // event timings are taken from eager launches only
   hipError_t e = enqueue_ticks(p, K, p->cap_stream, b);
-  p->prof_on = prof;
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
   if (e != hipSuccess) return fail(SPFF_E_DEVICE, "tick capture failed: %s", hipGetErrorString(e));
@@ -311,7 +306,7 @@ spff_status launch_block(spff_problem* p, bool* launched, int* nticks) {
   spff_status st = set_list(p, active, b);
   if (st != SPFF_OK) return st;
   const int K = p->cfg.ticks_per_sync;
-  if (p->cfg.use_graph && !p->prof_on) {
+  if (p->cfg.use_graph) {
     if (!p->graphs[b]) {
       st = build_graph(p, b);
       if (st != SPFF_OK) return st;
@@ -423,6 +418,7 @@ spff_status init_device(spff_problem* p, const void* E_dev, const void* phi_init
   // the synchronous twiddle staging buffer is reused: wait for the copies
   HIP_TRY(hipStreamSynchronize(p->stream));
 
+  HIP_TRY(hipMemsetAsync(p->d_seq(), 0, sizeof(SlotSeq) * p->S, p->stream));
   if (p->scratch_only) {
     for (int s = 0; s < p->S; ++s) {
       unsigned char* b = p->slot(s);
@@ -655,12 +651,35 @@ spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps
   for (size_t i = 0; i < (size_t)3 * p->S * nsteps; ++i)
     if (!std::isfinite(eps_bar[i])) return fail(SPFF_E_INVALID, "eps_bar must be finite");
   const int S = p->S;
-  std::vector<int> next(S, 0);
-  std::vector<double> t0(S, 0.0);
-  const double tstart = now_ms();
+  if (p->clock_khz <= 0.0) {
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    p->clock_khz = khz > 0 ? (double)khz : 1e5;
+  }
+  // Steps are handed to the device in chunks of at most SEQ_MAX per slot; the
+  // controller chains the steps of a chunk on the device.
+  std::vector<int> next(S, 0);      // first step of the slot's current chunk
+  std::vector<int> clen(S, 0);      // length of the slot's current chunk
+  std::vector<SlotSeq> q(1);
+  std::vector<StepRec> rec(SEQ_MAX);
+  auto upload_chunk = [&](int s) -> spff_status {
+    const int len = std::min(SEQ_MAX, nsteps - next[s]);
+    SlotSeq& h = q[0];
+    h.len = len;
+    h.pos = 0;
+    for (int k = 0; k < len; ++k)
+      for (int c = 0; c < 3; ++c) h.eps_bar[k][c] = eps_bar[3 * ((size_t)s * nsteps + next[s] + k) + c];
+    HIP_TRY(hipMemcpyAsync(p->d_seq() + s, &h, sizeof(SlotSeq), hipMemcpyHostToDevice, p->stream));
+    // the staging struct is reused for the next slot: wait for this copy
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    clen[s] = len;
+    start_step(p, s, h.eps_bar[0]);
+    return SPFF_OK;
+  };
   for (int s = 0; s < S; ++s) {
-    start_step(p, s, eps_bar + 3 * (size_t)s * nsteps);
-    t0[s] = tstart;
+    spff_status st = upload_chunk(s);
+    if (st != SPFF_OK) return st;
   }
   HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * S, hipMemcpyHostToDevice, p->stream));
   spff_status worst = SPFF_OK;
@@ -674,23 +693,59 @@ spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps
     HIP_TRY(hipMemcpyAsync(p->host_ctl, p->d_ctl(), cbytes, hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
     collect_profile(p, k);
-    const double t = now_ms();
     bool dirty = false;
     for (int s = 0; s < S; ++s) {
-      if (next[s] >= nsteps || p->host_ctl[s].phase != PH_IDLE) continue;
-      const SlotCtl& c = p->host_ctl[s];
-      const spff_status ss = slot_status(c);
-      if (ss < 0 && (worst >= 0 || ss < worst)) worst = ss;
-      if (ss > 0 && worst == SPFF_OK) worst = ss;
-      if (stats) fill_stats(p, c, stats[(size_t)s * nsteps + next[s]], t - t0[s]);
-      for (int k = 0; k < 3; ++k) p->last_eps_bar[3 * s + k] = c.eps_bar[k];
-      ++next[s];
-      if (next[s] < nsteps && ss >= 0) {
-        start_step(p, s, eps_bar + 3 * ((size_t)s * nsteps + next[s]));
-        t0[s] = t;
+      if (clen[s] == 0 || p->host_ctl[s].phase != PH_IDLE) continue;
+      // the slot's chunk has ended (all steps done, or a step failed)
+      HIP_TRY(hipMemcpyAsync(rec.data(), p->d_rec() + (size_t)s * SEQ_MAX, sizeof(StepRec) * clen[s],
+                             hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipMemcpyAsync(&q[0], p->d_seq() + s, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      const int done = q[0].pos;
+      bool failed = done < clen[s];
+      for (int j = 0; j < done; ++j) {
+        const StepRec& r = rec[j];
+        SlotCtl c{};
+        c.am = r.am;
+        c.newton = r.newton;
+        c.cg = r.cg;
+        c.bccg = r.bccg;
+        c.ticks = r.ticks;
+        c.status = r.status;
+        c.flags = r.flags;
+        c.dphi = r.dphi;
+        c.mech_res = r.mech_res;
+        c.pf_res = r.pf_res;
+        c.F_e = r.F_e;
+        c.F_f = r.F_f;
+        for (int m = 0; m < 3; ++m) {
+          c.sbar[m] = r.sbar[m];
+          c.eps_bar[m] = r.eps_bar[m];
+        }
+        c.phi_sum = r.phi_sum;
+        c.phi_max = r.phi_max;
+        c.crack_px = r.crack_px;
+        const spff_status ss = slot_status(c);
+        if (ss < 0 && (worst >= 0 || ss < worst)) worst = ss;
+        if (ss > 0 && worst == SPFF_OK) worst = ss;
+        if (ss < 0) failed = true;
+        const double ms = (double)(r.t_end - r.t_start) / p->clock_khz;
+        if (stats) fill_stats(p, c, stats[(size_t)s * nsteps + next[s] + j], ms);
+        for (int m = 0; m < 3; ++m) p->last_eps_bar[3 * s + m] = r.eps_bar[m];
+      }
+      if (done == 0 && p->host_ctl[s].status < 0) {
+        // failed before its record was written
+        const spff_status ss = (spff_status)p->host_ctl[s].status;
+        if (worst >= 0 || ss < worst) worst = ss;
+        failed = true;
+      }
+      next[s] += clen[s];
+      clen[s] = 0;
+      if (!failed && next[s] < nsteps) {
+        spff_status st = upload_chunk(s);
+        if (st != SPFF_OK) return st;
         dirty = true;
       } else {
-        if (ss < 0) next[s] = nsteps;  // a failed problem stops its sequence
         --remaining;
       }
     }
@@ -830,23 +885,21 @@ spff_status spff_apply_operator(spff_problem* p, int32_t op, const void* in_dev,
 spff_status spff_profile_enable(spff_problem* p, int32_t enable) {
   if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
   HIP_TRY(hipStreamSynchronize(p->stream));
-  const size_t need = 5 * (size_t)p->cfg.ticks_per_sync;
-  if (enable && p->events.size() < need) {
-    while (p->events.size() < need) {
-      hipEvent_t e;
-      HIP_TRY(hipEventCreate(&e));
-      p->events.push_back(e);
-    }
+  if (p->clock_khz <= 0.0) {
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    p->clock_khz = khz > 0 ? (double)khz : 1e5;
   }
   p->prof_on = enable != 0;
-  for (int j = 0; j < 4; ++j) {
-    p->kernel_ms[j] = 0.0;
-    p->launches[j] = 0;
-  }
+  for (int j = 0; j < 4; ++j) p->launches[j] = 0;
   p->prof_ticks = 0;
+  static const KTime init[4] = {{~0ull, 0ull}, {~0ull, 0ull}, {~0ull, 0ull}, {~0ull, 0ull}};
+  HIP_TRY(hipMemcpyAsync(p->d_kt(), init, sizeof(init), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemsetAsync(p->d_ktsum(), 0, sizeof(unsigned long long) * 4, p->stream));
   HIP_TRY(hipMemsetAsync(p->d_prof(), 0, sizeof(double) * 3 * p->S, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
-  // the byte counters are compiled into the captured blocks: recapture lazily
+  // the profiling buffers are compiled into the captured blocks: recapture lazily
   drop_graphs(p);
   return SPFF_OK;
 }
@@ -854,13 +907,15 @@ spff_status spff_profile_enable(spff_problem* p, int32_t enable) {
 spff_status spff_profile_read(spff_problem* p, spff_profile* out) {
   if (!p || !out) return fail(SPFF_E_INVALID, "NULL argument");
   std::vector<double> b(3 * (size_t)p->S);
+  unsigned long long ks[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(b.data(), p->d_prof(), sizeof(double) * b.size(), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(ks, p->d_ktsum(), sizeof(ks), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   std::memset(out, 0, sizeof(*out));
   for (int s = 0; s < p->S; ++s)
     for (int j = 0; j < 3; ++j) out->alg_bytes[j] += b[3 * s + j];
   for (int j = 0; j < 4; ++j) {
-    out->kernel_ms[j] = p->kernel_ms[j];
+    out->kernel_ms[j] = p->clock_khz > 0.0 ? (double)ks[j] / p->clock_khz : 0.0;
     out->launches[j] = p->launches[j];
   }
   out->ticks = p->prof_ticks;
@@ -884,7 +939,6 @@ spff_status spff_destroy_problem(spff_problem* p) {
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->host_ctl) (void)hipHostFree(p->host_ctl);
   if (p->host_list) (void)hipHostFree(p->host_list);
-  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   delete p;
   return SPFF_OK;
 }

@@ -33,17 +33,18 @@ __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
 // ---------------------------------------------------------------------------
 // Stockham autosort FFT on `ntrans` transforms of length M (power of two)
-// held in LDS, transform t at buf + t*stride.  Radix-4 passes, one radix-2
-// pass when log2 M is odd.  Pass with sub-transform size Ns and radix Rd:
+// held in LDS, transform t at buf + t*stride.  A pass with sub-transform size
+// Ns and radix Rd (2, 4 or 8):
 //   j in [0, M/Rd), k = j mod Ns
 //   v_r = x[j + r M/Rd] * w_{Ns Rd}^{r k}          (twiddle)
 //   v'  = DFT_Rd(v)
 //   y[(j - k) Rd + k + s Ns] = v'_s
 // Each pass reads its inputs into registers, synchronises, then writes in
 // place (chunks of whole transforms, at most T*MAXE elements per chunk).
-// tw holds the (M*twmul)-th roots of unity exp(-2 pi i e/(M twmul)); the
-// inverse transform (INV) uses their conjugates and is unnormalised.
-// Requires M <= blockDim.x * MAXE.
+// tw holds the (M*twmul)-th roots of unity exp(-2 pi i e/(M twmul)); a
+// butterfly loads w^k (and w^4k for radix 8) and forms the other powers by
+// products (at most three chained).  The inverse (INV) uses conjugates and is
+// unnormalised.  Requires M <= blockDim.x * MAXE.
 // ---------------------------------------------------------------------------
 template <bool INV, typename V>
 __device__ __forceinline__ void bfly4(V& v0, V& v1, V& v2, V& v3) {
@@ -55,103 +56,126 @@ __device__ __forceinline__ void bfly4(V& v0, V& v1, V& v2, V& v3) {
   v3 = csub(a1, a3);
 }
 
+// 8-point DFT in place (natural order in and out): two 4-point DFTs of the
+// even and odd inputs, combined with w8^s.
+template <bool INV, typename V>
+__device__ __forceinline__ void bfly8(V* v) {
+  using T = decltype(V::x);
+  const T h = T(0.70710678118654752440084436210485);
+  V a0 = v[0], a1 = v[2], a2 = v[4], a3 = v[6];
+  V b0 = v[1], b1 = v[3], b2 = v[5], b3 = v[7];
+  bfly4<INV>(a0, a1, a2, a3);
+  bfly4<INV>(b0, b1, b2, b3);
+  if (INV) {
+    b1 = mk<V>((b1.x - b1.y) * h, (b1.x + b1.y) * h);
+    b2 = cmuli(b2);
+    b3 = mk<V>(-(b3.x + b3.y) * h, (b3.x - b3.y) * h);
+  } else {
+    b1 = mk<V>((b1.x + b1.y) * h, (b1.y - b1.x) * h);
+    b2 = cmulni(b2);
+    b3 = mk<V>((b3.y - b3.x) * h, -(b3.x + b3.y) * h);
+  }
+  v[0] = cadd(a0, b0);
+  v[4] = csub(a0, b0);
+  v[1] = cadd(a1, b1);
+  v[5] = csub(a1, b1);
+  v[2] = cadd(a2, b2);
+  v[6] = csub(a2, b2);
+  v[3] = cadd(a3, b3);
+  v[7] = csub(a3, b3);
+}
+
+template <typename real, bool INV, int MAXE, int RD>
+__device__ __forceinline__ void stockham_pass(cplx<real>* buf, int logM, int logNs, int ntrans, int stride,
+                                              const cplx<real>* __restrict__ tw, int twmul, int tpc) {
+  using V = cplx<real>;
+  constexpr int LR = RD == 8 ? 3 : (RD == 4 ? 2 : 1);
+  constexpr int NB = MAXE / RD;  // butterflies per thread per chunk
+  const int tid = threadIdx.x, T = blockDim.x;
+  const int Ns = 1 << logNs;
+  const int logMR = logM - LR, MR = 1 << logMR;
+  const int tws = ((1 << logM) >> (logNs + LR)) * twmul;
+  for (int t0 = 0; t0 < ntrans; t0 += tpc) {
+    const int nt = min(tpc, ntrans - t0);
+    const int nb = nt << logMR;
+    V v[NB][RD];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int b = tid + i * T;
+      if (b < nb) {
+        const V* src = buf + (t0 + (b >> logMR)) * stride + (b & (MR - 1));
+#pragma unroll
+        for (int r = 0; r < RD; ++r) v[i][r] = src[r * MR];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int b = tid + i * T;
+      if (b < nb) {
+        const int j = b & (MR - 1);
+        const int k = j & (Ns - 1);
+        V* u = v[i];
+        if (Ns > 1) {
+          V w1 = tw[k * tws];
+          if (INV) w1 = cconj(w1);
+          if (RD == 2) {
+            u[1] = cmul(u[1], w1);
+          } else if (RD == 4) {
+            V w2 = tw[2 * k * tws];
+            if (INV) w2 = cconj(w2);
+            const V w3 = cmul(w1, w2);
+            u[1] = cmul(u[1], w1);
+            u[2] = cmul(u[2], w2);
+            u[3] = cmul(u[3], w3);
+          } else {
+            V w4 = tw[4 * k * tws];
+            if (INV) w4 = cconj(w4);
+            const V w2 = cmul(w1, w1), w3 = cmul(w1, w2);
+            u[1] = cmul(u[1], w1);
+            u[2] = cmul(u[2], w2);
+            u[3] = cmul(u[3], w3);
+            u[4] = cmul(u[4], w4);
+            u[5] = cmul(u[5], cmul(w4, w1));
+            u[6] = cmul(u[6], cmul(w4, w2));
+            u[7] = cmul(u[7], cmul(w4, w3));
+          }
+        }
+        if (RD == 2) {
+          const V a = u[0], c = u[1];
+          u[0] = cadd(a, c);
+          u[1] = csub(a, c);
+        } else if (RD == 4) {
+          bfly4<INV>(u[0], u[1], u[2], u[3]);
+        } else {
+          bfly8<INV>(u);
+        }
+        V* dst = buf + (t0 + (b >> logMR)) * stride + ((j - k) << LR) + k;
+#pragma unroll
+        for (int r = 0; r < RD; ++r) dst[r * Ns] = u[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename real, bool INV, int MAXE>
 __device__ void fft_lds(cplx<real>* buf, int M, int ntrans, int stride, const cplx<real>* __restrict__ tw,
                         int twmul) {
-  using V = cplx<real>;
-  const int tid = threadIdx.x, T = blockDim.x;
-  int tpc = (T * MAXE) / M;
+  int tpc = (blockDim.x * MAXE) / M;
   if (tpc < 1) tpc = 1;
   const int logM = ilog2(M);
+  // Radix-8 passes (stockham_pass<..., 8>) cut the pass count by a third but
+  // need ~90 more VGPRs per thread on gfx950, halving occupancy; at the
+  // batched sizes that costs more than the saved LDS round trips, so the
+  // schedule is radix 4 with one radix-2 pass for odd log2 M.
   for (int logNs = 0; logNs < logM;) {
-    const int Ns = 1 << logNs;
-    const bool r4 = (logM - logNs) >= 2;
-    if (r4) {
-      const int logMR = logM - 2, MR = 1 << logMR;
-      const int tws = (M >> (logNs + 2)) * twmul;
-      for (int t0 = 0; t0 < ntrans; t0 += tpc) {
-        const int nt = min(tpc, ntrans - t0);
-        const int nb = nt << logMR;
-        V v[MAXE];
-#pragma unroll
-        for (int i = 0; i < MAXE / 4; ++i) {
-          const int b = tid + i * T;
-          if (b < nb) {
-            const int t = t0 + (b >> logMR), j = b & (MR - 1);
-            const V* src = buf + t * stride + j;
-            v[4 * i + 0] = src[0];
-            v[4 * i + 1] = src[MR];
-            v[4 * i + 2] = src[2 * MR];
-            v[4 * i + 3] = src[3 * MR];
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < MAXE / 4; ++i) {
-          const int b = tid + i * T;
-          if (b < nb) {
-            const int t = t0 + (b >> logMR), j = b & (MR - 1);
-            const int k = j & (Ns - 1);
-            V v0 = v[4 * i], v1 = v[4 * i + 1], v2 = v[4 * i + 2], v3 = v[4 * i + 3];
-            if (Ns > 1) {
-              V w1 = tw[k * tws], w2 = tw[2 * k * tws], w3 = tw[3 * k * tws];
-              if (INV) {
-                w1 = cconj(w1);
-                w2 = cconj(w2);
-                w3 = cconj(w3);
-              }
-              v1 = cmul(v1, w1);
-              v2 = cmul(v2, w2);
-              v3 = cmul(v3, w3);
-            }
-            bfly4<INV>(v0, v1, v2, v3);
-            V* dst = buf + t * stride + ((j - k) << 2) + k;
-            dst[0] = v0;
-            dst[Ns] = v1;
-            dst[2 * Ns] = v2;
-            dst[3 * Ns] = v3;
-          }
-        }
-        __syncthreads();
-      }
+    const int rem = logM - logNs;
+    if (rem >= 2) {
+      stockham_pass<real, INV, MAXE, 4>(buf, logM, logNs, ntrans, stride, tw, twmul, tpc);
       logNs += 2;
     } else {
-      const int logMR = logM - 1, MR = 1 << logMR;
-      const int tws = (M >> (logNs + 1)) * twmul;
-      for (int t0 = 0; t0 < ntrans; t0 += tpc) {
-        const int nt = min(tpc, ntrans - t0);
-        const int nb = nt << logMR;
-        V v[MAXE];
-#pragma unroll
-        for (int i = 0; i < MAXE / 2; ++i) {
-          const int b = tid + i * T;
-          if (b < nb) {
-            const int t = t0 + (b >> logMR), j = b & (MR - 1);
-            const V* src = buf + t * stride + j;
-            v[2 * i + 0] = src[0];
-            v[2 * i + 1] = src[MR];
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < MAXE / 2; ++i) {
-          const int b = tid + i * T;
-          if (b < nb) {
-            const int t = t0 + (b >> logMR), j = b & (MR - 1);
-            const int k = j & (Ns - 1);
-            V v0 = v[2 * i], v1 = v[2 * i + 1];
-            if (Ns > 1) {
-              V w1 = tw[k * tws];
-              if (INV) w1 = cconj(w1);
-              v1 = cmul(v1, w1);
-            }
-            V* dst = buf + t * stride + ((j - k) << 1) + k;
-            dst[0] = cadd(v0, v1);
-            dst[Ns] = csub(v0, v1);
-          }
-        }
-        __syncthreads();
-      }
+      stockham_pass<real, INV, MAXE, 2>(buf, logM, logNs, ntrans, stride, tw, twmul, tpc);
       logNs += 1;
     }
   }
@@ -163,21 +187,22 @@ __device__ void fft_lds(cplx<real>* buf, int M, int ntrans, int stride, const cp
 template <typename real>
 __device__ void r2c_post(cplx<real>* buf, int M, int ntrans, int stride, const cplx<real>* __restrict__ twN) {
   using V = cplx<real>;
-  const int half = M >> 1, per = half + 1;
-  const int total = ntrans * per;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int t = idx / per, k = idx - t * per;
+  const int half = M >> 1;
+  // thread owns bin pair (k, M - k) of every transform; k = 0 packs X[0], X[M]
+  for (int t = 0; t < ntrans; ++t) {
     V* z = buf + t * stride;
-    if (k == 0) {
-      const V z0 = z[0];
-      z[0] = mk<V>(z0.x + z0.y, z0.x - z0.y);
-    } else {
-      const V zk = z[k], zm = z[M - k];
-      const V e = cscale(cadd(zk, cconj(zm)), real(0.5));
-      const V o = cscale(cmulni(csub(zk, cconj(zm))), real(0.5));
-      const V wo = cmul(twN[k], o);
-      z[k] = cadd(e, wo);
-      z[M - k] = cconj(csub(e, wo));
+    for (int k = threadIdx.x; k <= half; k += blockDim.x) {
+      if (k == 0) {
+        const V z0 = z[0];
+        z[0] = mk<V>(z0.x + z0.y, z0.x - z0.y);
+      } else {
+        const V zk = z[k], zm = z[M - k];
+        const V e = cscale(cadd(zk, cconj(zm)), real(0.5));
+        const V o = cscale(cmulni(csub(zk, cconj(zm))), real(0.5));
+        const V wo = cmul(twN[k], o);
+        z[k] = cadd(e, wo);
+        z[M - k] = cconj(csub(e, wo));
+      }
     }
   }
   __syncthreads();
@@ -188,21 +213,21 @@ __device__ void r2c_post(cplx<real>* buf, int M, int ntrans, int stride, const c
 template <typename real>
 __device__ void c2r_pre(cplx<real>* buf, int M, int ntrans, int stride, const cplx<real>* __restrict__ twN) {
   using V = cplx<real>;
-  const int half = M >> 1, per = half + 1;
-  const int total = ntrans * per;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int t = idx / per, k = idx - t * per;
+  const int half = M >> 1;
+  for (int t = 0; t < ntrans; ++t) {
     V* z = buf + t * stride;
-    if (k == 0) {
-      const V x0 = z[0];
-      z[0] = mk<V>(x0.x + x0.y, x0.x - x0.y);
-    } else {
-      const V xk = z[k], xm = z[M - k];
-      const V a = cadd(xk, cconj(xm));
-      const V b = csub(xk, cconj(xm));
-      const V iwb = cmuli(cmul(cconj(twN[k]), b));
-      z[k] = cadd(a, iwb);
-      z[M - k] = cconj(csub(a, iwb));
+    for (int k = threadIdx.x; k <= half; k += blockDim.x) {
+      if (k == 0) {
+        const V x0 = z[0];
+        z[0] = mk<V>(x0.x + x0.y, x0.x - x0.y);
+      } else {
+        const V xk = z[k], xm = z[M - k];
+        const V a = cadd(xk, cconj(xm));
+        const V b = csub(xk, cconj(xm));
+        const V iwb = cmuli(cmul(cconj(twN[k]), b));
+        z[k] = cadd(a, iwb);
+        z[M - k] = cconj(csub(a, iwb));
+      }
     }
   }
   __syncthreads();

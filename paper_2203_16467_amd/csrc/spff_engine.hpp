@@ -76,6 +76,7 @@ struct SlotCtl {
   int32_t am, newton, cg, bccg;     // counters of the current load step
   int32_t cg_newton, pf_it;         // CG iterations of the current Newton step, BCCG of the current solve
   int32_t newton_solve, pad0;       // Newton steps of the current mechanics solve
+  uint64_t t_start;                 // device wall clock at the start of the step
   int32_t ticks, status;
   double eps_bar[3];
   // mechanics
@@ -105,6 +106,31 @@ struct SlotPtr {
   real* rm;      // [3][n]
   real* pm;      // [3][n]
   void* spec;    // complex [3][nx/2][ny]  (half spectrum, transposed)
+};
+
+// Device-side load-step queue of a slot: the controller starts step pos+1
+// as soon as step pos has finished, without a host round trip, and records
+// the finished step's statistics in the slot's StepRec array.
+constexpr int SEQ_MAX = 256;
+
+struct SlotSeq {
+  int32_t len, pos;
+  int32_t pad[2];
+  double eps_bar[SEQ_MAX][3];
+};
+
+struct StepRec {
+  int32_t status, flags, am, newton, cg, bccg, ticks, pad;
+  uint64_t t_start, t_end;  // device wall clock
+  double dphi, mech_res, pf_res, F_e, F_f, sbar[3], phi_sum, phi_max, crack_px;
+  double eps_bar[3];
+};
+
+// Device-side kernel timing (profiling): every work-group of a tick kernel
+// lowers `start` to its first clock reading and raises `end` to its last; the
+// controller of the same tick folds end - start into per-kernel totals.
+struct KTime {
+  unsigned long long start, end;
 };
 
 // Number of FP64 partials per work-group written by each kernel.

@@ -42,6 +42,20 @@ __device__ __forceinline__ int phase_comps_row(int phase) {
   }
 }
 
+// Row-kernel coordinates (row group g, list index si) of this work-group.
+// Work-groups are dispatched to the 8 XCDs round-robin by linear id; the
+// remap gives consecutive row groups of a slot to one XCD, so the short
+// transposed spectrum segments of neighbouring groups (R rows each) meet in
+// the same L2 and leave it as whole lines.
+__device__ __forceinline__ void row_coords(int ngr, int& g, int& si) {
+  const int N = gridDim.x * gridDim.y;
+  int L = blockIdx.x + blockIdx.y * gridDim.x;
+  if ((N & 7) == 0) L = (L & 7) * (N >> 3) + (L >> 3);
+  const int lg = ilog2(ngr);  // ngr is a power of two
+  si = L >> lg;
+  g = L & (ngr - 1);
+}
+
 template <typename real>
 struct V2 {
   real a, b;
@@ -70,7 +84,7 @@ __device__ __forceinline__ real lower_bound(real pref, const SlotParam& P) {
 // store of the half spectra; FP64 partial sums per work-group.
 // ===========================================================================
 template <typename real>
-__global__ __launch_bounds__(THREADS) void k_rowfwd(const int* __restrict__ list,
+__device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
                                                     const SlotPtr<real>* __restrict__ ptrs,
                                                     const SlotParam* __restrict__ prms,
                                                     const SlotCtl* __restrict__ ctls,
@@ -79,7 +93,9 @@ __global__ __launch_bounds__(THREADS) void k_rowfwd(const int* __restrict__ list
   using C = cplx<real>;
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_ROW];
-  const int s = list[blockIdx.y], g = blockIdx.x;
+  int g, si;
+  row_coords(ngr, g, si);
+  const int s = list[si];
   if (s < 0) return;
   const SlotCtl& ctl = ctls[s];
   const int phase = ctl.phase;
@@ -101,8 +117,9 @@ __global__ __launch_bounds__(THREADS) void k_rowfwd(const int* __restrict__ list
   const real eb0 = real(ctl.eps_bar[0]), eb1 = real(ctl.eps_bar[1]), eb2 = real(ctl.eps_bar[2]);
   const int split = P.split;
 
+  const int logM = ilog2(M), logR = ilog2(R);
   for (int idx = threadIdx.x; idx < R * M; idx += blockDim.x) {
-    const int r = idx / M, h = idx - r * M;
+    const int r = idx >> logM, h = idx & (M - 1);
     const int o = (y0 + r) * nx + 2 * h;
     const int li = r * stride + h;  // LDS index of component 0
     real val[3][2];
@@ -288,10 +305,10 @@ __global__ __launch_bounds__(THREADS) void k_rowfwd(const int* __restrict__ list
     C* spec = reinterpret_cast<C*>(F.spec);
     const int tot = ncomp * M * R;
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-      const int r = idx % R;
-      const int rest = idx / R;
-      const int kx = rest % M, c = rest / M;
-      spec[(size_t)(c * M + kx) * ny + y0 + r] = buf[(c * R + r) * stride + kx];
+      const int r = idx & (R - 1);
+      const int rest = idx >> logR;
+      const int kx = rest & (M - 1), c = rest >> logM;
+      spec[(size_t)(rest) * ny + y0 + r] = buf[(c * R + r) * stride + kx];
     }
   }
   block_reduce_store<NP_ROW>(acc, red, part + ((size_t)s * ngr + g) * NP_ROW, phase == PH_STATS ? 3 : -1);
@@ -319,7 +336,7 @@ __device__ __forceinline__ void project3(real* a, real fx, real fy) {
 }
 
 template <typename real>
-__global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+__device__ __forceinline__ void k_col_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                                  const SlotParam* __restrict__ prms,
                                                  const SlotCtl* __restrict__ ctls,
                                                  const cplx<real>* __restrict__ twy, double* __restrict__ part,
@@ -366,10 +383,11 @@ __global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, c
 
   // load W columns of each component
   const int tot = ncomp * W * ny;
+  const int logny = ilog2(ny), logW = ilog2(W);
   for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int y = idx % ny, rest = idx / ny;
-    const int w = rest % W, c = rest / W;
-    buf[(c * W + w) * stride + y] = spec[(size_t)(c * M + kx0 + w) * ny + y];
+    const int y = idx & (ny - 1), rest = idx >> logny;
+    const int w = rest & (W - 1), c = rest >> logW;
+    buf[rest * stride + y] = spec[(size_t)(c * M + kx0 + w) * ny + y];
   }
   __syncthreads();
   fft_lds<real, false, MAXE>(buf, ny, ncomp * W, stride, twy, 1);
@@ -379,7 +397,7 @@ __global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, c
   // per-mode operator; thread owns mode (w, ky); for the packed column kx = 0
   // threads with ky <= ny/2 own the pair (ky, ny - ky)
   for (int idx = threadIdx.x; idx < W * ny; idx += blockDim.x) {
-    const int w = idx / ny, ky = idx - w * ny;
+    const int w = idx >> logny, ky = idx & (ny - 1);
     const int kx = kx0 + w;
     const int kys = ky < ny / 2 ? ky : ky - ny;
     const real fy_true = real(kys) / real(ny);
@@ -457,9 +475,9 @@ __global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, c
   if (mode != 2) {
     fft_lds<real, true, MAXE>(buf, ny, ncomp * W, stride, twy, 1);
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-      const int y = idx % ny, rest = idx / ny;
-      const int w = rest % W, c = rest / W;
-      spec[(size_t)(c * M + kx0 + w) * ny + y] = buf[(c * W + w) * stride + y];
+      const int y = idx & (ny - 1), rest = idx >> logny;
+      const int w = rest & (W - 1), c = rest >> logW;
+      spec[(size_t)(c * M + kx0 + w) * ny + y] = buf[rest * stride + y];
     }
   }
   block_reduce_store<NP_COL>(acc, red, part + ((size_t)s * ngc + g) * NP_COL);
@@ -470,7 +488,7 @@ __global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, c
 // phase); FP64 partial sums per work-group.
 // ===========================================================================
 template <typename real>
-__global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list,
+__device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
                                                     const SlotPtr<real>* __restrict__ ptrs,
                                                     const SlotParam* __restrict__ prms,
                                                     const SlotCtl* __restrict__ ctls,
@@ -481,7 +499,9 @@ __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_INV];
   __shared__ double scal[1];
-  const int s = list[blockIdx.y], g = blockIdx.x;
+  int g, si;
+  row_coords(ngr, g, si);
+  const int s = list[si];
   if (s < 0) return;
   const SlotCtl& ctl = ctls[s];
   const int phase = ctl.phase;
@@ -522,11 +542,12 @@ __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list
   }
 
   const int tot = ncomp * M * R;
+  const int logM = ilog2(M), logR = ilog2(R);
   for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int r = idx % R;
-    const int rest = idx / R;
-    const int kx = rest % M, c = rest / M;
-    buf[(c * R + r) * stride + kx] = spec[(size_t)(c * M + kx) * ny + y0 + r];
+    const int r = idx & (R - 1);
+    const int rest = idx >> logR;
+    const int kx = rest & (M - 1), c = rest >> logM;
+    buf[(c * R + r) * stride + kx] = spec[(size_t)rest * ny + y0 + r];
   }
   __syncthreads();
   c2r_pre<real>(buf, M, ncomp * R, stride, twx);
@@ -534,7 +555,7 @@ __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list
 
   double acc[NP_INV] = {0.0, 0.0, 0.0, 0.0};
   for (int idx = threadIdx.x; idx < R * M; idx += blockDim.x) {
-    const int r = idx / M, h = idx - r * M;
+    const int r = idx >> logM, h = idx & (M - 1);
     const int o = (y0 + r) * nx + 2 * h;
     const int li = r * stride + h;
     switch (phase) {
@@ -606,10 +627,11 @@ __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list
 // Algorithmic HBM bytes per pixel moved by the row-forward, column and
 // row-inverse kernels for the phase a slot executed (r = sizeof(real)):
 // every input plane read once, every output plane written once, half spectra
-// (2r bytes per pixel per component) written by the row-forward kernel, read
-// and written by the column kernel, read by the row-inverse kernel.
+// (nx/2 * ny complex values = r bytes per pixel per component) written by the
+// row-forward kernel, read and written by the column kernel, read by the
+// row-inverse kernel.
 __device__ inline void phase_bytes(int phase, int flags, int split, double r, double* b) {
-  const double sp = 2.0 * r;  // half spectrum, per pixel per component
+  const double sp = r;  // half spectrum, per pixel per component
   b[0] = b[1] = b[2] = 0.0;
   switch (phase) {
     case PH_M_RES:
@@ -653,16 +675,18 @@ __device__ inline void phase_bytes(int phase, int flags, int split, double r, do
 // order, updates FP64 scalars and moves the slot's state machine.
 // ===========================================================================
 template <typename real>
-__global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const SlotParam* __restrict__ prms,
+__device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const SlotParam* __restrict__ prms,
                                              SlotCtl* __restrict__ ctls,
                                              const double* __restrict__ prow, const double* __restrict__ pcol,
                                              const double* __restrict__ pinv, double* __restrict__ prof,
+                                             SlotSeq* __restrict__ seqs, StepRec* __restrict__ recs,
                                              int nx, int ny, int ngr, int ngc) {
   const int s = list[blockIdx.x];
   if (s < 0) return;
   SlotCtl& C = ctls[s];
   const int phase = C.phase;
   if (phase == PH_IDLE) return;
+  if (threadIdx.x == 0 && C.ticks == 0 && C.t_start == 0) C.t_start = wall_clock64();
   const SlotParam& P = prms[s];
   if (prof && threadIdx.x == 0) {
     double b[3];
@@ -865,6 +889,52 @@ __global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const
     status = -4;
     nphase = PH_IDLE;
   }
+  // a load step just ended: record it and start the next one of the queue
+  bool restart = false;
+  if (seqs && nphase == PH_IDLE && (phase == PH_STATS || bad) && !(flags & FL_INIT_SOLVE) && threadIdx.x == 0) {
+    SlotSeq& q = seqs[s];
+    if (q.pos < q.len) {
+      StepRec& r = recs[(size_t)s * SEQ_MAX + q.pos];
+      r.status = status;
+      r.flags = flags;
+      r.am = am;
+      r.newton = newton;
+      r.cg = cg;
+      r.bccg = bccg;
+      r.ticks = C.ticks + 1;
+      r.t_start = C.t_start;
+      r.t_end = wall_clock64();
+      r.dphi = dphi;
+      r.mech_res = mech_res;
+      r.pf_res = pf_res;
+      r.F_e = C.F_e;
+      r.F_f = C.F_f;
+      for (int k = 0; k < 3; ++k) {
+        r.sbar[k] = C.sbar[k];
+        r.eps_bar[k] = C.eps_bar[k];
+      }
+      r.phi_sum = C.phi_sum;
+      r.phi_max = C.phi_max;
+      r.crack_px = C.crack_px;
+      q.pos += 1;
+      if (q.pos < q.len && status >= 0) restart = true;
+    }
+  }
+  if (restart) {
+    // fresh control block for the next load step of the queue
+    const SlotSeq& q = seqs[s];
+    C.eps_bar[0] = q.eps_bar[q.pos][0];
+    C.eps_bar[1] = q.eps_bar[q.pos][1];
+    C.eps_bar[2] = q.eps_bar[q.pos][2];
+    C.phase = PH_M_RES;
+    C.flags = FL_FIRST_OF_STEP;
+    C.am = C.newton = C.cg = C.bccg = C.cg_newton = C.pf_it = C.newton_solve = 0;
+    C.ticks = 0;
+    C.status = 0;
+    C.dphi = 0.0;
+    C.t_start = wall_clock64();
+    return;
+  }
   if (threadIdx.x == 0) {
     C.phase = nphase;
     C.flags = flags;
@@ -899,6 +969,73 @@ __global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const
     C.pf_floor = pf_floor;
     C.ticks = C.ticks + 1;
   }
+}
+
+// ===========================================================================
+// Kernel entry points: the bodies above, bracketed by the device clock when
+// profiling (kt != nullptr).
+// ===========================================================================
+__device__ __forceinline__ void kt_begin(KTime* kt) {
+  if (kt && threadIdx.x == 0) atomicMin(&kt->start, (unsigned long long)wall_clock64());
+}
+__device__ __forceinline__ void kt_end(KTime* kt) {
+  if (kt) {
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&kt->end, (unsigned long long)wall_clock64());
+  }
+}
+
+template <typename real>
+__global__ __launch_bounds__(THREADS) void k_rowfwd(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                                    const SlotParam* __restrict__ prms,
+                                                    const SlotCtl* __restrict__ ctls,
+                                                    const cplx<real>* __restrict__ twx, double* __restrict__ part,
+                                                    int nx, int ny, int R, int ngr, KTime* kt) {
+  kt_begin(kt);
+  k_rowfwd_body<real>(list, ptrs, prms, ctls, twx, part, nx, ny, R, ngr);
+  kt_end(kt);
+}
+
+template <typename real>
+__global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                                 const SlotParam* __restrict__ prms,
+                                                 const SlotCtl* __restrict__ ctls,
+                                                 const cplx<real>* __restrict__ twy, double* __restrict__ part,
+                                                 int nx, int ny, int W, int ngc, KTime* kt) {
+  kt_begin(kt);
+  k_col_body<real>(list, ptrs, prms, ctls, twy, part, nx, ny, W, ngc);
+  kt_end(kt);
+}
+
+template <typename real>
+__global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                                    const SlotParam* __restrict__ prms,
+                                                    const SlotCtl* __restrict__ ctls,
+                                                    const cplx<real>* __restrict__ twx,
+                                                    const double* __restrict__ part_row,
+                                                    double* __restrict__ part, int nx, int ny, int R, int ngr,
+                                                    KTime* kt) {
+  kt_begin(kt);
+  k_rowinv_body<real>(list, ptrs, prms, ctls, twx, part_row, part, nx, ny, R, ngr);
+  kt_end(kt);
+}
+
+template <typename real>
+__global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const SlotParam* __restrict__ prms,
+                                             SlotCtl* __restrict__ ctls, const double* __restrict__ prow,
+                                             const double* __restrict__ pcol, const double* __restrict__ pinv,
+                                             double* __restrict__ prof, SlotSeq* __restrict__ seqs,
+                                             StepRec* __restrict__ recs, int nx, int ny, int ngr, int ngc,
+                                             KTime* kt, unsigned long long* __restrict__ ktsum) {
+  // fold this tick's kernel times (one work-group, before any early return)
+  if (kt && blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int j = 0; j < 3; ++j) {
+      if (kt[j].end > kt[j].start) ktsum[j] += kt[j].end - kt[j].start;
+      kt[j].start = ~0ull;
+      kt[j].end = 0ull;
+    }
+  }
+  k_ctrl_body<real>(list, prms, ctls, prow, pcol, pinv, prof, seqs, recs, nx, ny, ngr, ngc);
 }
 
 // ===========================================================================
@@ -958,21 +1095,17 @@ template <typename real>
 hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>* ptrs, const SlotParam* prms,
                        SlotCtl* ctls, const typename HostCplx<real>::type* twx,
                        const typename HostCplx<real>::type* twy, double* prow, double* pcol, double* pinv,
-                       double* prof, hipEvent_t* ev, hipStream_t st) {
+                       double* prof, SlotSeq* seqs, StepRec* recs, KTime* kt, unsigned long long* ktsum,
+                       hipStream_t st) {
   dim3 grow(G.ngr, G.S), gcol(G.ngc, G.S);
-  if (ev) (void)hipEventRecord(ev[0], st);
   hipLaunchKernelGGL(k_rowfwd<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, G.nx,
-                     G.ny, G.R, G.ngr);
-  if (ev) (void)hipEventRecord(ev[1], st);
+                     G.ny, G.R, G.ngr, kt ? kt + 0 : nullptr);
   hipLaunchKernelGGL(k_col<real>, gcol, dim3(G.threads), G.lds_col, st, list, ptrs, prms, ctls, twy, pcol, G.nx,
-                     G.ny, G.W, G.ngc);
-  if (ev) (void)hipEventRecord(ev[2], st);
+                     G.ny, G.W, G.ngc, kt ? kt + 1 : nullptr);
   hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, pinv,
-                     G.nx, G.ny, G.R, G.ngr);
-  if (ev) (void)hipEventRecord(ev[3], st);
-  hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(64), 0, st, list, prms, ctls, prow, pcol, pinv, prof, G.nx,
-                     G.ny, G.ngr, G.ngc);
-  if (ev) (void)hipEventRecord(ev[4], st);
+                     G.nx, G.ny, G.R, G.ngr, kt ? kt + 2 : nullptr);
+  hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(64), 0, st, list, prms, ctls, prow, pcol, pinv, prof, seqs,
+                     recs, G.nx, G.ny, G.ngr, G.ngc, kt, ktsum);
   return hipGetLastError();
 }
 
@@ -999,10 +1132,10 @@ hipError_t launch_fields(const SlotPtr<real>* ptrs, const SlotParam* prms, const
 
 template hipError_t launch_tick<float>(const LaunchGeom&, const int*, const SlotPtr<float>*, const SlotParam*,
                                        SlotCtl*, const float2*, const float2*, double*, double*, double*, double*,
-                                       hipEvent_t*, hipStream_t);
+                                       SlotSeq*, StepRec*, KTime*, unsigned long long*, hipStream_t);
 template hipError_t launch_tick<double>(const LaunchGeom&, const int*, const SlotPtr<double>*, const SlotParam*,
                                         SlotCtl*, const double2*, const double2*, double*, double*, double*,
-                                        double*, hipEvent_t*, hipStream_t);
+                                        double*, SlotSeq*, StepRec*, KTime*, unsigned long long*, hipStream_t);
 template hipError_t launch_validate<float>(const float*, size_t, double, double, double, unsigned int*,
                                            hipStream_t);
 template hipError_t launch_validate<double>(const double*, size_t, double, double, double, unsigned int*,

@@ -24,7 +24,8 @@ template <typename real>
 hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>* ptrs, const SlotParam* prms,
                        SlotCtl* ctls, const typename HostCplx<real>::type* twx,
                        const typename HostCplx<real>::type* twy, double* prow, double* pcol, double* pinv,
-                       double* prof, hipEvent_t* ev, hipStream_t st);
+                       double* prof, SlotSeq* seqs, StepRec* recs, KTime* kt, unsigned long long* ktsum,
+                       hipStream_t st);
 
 template <typename real>
 hipError_t launch_validate(const real* a, size_t n, double lo_excl, double lo_incl, double hi_incl,
