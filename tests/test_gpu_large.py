@@ -1,0 +1,154 @@
+"""GPU parity at the full workload sizes.
+
+- Batched: 64 realizations of 512x512 in the launch configuration the
+  benchmark times (captured graphs, 16 ticks per host check).  Sampled
+  outputs (whole realizations) against the FP64 oracle started from the
+  GPU state, and invariants of every realization.
+- Large single instance: 2048x2048, l = 1 px.  FP32-bulk against the FP64
+  GPU build from the same state at an elastic load step and at the
+  nucleation step, and the 256x256 crop of the same microstructure against
+  the FP64 oracle.
+
+Contract (FP32 bulk vs FP64): strain / stress / eps* relative L2 <= 1e-4,
+phi max-abs <= 1e-3, crack set {phi > 0.9} differing in <= 0.5% of pixels.
+"""
+
+import numpy as np
+import pytest
+
+import spff_inputs as si
+from gpu_common import (cfg_for, crack_xor_fraction, gpu_fields, oracle_fields, oracle_for, rel_l2,
+                        set_oracle_from_gpu)
+from paper_2203_16467_amd import spff
+from test_gpu_parity import compare, torch_E
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _first_nucleation(prob, ramp, chunk=50):
+    """Index of the first load step whose phi_max > 0 (runs the problem
+    through the ramp in device-queued chunks)."""
+    for c0 in range(0, len(ramp), chunk):
+        _, stats = prob.run_sequence(ramp[c0:c0 + chunk])
+        for k, s in enumerate(stats[0]):
+            if s["phi_max"] > 0.0:
+                return c0 + k
+    return None
+
+
+def _check_fp32_vs_fp64(g32, g64, s32, s64):
+    for k in ("strain", "stress", "eps_star", "psi_plus"):
+        e = rel_l2(g32[k], g64[k])
+        assert e <= TOL, (k, e)
+    assert np.abs(g32["phi"] - g64["phi"]).max() <= 1e-3
+    assert crack_xor_fraction(g32["phi"], g64["phi"]) <= 0.005
+    # energies relative to the total energy the minimisation controls: at
+    # the nucleation onset F_f is ~1e-9 of F_e and its own relative error is
+    # set by the solver tolerance, not by the precision
+    tot = s64["F_e"] + s64["F_f"]
+    assert abs(s32["F_e"] - s64["F_e"]) <= TOL * tot
+    assert abs(s32["F_f"] - s64["F_f"]) <= TOL * tot
+    for k in range(3):
+        assert s32["sigma_bar"][k] == pytest.approx(s64["sigma_bar"][k], rel=TOL, abs=1e-12)
+
+
+def test_batched_512_sampled_parity_and_invariants():
+    """64 x 512^2, AT1, spectral split, l = 2 px (the batched workload), in
+    the benchmark's launch configuration.  Load step 40 (elastic) of every
+    realization; realization 37 against the oracle from the GPU state."""
+    n, B = 512, 64
+    E = np.stack([si.young_modulus(n, 16.0, 0.2, 3000 + i) for i in range(B)])
+    ramp = si.uniaxial_ramp(200, 0.2, 2.0)
+    cfg = cfg_for(n, use_graph=1, ticks_per_sync=16)
+    p = spff.Problem(torch_E(E, "fp32"), cfg)
+    st, _ = p.run_sequence(ramp[:40])
+    assert st == spff.OK
+    sample = 37
+    o = oracle_for(E[sample], cfg)
+    set_oracle_from_gpu(o, p, sample)
+    st, stats = p.run_sequence(ramp[40:41])
+    assert st == spff.OK
+    ost = o.load_step(ramp[40])
+    cmp = compare(gpu_fields(p, sample), oracle_fields(o), "fp32")
+    print(cmp, stats[sample][0]["cg_iters"], ost["cg"])
+    assert stats[sample][0]["F_e"] == pytest.approx(ost["F_e"], rel=TOL)
+    # invariants over the whole batch
+    for i in range(B):
+        s = stats[i][0]
+        assert s["status"] == spff.OK and s["phi_max"] == 0.0 and np.isfinite(s["F_e"])
+        assert s["sigma_bar"][1] > 0.0
+    f = p.get_fields(spff.FIELD_PHI | spff.FIELD_STRESS)
+    assert bool((f["phi"] == 0).all()) and bool(f["stress"].isfinite().all())
+    p.close()
+
+
+@pytest.fixture(scope="module")
+def c5():
+    E = si.young_modulus(2048, 32.0, 0.3, 5000)
+    ramp = si.uniaxial_ramp(500, 0.2, 1.0)
+    return E, ramp
+
+
+def test_large_2048_fp32_against_fp64(c5):
+    """2048^2, l = 1 px: the FP32-bulk build against the FP64 build from the
+    same state (the FP32 state promoted), at an elastic step and at the
+    nucleation step (alternating minimisation capped at 3 iterations)."""
+    E, ramp = c5
+    kw = dict(ell=1.0, max_am=3, use_graph=1, ticks_per_sync=16)
+    p32 = spff.Problem(torch_E(E, "fp32"), cfg_for(2048, **kw))
+    k_nuc = _first_nucleation(p32, ramp)
+    assert k_nuc is not None and k_nuc > 10
+    p32.close()
+    p32 = spff.Problem(torch_E(E, "fp32"), cfg_for(2048, **kw))
+    p64 = spff.Problem(torch_E(E, "fp64"), cfg_for(2048, precision="fp64", **kw))
+    k_el = k_nuc // 2
+    done = 0
+    for k in (k_el, k_nuc):
+        if k > done:
+            p32.run_sequence(ramp[done:k])
+        st, eb = p32.get_state()
+        p64.set_state(st.double(), eb)
+        _, s32 = p32.load_step(ramp[k])
+        _, s64 = p64.load_step(ramp[k])
+        done = k + 1
+        g32, g64 = gpu_fields(p32), gpu_fields(p64)
+        print(k, s32[0]["cg_iters"], s64[0]["cg_iters"], s32[0]["bccg_iters"], s64[0]["bccg_iters"],
+              s32[0]["phi_max"], s64[0]["phi_max"])
+        _check_fp32_vs_fp64(g32, g64, s32[0], s64[0])
+        if k == k_nuc:
+            assert s32[0]["phi_max"] > 0.0 and s32[0]["am_iters"] == s64[0]["am_iters"]
+    p32.close()
+    p64.close()
+
+
+def test_large_crop_256_against_oracle(c5):
+    """The 256^2 crop E[0:256, 0:256] of the 2048^2 microstructure (treated
+    as periodic, l = 1 px): GPU FP32 against the FP64 oracle from the GPU
+    state at an elastic step and at the crop's nucleation step (alternating
+    minimisation capped at 3 iterations on both sides)."""
+    E, ramp = c5
+    Ec = np.ascontiguousarray(E[:256, :256])
+    cfg = cfg_for(256, ell=1.0, max_am=3, use_graph=1, ticks_per_sync=8)
+    p = spff.Problem(torch_E(Ec, "fp32"), cfg)
+    k_nuc = _first_nucleation(p, ramp)
+    assert k_nuc is not None and k_nuc > 10
+    p.close()
+    p = spff.Problem(torch_E(Ec, "fp32"), cfg)
+    o = oracle_for(Ec, cfg, max_am=3)
+    done = 0
+    for k in (k_nuc // 2, k_nuc):
+        if k > done:
+            p.run_sequence(ramp[done:k])
+        set_oracle_from_gpu(o, p)
+        _, stats = p.load_step(ramp[k])
+        ost = o.load_step(ramp[k])
+        done = k + 1
+        cmp = compare(gpu_fields(p), oracle_fields(o), "fp32")
+        print(k, cmp, stats[0]["cg_iters"], ost["cg"], stats[0]["bccg_iters"], ost["bccg"])
+        assert stats[0]["F_e"] == pytest.approx(ost["F_e"], rel=TOL)
+        if k == k_nuc:
+            assert stats[0]["phi_max"] > 0.0 and stats[0]["am_iters"] == ost["am"]
+            assert abs(stats[0]["F_f"] - ost["F_f"]) <= TOL * (ost["F_e"] + ost["F_f"])
+    p.close()
