@@ -209,16 +209,18 @@ spff_status spff_set_state(spff_problem* p, const void* src_dev, const double* e
 enum { SPFF_OP_PROJECT = 0, SPFF_OP_NEG_LAPLACIAN = 1 };
 spff_status spff_apply_operator(spff_problem* p, int32_t op, const void* in_dev, void* out_dev);
 
-/* Kernel profiling.  While enabled, every work-group of the row-forward,
- * column and row-inverse FFT kernels brackets its work with the device wall
- * clock; per tick the controller folds (last end - first start) into a
- * per-kernel total, so the times are kernel execution times (also inside
- * captured graphs, without host events).  The controller also accumulates
- * each kernel's algorithmic HBM bytes for the phase every problem executed
- * (inputs read once, outputs written once, half spectra round-tripped).
- * Enabling resets the totals. */
+/* Kernel profiling.  A tick is four kernels: row-forward FFT, column FFT,
+ * row-inverse FFT and the controller.  While enabled, every work-group of
+ * the three FFT kernels brackets its work with the device wall clock, and
+ * the controller of the same tick folds (last end - first start) of each
+ * into a per-kernel total: kernel execution times, also inside captured
+ * graphs, without host events (the controller itself is not timed: its
+ * kernel_ms stays zero).  The controller also accumulates each kernel's
+ * algorithmic HBM bytes for the phase every problem executed (inputs read
+ * once, outputs written once, half spectra round-tripped).  Enabling resets
+ * the totals. */
 typedef struct spff_profile {
-  double kernel_ms[4];     /* summed execution time per kernel (controller: 0) */
+  double kernel_ms[4];     /* summed execution time per kernel */
   int64_t launches[4];     /* launches per kernel */
   double alg_bytes[4];     /* summed algorithmic bytes per kernel */
   int64_t ticks;

@@ -120,6 +120,31 @@ LaunchGeom plan(const spff_config* c, int S, size_t csize) {
   G.ngc = M / W;
   G.lds_row = 3 * (size_t)R * (M + PAD) * csize;
   G.lds_col = 3 * (size_t)W * (c->ny + PAD) * csize;
+  G.threads_col = G.threads;
+  G.col_reg = 0;
+  // FP32 columns of 128..512 points: register-resident transforms, a group
+  // of ny/8 lanes per column, W columns per work-group (at least one
+  // wavefront, at most THREADS lanes); W is fixed by plan_cols if given so
+  // that the partial sums (hence the results) do not depend on the batch
+  if (c->precision == SPFF_FP32 && (c->ny == 128 || c->ny == 256 || c->ny == 512)) {
+    const int Lc = c->ny / 8;
+    const int wmin = 64 / Lc, wmax = THREADS / Lc;
+    if (wmin <= M) {
+      int Wr = wmin;
+      if (c->plan_cols > 0) {
+        Wr = std::max(wmin, std::min(wmax, c->plan_cols));
+      } else {
+        while (Wr * 2 <= wmax && Wr * 2 <= M && (long)(M / (2 * Wr)) * S >= TARGET_WG) Wr *= 2;
+      }
+      if (Wr <= M) {
+        G.col_reg = 1;
+        G.W = Wr;
+        G.ngc = M / Wr;
+        G.threads_col = Wr * Lc;
+        G.lds_col = (size_t)Wr * (c->ny + c->ny / 8) * csize;
+      }
+    }
+  }
   return G;
 }
 
@@ -147,7 +172,7 @@ Layout layout(const spff_config* c, int S, size_t rsize, bool scratch_only = fal
   L.bad = take(64);
   L.prof = take(sizeof(double) * 3 * S);
   L.seq = take(sizeof(SlotSeq) * S);
-  L.kt = take(sizeof(KTime) * 4);
+  L.kt = take(sizeof(KTime) * 3);
   L.ktsum = take(sizeof(unsigned long long) * 4);
   L.rec = take(sizeof(StepRec) * SEQ_MAX * S);
   L.slot0 = off;
@@ -894,8 +919,12 @@ spff_status spff_profile_enable(spff_problem* p, int32_t enable) {
   p->prof_on = enable != 0;
   for (int j = 0; j < 4; ++j) p->launches[j] = 0;
   p->prof_ticks = 0;
-  static const KTime init[4] = {{~0ull, 0ull}, {~0ull, 0ull}, {~0ull, 0ull}, {~0ull, 0ull}};
-  HIP_TRY(hipMemcpyAsync(p->d_kt(), init, sizeof(init), hipMemcpyHostToDevice, p->stream));
+  std::vector<KTime> init(3);
+  for (KTime& k : init) {
+    std::fill(std::begin(k.start), std::end(k.start), ~0ull);
+    std::fill(std::begin(k.end), std::end(k.end), 0ull);
+  }
+  HIP_TRY(hipMemcpyAsync(p->d_kt(), init.data(), sizeof(KTime) * 3, hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipMemsetAsync(p->d_ktsum(), 0, sizeof(unsigned long long) * 4, p->stream));
   HIP_TRY(hipMemsetAsync(p->d_prof(), 0, sizeof(double) * 3 * p->S, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));

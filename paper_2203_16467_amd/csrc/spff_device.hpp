@@ -181,6 +181,115 @@ __device__ void fft_lds(cplx<real>* buf, int M, int ntrans, int stride, const cp
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident FFT of length N (power of two) by a group of L = N/E
+// lanes holding E elements each: lane l holds x[l + m L], m < E.
+// Stockham passes of radix RD (E while the remaining factor allows, then the
+// remainder); lane l computes butterflies j = l + t L, t < E/RD.  The inputs
+// of butterfly j, x[j + r N/RD], are the lane's own slots v[t + r E/RD] in
+// every pass.  Outputs go to the group's LDS area at (j - k) RD + k + s NS
+// (k = j mod NS) and are read back in the lane's pattern -- except after
+// the last pass, whose outputs j + s N/RD are the lane's own slots.  So a
+// forward transform ends, and an inverse one starts, in the load layout: a
+// per-mode operator in between needs no data movement, and global loads and
+// stores of x[l + m L] are coalesced across lanes.  Groups never span
+// wavefronts (L <= 64), so an exchange is ordered by wave_sync() alone.
+// tw holds the (N twmul)-th roots of unity exp(-2 pi i e / (N twmul)); the
+// inverse (INV) uses conjugates and is unnormalised.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS index of element i of an exchange area (one pad slot per 8 elements,
+// so that the stride-RD writes of a pass spread over the banks)
+__device__ __forceinline__ int xpad(int i) { return i + (i >> 3); }
+template <int N> struct XArea { static constexpr int size = N + N / 8; };
+
+template <bool INV, int RD, typename V>
+__device__ __forceinline__ void dft_small(V (&u)[RD]) {
+  if constexpr (RD == 2) {
+    const V a = u[0], b = u[1];
+    u[0] = cadd(a, b);
+    u[1] = csub(a, b);
+  } else if constexpr (RD == 4) {
+    bfly4<INV>(u[0], u[1], u[2], u[3]);
+  } else {
+    bfly8<INV>(u);
+  }
+}
+
+template <typename real, bool INV, int N, int E, int RD, int NS>
+__device__ __forceinline__ void reg_pass(cplx<real> (&v)[E], cplx<real>* x, int lane,
+                                         const cplx<real>* __restrict__ tw, int twmul) {
+  using V = cplx<real>;
+  constexpr int L = N / E, B = E / RD;
+  constexpr bool LAST = NS * RD == N;
+  constexpr int STEP = N / (NS * RD);
+  V o[LAST ? E : 1];
+#pragma unroll
+  for (int t = 0; t < B; ++t) {
+    const int j = lane + t * L;
+    const int k = j & (NS - 1);
+    V u[RD];
+#pragma unroll
+    for (int r = 0; r < RD; ++r) u[r] = v[t + r * B];
+    if constexpr (NS > 1) {
+      const int e = k * STEP * twmul;
+      V w1 = tw[e];
+      if (INV) w1 = cconj(w1);
+      if constexpr (RD == 2) {
+        u[1] = cmul(u[1], w1);
+      } else {
+        V w2 = tw[2 * e];
+        if (INV) w2 = cconj(w2);
+        const V w3 = cmul(w1, w2);
+        u[1] = cmul(u[1], w1);
+        u[2] = cmul(u[2], w2);
+        u[3] = cmul(u[3], w3);
+        if constexpr (RD == 8) {
+          V w4 = tw[4 * e];
+          if (INV) w4 = cconj(w4);
+          u[4] = cmul(u[4], w4);
+          u[5] = cmul(u[5], cmul(w4, w1));
+          u[6] = cmul(u[6], cmul(w4, w2));
+          u[7] = cmul(u[7], cmul(w4, w3));
+        }
+      }
+    }
+    dft_small<INV, RD>(u);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int q = 0; q < RD; ++q) o[t + q * B] = u[q];
+    } else {
+      const int base = (j - k) * RD + k;
+#pragma unroll
+      for (int q = 0; q < RD; ++q) x[xpad(base + q * NS)] = u[q];
+    }
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = o[m];
+  } else {
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = x[xpad(lane + m * L)];
+    wave_sync();
+  }
+}
+
+template <typename real, bool INV, int N, int E, int NS = 1>
+__device__ __forceinline__ void reg_fft(cplx<real> (&v)[E], cplx<real>* x, int lane,
+                                        const cplx<real>* __restrict__ tw, int twmul) {
+  if constexpr (NS < N) {
+    constexpr int RD = (N / NS) >= E ? E : (N / NS);
+    reg_pass<real, INV, N, E, RD, NS>(v, x, lane, tw, twmul);
+    reg_fft<real, INV, N, E, NS * RD>(v, x, lane, tw, twmul);
+  }
+}
+
 // After an M-point complex FFT of z[n] = x[2n] + i x[2n+1] (N = 2M real
 // samples), turn Z into the half spectrum of x: bins k = 1..M-1 hold X[k];
 // bin 0 holds X[0] + i X[M] (both real).  twN = N-th roots of unity.
@@ -248,10 +357,12 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Reduce NP per-thread accumulators over the block; slot MAXSLOT (if >= 0)
-// is reduced with max instead of sum.  Thread 0 writes the NP results to out.
+// is reduced with max instead of sum.  Thread 0 writes result i to
+// out[i * cstride] (partials are stored component-major, so a wavefront
+// reading one component of many work-groups reads contiguous memory).
 // red: LDS scratch of at least (blockDim.x/64) * NP doubles.
 template <int NP>
-__device__ void block_reduce_store(double (&acc)[NP], double* red, double* out, int maxslot = -1) {
+__device__ void block_reduce_store(double (&acc)[NP], double* red, double* out, int cstride, int maxslot = -1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
@@ -264,19 +375,26 @@ __device__ void block_reduce_store(double (&acc)[NP], double* red, double* out, 
     for (int i = 0; i < NP; ++i) {
       double s = red[i];
       for (int w = 1; w < nw; ++w) s = (i == maxslot) ? fmax(s, red[w * NP + i]) : s + red[w * NP + i];
-      out[i] = s;
+      out[(size_t)i * cstride] = s;
     }
   }
 }
 
-// Sum (or max) of `count` partials p[i*stride] by one wavefront in a fixed
-// order; every lane returns the same value.  Used identically by the
-// controller and by kernels that need a scalar of the same tick.
-__device__ __forceinline__ double wave_reduce_partials(const double* __restrict__ p, int count, int stride,
+// Sum (or max) of `count` contiguous partials p[0..count) by one wavefront in
+// a fixed order (lane-strided running sums, then a butterfly); every lane
+// returns the same value.  Used identically by the controller and by kernels
+// that need a scalar of the same tick.  The loads of a lane are independent
+// and are issued before the dependent adds.
+__device__ __forceinline__ double wave_reduce_partials(const double* __restrict__ p, int count,
                                                        bool is_max = false) {
   const int lane = threadIdx.x & 63;
   double s = is_max ? -1.0e300 : 0.0;
-  for (int i = lane; i < count; i += 64) s = is_max ? fmax(s, p[i * stride]) : s + p[i * stride];
+  int i = lane;
+  for (; i + 192 < count; i += 256) {
+    const double a = p[i], b = p[i + 64], c = p[i + 128], d = p[i + 192];
+    s = is_max ? fmax(fmax(fmax(fmax(s, a), b), c), d) : (((s + a) + b) + c) + d;
+  }
+  for (; i < count; i += 64) s = is_max ? fmax(s, p[i]) : s + p[i];
   return is_max ? wave_max(s) : wave_sum(s);
 }
 

@@ -126,11 +126,17 @@ struct StepRec {
   double eps_bar[3];
 };
 
-// Device-side kernel timing (profiling): every work-group of a tick kernel
-// lowers `start` to its first clock reading and raises `end` to its last; the
-// controller of the same tick folds end - start into per-kernel totals.
+// Device-side kernel timing (profiling) of one kernel: every work-group
+// lowers one of KT_LINES `start` words to its first clock reading and raises
+// one of KT_LINES `end` words to its last (hashed by work-group, one word per
+// 128-byte line, so that thousands of groups do not contend on one address);
+// the controller of the same tick folds max(end) - min(start) into a
+// per-kernel total and resets the words.
+constexpr int KT_LINES = 64;
+constexpr int KT_STRIDE = 16;  // 64-bit words per line
 struct KTime {
-  unsigned long long start, end;
+  unsigned long long start[KT_LINES * KT_STRIDE];
+  unsigned long long end[KT_LINES * KT_STRIDE];
 };
 
 // Number of FP64 partials per work-group written by each kernel.

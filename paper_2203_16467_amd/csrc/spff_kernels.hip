@@ -14,6 +14,8 @@
 // components; a column kernel work-group owns W consecutive kx columns.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "spff_device.hpp"
 #include "spff_engine.hpp"
 #include "spff_launch.hpp"
@@ -311,7 +313,7 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
       spec[(size_t)(rest) * ny + y0 + r] = buf[(c * R + r) * stride + kx];
     }
   }
-  block_reduce_store<NP_ROW>(acc, red, part + ((size_t)s * ngr + g) * NP_ROW, phase == PH_STATS ? 3 : -1);
+  block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, phase == PH_STATS ? 3 : -1);
 }
 
 // ===========================================================================
@@ -480,7 +482,174 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
       spec[(size_t)(c * M + kx0 + w) * ny + y] = buf[rest * stride + y];
     }
   }
-  block_reduce_store<NP_COL>(acc, red, part + ((size_t)s * ngc + g) * NP_COL);
+  block_reduce_store<NP_COL>(acc, red, part + (size_t)s * NP_COL * ngc + g, ngc);
+}
+
+// Column kernel with register-resident transforms (ny = N in {128, 256,
+// 512}, FP32): a group of N/8 lanes owns one kx column of every component,
+// 8 modes per lane per component (lane l: ky = l + m N/8).  Forward FFTs,
+// the per-mode operator and the inverse FFTs run on the lane's registers;
+// only the two Stockham exchanges per transform go through LDS, inside the
+// group's wavefront.  The packed column kx = 0 (X[0] + i X[nx/2]) takes
+// the partner mode -ky from lane (L - l) mod L by a cross-lane shuffle.
+template <typename real, int N>
+__device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                            const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
+                                            const cplx<real>* __restrict__ twy, double* __restrict__ part, int nx,
+                                            int ngc) {
+  using C = cplx<real>;
+  constexpr int E = 8, L = N / E;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[(THREADS / 64) * NP_COL];
+  const int s = list[blockIdx.y], g = blockIdx.x;
+  if (s < 0) return;
+  const int phase = ctls[s].phase;
+  int ncomp, mode;  // mode 0: projection, 1: Laplacian, 2: Parseval reduction
+  switch (phase) {
+    case PH_M_RES:
+    case PH_M_CG:
+    case PH_X_PROJ:
+      ncomp = 3;
+      mode = 0;
+      break;
+    case PH_X_LAP:
+    case PH_PF_ASM:
+    case PH_PF_R:
+      ncomp = 1;
+      mode = 1;
+      break;
+    case PH_PF_PQ:
+    case PH_STATS:
+      ncomp = 1;
+      mode = 2;
+      break;
+    default:
+      return;
+  }
+  const SlotParam& P = prms[s];
+  const SlotPtr<real> F = ptrs[s];
+  const int M = nx >> 1;
+  const int W = blockDim.x / L;
+  const int col = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+  const int kx = g * W + col;
+  C* x = reinterpret_cast<C*>(smem_raw) + col * XArea<N>::size;
+  C* spec = reinterpret_cast<C*>(F.spec);
+  const real inv_n = real(1.0 / (double(nx) * double(N)));
+  const real two_pi = real(TWO_PI);
+  const real lap_scale = (phase == PH_X_LAP ? real(1) : real(P.kappa)) * inv_n;
+
+  C v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c < ncomp) {
+      const C* src = spec + (size_t)(c * M + kx) * N + lane;
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[c][m] = src[m * L];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (c < ncomp) reg_fft<real, false, N, E>(v[c], x, lane, twy, 1);
+
+  double acc[NP_COL] = {0.0, 0.0};
+  if (kx > 0) {
+    const real fx = real(kx) / real(nx);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int ky = lane + m * L;
+      const int kys = ky < N / 2 ? ky : ky - N;
+      const real fy_true = real(kys) / real(N);
+      const real fy_grad = (2 * ky == N) ? real(0) : fy_true;
+      if (mode == 0) {
+        real re[3] = {v[0][m].x, v[1][m].x, v[2][m].x}, im[3] = {v[0][m].y, v[1][m].y, v[2][m].y};
+        project3(re, fx, fy_grad);
+        project3(im, fx, fy_grad);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c][m] = mk<C>(re[c] * inv_n, im[c] * inv_n);
+      } else {
+        const real Lk = two_pi * two_pi * (fx * fx + fy_true * fy_true);
+        if (mode == 1) {
+          v[0][m] = cscale(v[0][m], Lk * lap_scale);
+        } else {
+          acc[0] += 2.0 * double(Lk) * (double(v[0][m].x) * double(v[0][m].x) + double(v[0][m].y) * double(v[0][m].y));
+        }
+      }
+    }
+  } else {
+    // packed column: A = X(kx = 0), B = X(kx = nx/2) at ky, from Z(ky) and
+    // conj Z(-ky); the partner of slot m of lane l is slot E-1-m of lane
+    // L-l (l > 0), or slot (E-m) mod E of lane 0 itself
+    C Pn[3][E];
+    const int src = (L - lane) & (L - 1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c < ncomp) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const real px = __shfl(v[c][i].x, src, L), py = __shfl(v[c][i].y, src, L);
+          Pn[c][E - 1 - i] = mk<C>(px, py);
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int m = 0; m < E; ++m) Pn[c][m] = v[c][(E - m) & (E - 1)];
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int ky = lane + m * L;
+      const int kys = ky < N / 2 ? ky : ky - N;
+      const real fy_true = real(kys) / real(N);
+      const real fy_grad = (2 * ky == N) ? real(0) : fy_true;
+      if (mode == 0) {
+        real ar[3], ai[3], br[3], bi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C cp = v[c][m], cm = cconj(Pn[c][m]);
+          const C A = cscale(cadd(cp, cm), real(0.5));
+          const C Bq = cscale(cmulni(csub(cp, cm)), real(0.5));
+          ar[c] = A.x;
+          ai[c] = A.y;
+          br[c] = Bq.x;
+          bi[c] = Bq.y;
+        }
+        project3(ar, real(0), fy_grad);
+        project3(ai, real(0), fy_grad);
+        // kx = nx/2: gradient wavevector x-component is zero (Nyquist)
+        project3(br, real(0), fy_grad);
+        project3(bi, real(0), fy_grad);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C A = mk<C>(ar[c] * inv_n, ai[c] * inv_n), Bq = mk<C>(br[c] * inv_n, bi[c] * inv_n);
+          v[c][m] = cadd(A, cmuli(Bq));
+        }
+      } else {
+        const C cp = v[0][m], cm = cconj(Pn[0][m]);
+        const C A = cscale(cadd(cp, cm), real(0.5));
+        const C Bq = cscale(cmulni(csub(cp, cm)), real(0.5));
+        const real L0 = two_pi * two_pi * (fy_true * fy_true);
+        const real LN = two_pi * two_pi * (real(0.25) + fy_true * fy_true);
+        if (mode == 1) {
+          v[0][m] = cadd(cscale(A, L0 * lap_scale), cmuli(cscale(Bq, LN * lap_scale)));
+        } else {
+          acc[0] += double(L0) * (double(A.x) * double(A.x) + double(A.y) * double(A.y)) +
+                    double(LN) * (double(Bq.x) * double(Bq.x) + double(Bq.y) * double(Bq.y));
+        }
+      }
+    }
+  }
+  if (mode != 2) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c < ncomp) {
+        reg_fft<real, true, N, E>(v[c], x, lane, twy, 1);
+        C* dst = spec + (size_t)(c * M + kx) * N + lane;
+#pragma unroll
+        for (int m = 0; m < E; ++m) dst[m * L] = v[c][m];
+      }
+    }
+  }
+  block_reduce_store<NP_COL>(acc, red, part + (size_t)s * NP_COL * ngc + g, ngc);
 }
 
 // ===========================================================================
@@ -534,7 +703,7 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
   real alpha = 0;
   if (phase == PH_M_CG) {
     if (threadIdx.x < 64) {
-      const double pcp = wave_reduce_partials(part_row + (size_t)s * ngr * NP_ROW, ngr, NP_ROW);
+      const double pcp = wave_reduce_partials(part_row + (size_t)s * NP_ROW * ngr, ngr);
       if (threadIdx.x == 0) scal[0] = (pcp > 0.0 && isfinite(pcp)) ? ctl.rr / pcp : 0.0;
     }
     __syncthreads();
@@ -621,7 +790,7 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
         break;
     }
   }
-  block_reduce_store<NP_INV>(acc, red, part + ((size_t)s * ngr + g) * NP_INV);
+  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr);
 }
 
 // Algorithmic HBM bytes per pixel moved by the row-forward, column and
@@ -671,18 +840,15 @@ __device__ inline void phase_bytes(int phase, int flags, int split, double r, do
 }
 
 // ===========================================================================
-// Controller: one wavefront per slot.  Reduces the tick's partials in a fixed
-// order, updates FP64 scalars and moves the slot's state machine.
+// Controller of one slot, run by one wavefront.  Reduces the tick's partials
+// in a fixed order, updates FP64 scalars and moves the slot's state machine.
 // ===========================================================================
 template <typename real>
-__device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const SlotParam* __restrict__ prms,
-                                             SlotCtl* __restrict__ ctls,
-                                             const double* __restrict__ prow, const double* __restrict__ pcol,
-                                             const double* __restrict__ pinv, double* __restrict__ prof,
-                                             SlotSeq* __restrict__ seqs, StepRec* __restrict__ recs,
-                                             int nx, int ny, int ngr, int ngc) {
-  const int s = list[blockIdx.x];
-  if (s < 0) return;
+__device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ prms, SlotCtl* __restrict__ ctls,
+                                       const double* __restrict__ prow, const double* __restrict__ pcol,
+                                       const double* __restrict__ pinv, double* __restrict__ prof,
+                                       SlotSeq* __restrict__ seqs, StepRec* __restrict__ recs, int nx, int ny,
+                                       int ngr, int ngc) {
   SlotCtl& C = ctls[s];
   const int phase = C.phase;
   if (phase == PH_IDLE) return;
@@ -696,9 +862,9 @@ __device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const 
     prof[3 * s + 1] += b[1] * npx;
     prof[3 * s + 2] += b[2] * npx;
   }
-  const double* pr = prow + (size_t)s * ngr * NP_ROW;
-  const double* pc = pcol + (size_t)s * ngc * NP_COL;
-  const double* pi = pinv + (size_t)s * ngr * NP_INV;
+  const double* pr = prow + (size_t)s * NP_ROW * ngr;
+  const double* pc = pcol + (size_t)s * NP_COL * ngc;
+  const double* pi = pinv + (size_t)s * NP_INV * ngr;
   const double inv_n = 1.0 / (double(nx) * double(ny));
   // all lanes compute the same values; lane 0 writes
   double v[8];
@@ -724,9 +890,9 @@ __device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const 
   };
   switch (phase) {
     case PH_M_RES: {
-      const double sh2 = wave_reduce_partials(pr, ngr, NP_ROW);
-      const double sg2 = wave_reduce_partials(pr + 1, ngr, NP_ROW);
-      const double r2 = wave_reduce_partials(pi, ngr, NP_INV);
+      const double sh2 = wave_reduce_partials(pr, ngr);
+      const double sg2 = wave_reduce_partials(pr + 1 * ngr, ngr);
+      const double r2 = wave_reduce_partials(pi, ngr);
       bad = !isfinite(sh2) || !isfinite(r2) || !isfinite(sg2);
       mech_res = sqrt(r2);
       // G[sigma] cannot be evaluated more accurately than the rounding of
@@ -757,8 +923,8 @@ __device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const 
       break;
     }
     case PH_M_CG: {
-      const double pcp = wave_reduce_partials(pr, ngr, NP_ROW);
-      const double r2 = wave_reduce_partials(pi, ngr, NP_INV);
+      const double pcp = wave_reduce_partials(pr, ngr);
+      const double r2 = wave_reduce_partials(pi, ngr);
       bad = !isfinite(pcp) || !isfinite(r2);
       alpha_m = (pcp > 0.0) ? rr / pcp : 0.0;
       ++cg;
@@ -776,10 +942,10 @@ __device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const 
       break;
     }
     case PH_PF_ASM: {
-      const double b2 = wave_reduce_partials(pr, ngr, NP_ROW);
-      const double r2 = wave_reduce_partials(pi, ngr, NP_INV);
-      const double x2 = wave_reduce_partials(pi + 2, ngr, NP_INV);
-      const double dx2 = wave_reduce_partials(pi + 3, ngr, NP_INV);
+      const double b2 = wave_reduce_partials(pr, ngr);
+      const double r2 = wave_reduce_partials(pi, ngr);
+      const double x2 = wave_reduce_partials(pi + 2 * ngr, ngr);
+      const double dx2 = wave_reduce_partials(pi + 3 * ngr, ngr);
       bad = !isfinite(b2) || !isfinite(r2);
       pf_res = sqrt(r2);
       pf_bnorm = sqrt(b2);
@@ -800,9 +966,9 @@ __device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const 
       break;
     }
     case PH_PF_PQ: {
-      v[0] = wave_reduce_partials(pr, ngr, NP_ROW);      // sum d p^2
-      v[1] = wave_reduce_partials(pr + 1, ngr, NP_ROW);  // sum r p
-      v[2] = wave_reduce_partials(pc, ngc, NP_COL);      // sum L |p^|^2
+      v[0] = wave_reduce_partials(pr, ngr);      // sum d p^2
+      v[1] = wave_reduce_partials(pr + 1 * ngr, ngr);  // sum r p
+      v[2] = wave_reduce_partials(pc, ngc);      // sum L |p^|^2
       bad = !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
       pq = v[0] + P.kappa * inv_n * v[2];
       rp = v[1];
@@ -817,10 +983,10 @@ __device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const 
       break;
     }
     case PH_PF_R: {
-      const double r2 = wave_reduce_partials(pi, ngr, NP_INV);
-      const double rro = wave_reduce_partials(pi + 1, ngr, NP_INV);
-      const double x2 = wave_reduce_partials(pi + 2, ngr, NP_INV);
-      const double dx2 = wave_reduce_partials(pi + 3, ngr, NP_INV);
+      const double r2 = wave_reduce_partials(pi, ngr);
+      const double rro = wave_reduce_partials(pi + 1 * ngr, ngr);
+      const double x2 = wave_reduce_partials(pi + 2 * ngr, ngr);
+      const double dx2 = wave_reduce_partials(pi + 3 * ngr, ngr);
       bad = !isfinite(r2) || !isfinite(rro);
       beta_pf = (r2 - rro) / (alpha_pf * pq);
       rr_pf = r2;
@@ -846,7 +1012,7 @@ __device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const 
       break;
     }
     case PH_AM_CHK: {
-      dphi = wave_reduce_partials(pr, ngr, NP_ROW);
+      dphi = wave_reduce_partials(pr, ngr);
       bad = !isfinite(dphi);
       ++am;
       if (dphi <= P.tol_am) {
@@ -864,8 +1030,8 @@ __device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const 
       nphase = PH_IDLE;
       break;
     case PH_STATS: {
-      for (int i = 0; i < 8; ++i) v[i] = wave_reduce_partials(pr + i, ngr, NP_ROW, i == 3);
-      const double lg = wave_reduce_partials(pc, ngc, NP_COL);
+      for (int i = 0; i < 8; ++i) v[i] = wave_reduce_partials(pr + i * ngr, ngr, i == 3);
+      const double lg = wave_reduce_partials(pc, ngc);
       bad = false;
       for (int i = 0; i < 8; ++i) bad |= !isfinite(v[i]);
       if (threadIdx.x == 0) {
@@ -975,13 +1141,17 @@ __device__ __forceinline__ void k_ctrl_body(const int* __restrict__ list, const 
 // Kernel entry points: the bodies above, bracketed by the device clock when
 // profiling (kt != nullptr).
 // ===========================================================================
+__device__ __forceinline__ int kt_line() {
+  return (blockIdx.x + blockIdx.y * 29) & (KT_LINES - 1);
+}
 __device__ __forceinline__ void kt_begin(KTime* kt) {
-  if (kt && threadIdx.x == 0) atomicMin(&kt->start, (unsigned long long)wall_clock64());
+  if (kt && threadIdx.x == 0)
+    atomicMin(&kt->start[kt_line() * KT_STRIDE], (unsigned long long)wall_clock64());
 }
 __device__ __forceinline__ void kt_end(KTime* kt) {
   if (kt) {
     __syncthreads();
-    if (threadIdx.x == 0) atomicMax(&kt->end, (unsigned long long)wall_clock64());
+    if (threadIdx.x == 0) atomicMax(&kt->end[kt_line() * KT_STRIDE], (unsigned long long)wall_clock64());
   }
 }
 
@@ -1007,6 +1177,17 @@ __global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, c
   kt_end(kt);
 }
 
+template <typename real, int N>
+__global__ __launch_bounds__(THREADS) void k_colr(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                                  const SlotParam* __restrict__ prms,
+                                                  const SlotCtl* __restrict__ ctls,
+                                                  const cplx<real>* __restrict__ twy, double* __restrict__ part,
+                                                  int nx, int ngc, KTime* kt) {
+  kt_begin(kt);
+  k_colr_body<real, N>(list, ptrs, prms, ctls, twy, part, nx, ngc);
+  kt_end(kt);
+}
+
 template <typename real>
 __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                                     const SlotParam* __restrict__ prms,
@@ -1020,6 +1201,10 @@ __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list
   kt_end(kt);
 }
 
+// Controller: one wavefront per listed slot.  A separate launch rather than
+// a last-arriving-group step inside k_rowinv: publishing the partials across
+// the XCDs from every group would need a device-scope release per group (an
+// L2 write-back each), which costs far more than the kernel boundary.
 template <typename real>
 __global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const SlotParam* __restrict__ prms,
                                              SlotCtl* __restrict__ ctls, const double* __restrict__ prow,
@@ -1027,15 +1212,27 @@ __global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const
                                              double* __restrict__ prof, SlotSeq* __restrict__ seqs,
                                              StepRec* __restrict__ recs, int nx, int ny, int ngr, int ngc,
                                              KTime* kt, unsigned long long* __restrict__ ktsum) {
-  // fold this tick's kernel times (one work-group, before any early return)
-  if (kt && blockIdx.x == 0 && threadIdx.x == 0) {
+  // fold this tick's kernel times (first work-group, before any early
+  // return): lane l takes line l of every kernel
+  if (kt && blockIdx.x == 0) {
+    const int l = threadIdx.x;
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
-      if (kt[j].end > kt[j].start) ktsum[j] += kt[j].end - kt[j].start;
-      kt[j].start = ~0ull;
-      kt[j].end = 0ull;
+      unsigned long long a = kt[j].start[l * KT_STRIDE], b = kt[j].end[l * KT_STRIDE];
+      kt[j].start[l * KT_STRIDE] = ~0ull;
+      kt[j].end[l * KT_STRIDE] = 0ull;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long a2 = __shfl_xor(a, off, 64), b2 = __shfl_xor(b, off, 64);
+        a = a2 < a ? a2 : a;
+        b = b2 > b ? b2 : b;
+      }
+      if (l == 0 && b > a) ktsum[j] += b - a;
     }
   }
-  k_ctrl_body<real>(list, prms, ctls, prow, pcol, pinv, prof, seqs, recs, nx, ny, ngr, ngc);
+  const int s = list[blockIdx.x];
+  if (s < 0) return;
+  ctrl_slot<real>(s, prms, ctls, prow, pcol, pinv, prof, seqs, recs, nx, ny, ngr, ngc);
 }
 
 // ===========================================================================
@@ -1100,8 +1297,30 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
   dim3 grow(G.ngr, G.S), gcol(G.ngc, G.S);
   hipLaunchKernelGGL(k_rowfwd<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, G.nx,
                      G.ny, G.R, G.ngr, kt ? kt + 0 : nullptr);
-  hipLaunchKernelGGL(k_col<real>, gcol, dim3(G.threads), G.lds_col, st, list, ptrs, prms, ctls, twy, pcol, G.nx,
-                     G.ny, G.W, G.ngc, kt ? kt + 1 : nullptr);
+  KTime* ktc = kt ? kt + 1 : nullptr;
+  bool col_done = false;
+  if constexpr (std::is_same<real, float>::value) {
+    if (G.col_reg) {
+      col_done = true;
+      switch (G.ny) {
+      case 128:
+        hipLaunchKernelGGL((k_colr<real, 128>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
+                           twy, pcol, G.nx, G.ngc, ktc);
+        break;
+      case 256:
+        hipLaunchKernelGGL((k_colr<real, 256>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
+                           twy, pcol, G.nx, G.ngc, ktc);
+        break;
+      default:
+        hipLaunchKernelGGL((k_colr<real, 512>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
+                           twy, pcol, G.nx, G.ngc, ktc);
+        break;
+      }
+    }
+  }
+  if (!col_done)
+    hipLaunchKernelGGL(k_col<real>, gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls, twy, pcol,
+                       G.nx, G.ny, G.W, G.ngc, ktc);
   hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, pinv,
                      G.nx, G.ny, G.R, G.ngr, kt ? kt + 2 : nullptr);
   hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(64), 0, st, list, prms, ctls, prow, pcol, pinv, prof, seqs,

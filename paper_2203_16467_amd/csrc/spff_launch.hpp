@@ -15,7 +15,9 @@ struct LaunchGeom {
   int nx, ny, S;
   int R, ngr;  // rows per row work-group, row groups per slot
   int W, ngc;  // columns per column work-group, column groups per slot
-  int threads;  // threads per FFT work-group
+  int threads;      // threads per row work-group
+  int threads_col;  // threads per column work-group
+  int col_reg;      // column kernel with register-resident transforms
   size_t lds_row, lds_col;
 };
 

@@ -296,11 +296,12 @@ def test_profile_counters():
     p.profile_enable(True)
     p.run_sequence(ramp[3:6])
     prof = p.profile_read()
-    assert prof["ticks"] > 0 and all(v > 0 for v in prof["launches"].values())
+    ffts = ("rowfwd", "col", "rowinv")
+    assert prof["ticks"] > 0 and all(v == prof["ticks"] for v in prof["launches"].values())
     assert prof["alg_bytes"]["rowfwd"] > 0 and prof["alg_bytes"]["col"] > 0
     # device-clock execution times of the three FFT kernels (also inside the
     # captured graphs); the controller is not timed
-    assert all(prof["kernel_ms"][k] > 0 for k in ("rowfwd", "col", "rowinv"))
+    assert all(prof["kernel_ms"][k] > 0 for k in ffts)
     assert prof["kernel_ms"]["ctrl"] == 0
     # per launch, a 64x64 tick kernel runs for well under a millisecond
     assert prof["kernel_ms"]["col"] / prof["launches"]["col"] < 1.0
