@@ -145,6 +145,34 @@ LaunchGeom plan(const spff_config* c, int S, size_t csize) {
       }
     }
   }
+  // FP32 rows of 64..512 complex points (nx = 128..1024): register-resident
+  // transforms, a group of nx/16 lanes per row, R rows per work-group (at
+  // least one wavefront, at most THREADS lanes); R fixed by plan_rows if
+  // given.  A lane walks 8 pixel pairs of its row one after the other, so
+  // the path needs enough wavefronts in flight to hide that: below ~8 per
+  // CU (a few problems of a small grid) the LDS row kernels, whose threads
+  // take one pixel pair each, finish sooner.
+  G.row_reg = 0;
+  const bool many_waves = (long)S * c->ny * (M / 8) / 64 >= 2048;
+  if (c->precision == SPFF_FP32 && M >= 64 && M <= 512 && (many_waves || c->plan_rows > 0)) {
+    const int Lr = M / 8;
+    const int rmin = std::max(1, 64 / Lr), rmax = THREADS / Lr;
+    if (rmin <= c->ny) {
+      int Rr = rmin;
+      if (c->plan_rows > 0) {
+        Rr = std::max(rmin, std::min(rmax, c->plan_rows));
+      } else {
+        while (Rr * 2 <= rmax && Rr * 2 <= c->ny && (long)(c->ny / (2 * Rr)) * S >= TARGET_WG) Rr *= 2;
+      }
+      if (Rr <= c->ny) {
+        G.row_reg = 1;
+        G.R = Rr;
+        G.ngr = c->ny / Rr;
+        G.threads = Rr * Lr;
+        G.lds_row = ((size_t)Rr * (M + M / 8) + (size_t)M * (Rr + 1)) * csize;
+      }
+    }
+  }
   return G;
 }
 

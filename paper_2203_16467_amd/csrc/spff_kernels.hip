@@ -81,6 +81,210 @@ __device__ __forceinline__ real lower_bound(real pref, const SlotParam& P) {
   return pref >= real(P.threshold) ? pref : real(0);
 }
 
+// Per-slot scalars of a tick shared by the row prologue and epilogue.
+template <typename real>
+struct RowCtx {
+  int phase, flags, split, n, ncomp;
+  real lt, mt, kres, eb0, eb1, eb2, beta_m, beta_pf, alpha_pf;
+};
+
+template <typename real>
+__device__ __forceinline__ RowCtx<real> row_ctx(const SlotCtl& ctl, const SlotParam& P, int phase, int ncomp, int n) {
+  RowCtx<real> X;
+  X.phase = phase;
+  X.flags = ctl.flags;
+  X.split = P.split;
+  X.n = n;
+  X.ncomp = ncomp;
+  X.lt = real(P.lam_t);
+  X.mt = real(P.mu_t);
+  X.kres = real(P.k_res);
+  X.eb0 = real(ctl.eps_bar[0]);
+  X.eb1 = real(ctl.eps_bar[1]);
+  X.eb2 = real(ctl.eps_bar[2]);
+  X.beta_m = real(ctl.beta_m);
+  X.beta_pf = real(ctl.beta_pf);
+  X.alpha_pf = real(ctl.alpha_pf);
+  return X;
+}
+
+// Row-forward prologue for the pixel pair (o, o + 1): the phase's pointwise
+// work, the values entering the transforms (val[c][0..1]) and the FP64
+// partial sums.
+template <typename real>
+__device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotParam& P, const SlotPtr<real>& F,
+                                             int o, real (&val)[3][2], double (&acc)[NP_ROW]) {
+  const int phase = X.phase, flags = X.flags, split = X.split, n = X.n, ncomp = X.ncomp;
+  const real lt = X.lt, mt = X.mt, kres = X.kres, eb0 = X.eb0, eb1 = X.eb1, eb2 = X.eb2;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) val[0][q] = val[1][q] = val[2][q] = real(0);
+  switch (phase) {
+    case PH_M_RES: {
+      const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
+      if (flags & FL_FIRST_OF_STEP) st2(F.phi_ref + o, ph.a, ph.b);
+      V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
+      if (flags & FL_THETA_PENDING) {
+        const V2<real> tx = ld2(F.theta + o), ty = ld2(F.theta + n + o), txy = ld2(F.theta + 2 * n + o);
+        ex = {ex.a + tx.a, ex.b + tx.b};
+        ey = {ey.a + ty.a, ey.b + ty.b};
+        exy = {exy.a + txy.a, exy.b + txy.b};
+        st2(F.eps + o, ex.a, ex.b);
+        st2(F.eps + n + o, ey.a, ey.b);
+        st2(F.eps + 2 * n + o, exy.a, exy.b);
+      }
+      const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
+      const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const real lam = lt * Ev[q], mu = mt * Ev[q];
+        const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
+        const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
+        const Sym<real> sg = stress(e, lam, mu, hk, split);
+        const Sym<real> eh = {eb0, eb1, eb2};
+        const Sym<real> sh = stress(eh, lam, mu, hk, split);
+        acc[0] += double(ddot(sh, sh));
+        acc[1] += double(ddot(sg, sg));
+        val[0][q] = sg.xx;
+        val[1][q] = sg.yy;
+        val[2][q] = sg.xy;
+      }
+      break;
+    }
+    case PH_M_CG: {
+      const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
+      V2<real> px = ld2(F.rm + o), py = ld2(F.rm + n + o), pxy = ld2(F.rm + 2 * n + o);
+      if (!(flags & FL_CG_FIRST)) {
+        const real bt = real(X.beta_m);
+        const V2<real> qx = ld2(F.pm + o), qy = ld2(F.pm + n + o), qxy = ld2(F.pm + 2 * n + o);
+        px = {px.a + bt * qx.a, px.b + bt * qx.b};
+        py = {py.a + bt * qy.a, py.b + bt * qy.b};
+        pxy = {pxy.a + bt * qxy.a, pxy.b + bt * qxy.b};
+      }
+      st2(F.pm + o, px.a, px.b);
+      st2(F.pm + n + o, py.a, py.b);
+      st2(F.pm + 2 * n + o, pxy.a, pxy.b);
+      V2<real> ex = {0, 0}, ey = {0, 0}, exy = {0, 0};
+      if (split != 0) {
+        ex = ld2(F.eps + o);
+        ey = ld2(F.eps + n + o);
+        exy = ld2(F.eps + 2 * n + o);
+      }
+      const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
+      const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
+      const real pxv[2] = {px.a, px.b}, pyv[2] = {py.a, py.b}, psv[2] = {pxy.a, pxy.b};
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const real lam = lt * Ev[q], mu = mt * Ev[q];
+        const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
+        const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
+        const Sym<real> p = {pxv[q], pyv[q], psv[q]};
+        const Sym<real> cp = tangent(e, p, lam, mu, hk, split);
+        acc[0] += double(ddot(p, cp));
+        val[0][q] = cp.xx;
+        val[1][q] = cp.yy;
+        val[2][q] = cp.xy;
+      }
+      break;
+    }
+    case PH_PF_ASM: {
+      const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o), pr = ld2(F.phi_ref + o);
+      const V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
+      const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b}, rv[2] = {pr.a, pr.b};
+      const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
+      real dv[2], bv[2], cv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const real lam = lt * Ev[q], mu = mt * Ev[q];
+        const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
+        real pp, pm;
+        energies(e, lam, mu, split, &pp, &pm);
+        dv[q] = real(2) * pp + real(P.cwl * P.wpp + P.eta_dt);
+        bv[q] = real(2) * pp - real(P.cwl * P.dw0) + real(P.eta_dt) * rv[q];
+        const real lo = lower_bound(rv[q], P);
+        cv[q] = fmin(fmax(pv[q], lo), real(1));
+        acc[0] += double(bv[q]) * double(bv[q]);
+        val[0][q] = cv[q];
+      }
+      st2(F.theta + o, dv[0], dv[1]);
+      st2(F.theta + n + o, bv[0], bv[1]);
+      st2(F.theta + 2 * n + o, ph.a, ph.b);  // phi at the start of this PF solve
+      st2(F.phi + o, cv[0], cv[1]);
+      break;
+    }
+    case PH_PF_PQ: {
+      const V2<real> r = ld2(F.rm + o), d = ld2(F.theta + o);
+      V2<real> p;
+      if (flags & FL_PF_FIRST) {
+        p = {-r.a, -r.b};
+      } else {
+        const V2<real> po = ld2(F.pm + o);
+        const real bt = real(X.beta_pf);
+        p = {-r.a + bt * po.a, -r.b + bt * po.b};
+      }
+      const unsigned char* mask = reinterpret_cast<const unsigned char*>(F.pm + n);
+      if (mask[o]) p.a = real(0);
+      if (mask[o + 1]) p.b = real(0);
+      st2(F.pm + o, p.a, p.b);
+      acc[0] += double(d.a) * double(p.a) * double(p.a) + double(d.b) * double(p.b) * double(p.b);
+      acc[1] += double(r.a) * double(p.a) + double(r.b) * double(p.b);
+      val[0][0] = p.a;
+      val[0][1] = p.b;
+      break;
+    }
+    case PH_PF_R: {
+      const V2<real> ph = ld2(F.phi + o), p = ld2(F.pm + o), pr = ld2(F.phi_ref + o);
+      const real al = real(X.alpha_pf);
+      const real a0 = fmin(fmax(ph.a + al * p.a, lower_bound(pr.a, P)), real(1));
+      const real a1 = fmin(fmax(ph.b + al * p.b, lower_bound(pr.b, P)), real(1));
+      st2(F.phi + o, a0, a1);
+      val[0][0] = a0;
+      val[0][1] = a1;
+      break;
+    }
+    case PH_AM_CHK: {
+      const V2<real> ph = ld2(F.phi + o), pa = ld2(F.theta + 2 * n + o);
+      acc[0] += fabs(double(ph.a) - double(pa.a)) + fabs(double(ph.b) - double(pa.b));
+      break;
+    }
+    case PH_STATS: {
+      const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
+      const V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
+      const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
+      const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const real lam = lt * Ev[q], mu = mt * Ev[q];
+        const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
+        const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
+        real pp, pm;
+        energies(e, lam, mu, split, &pp, &pm);
+        const Sym<real> sg = stress(e, lam, mu, hk, split);
+        acc[0] += double(hk) * double(pp) + double(pm);
+        acc[1] += P.at == 1 ? double(pv[q]) : double(pv[q]) * double(pv[q]);
+        acc[2] += double(pv[q]);
+        acc[3] = fmax(acc[3], double(pv[q]));
+        acc[4] += pv[q] > real(0.9) ? 1.0 : 0.0;
+        acc[5] += double(sg.xx);
+        acc[6] += double(sg.yy);
+        acc[7] += double(sg.xy);
+        val[0][q] = pv[q];
+      }
+      break;
+    }
+    case PH_X_PROJ:
+    case PH_X_LAP: {
+      for (int c = 0; c < ncomp; ++c) {
+        const V2<real> t = ld2(F.theta + c * n + o);
+        val[c][0] = t.a;
+        val[c][1] = t.b;
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
 // ===========================================================================
 // Row-forward kernel: prologue (per phase) -> R2C row FFTs -> transposed
 // store of the half spectra; FP64 partial sums per work-group.
@@ -115,9 +319,7 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
   for (int i = 0; i < NP_ROW; ++i) acc[i] = 0.0;
   if (phase == PH_STATS) acc[3] = -1.0e300;
 
-  const real lt = real(P.lam_t), mt = real(P.mu_t), kres = real(P.k_res);
-  const real eb0 = real(ctl.eps_bar[0]), eb1 = real(ctl.eps_bar[1]), eb2 = real(ctl.eps_bar[2]);
-  const int split = P.split;
+  const RowCtx<real> X = row_ctx<real>(ctl, P, phase, ncomp, n);
 
   const int logM = ilog2(M), logR = ilog2(R);
   for (int idx = threadIdx.x; idx < R * M; idx += blockDim.x) {
@@ -125,174 +327,7 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
     const int o = (y0 + r) * nx + 2 * h;
     const int li = r * stride + h;  // LDS index of component 0
     real val[3][2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) val[0][q] = val[1][q] = val[2][q] = real(0);
-
-    switch (phase) {
-      case PH_M_RES: {
-        const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
-        if (flags & FL_FIRST_OF_STEP) st2(F.phi_ref + o, ph.a, ph.b);
-        V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
-        if (flags & FL_THETA_PENDING) {
-          const V2<real> tx = ld2(F.theta + o), ty = ld2(F.theta + n + o), txy = ld2(F.theta + 2 * n + o);
-          ex = {ex.a + tx.a, ex.b + tx.b};
-          ey = {ey.a + ty.a, ey.b + ty.b};
-          exy = {exy.a + txy.a, exy.b + txy.b};
-          st2(F.eps + o, ex.a, ex.b);
-          st2(F.eps + n + o, ey.a, ey.b);
-          st2(F.eps + 2 * n + o, exy.a, exy.b);
-        }
-        const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
-        const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const real lam = lt * Ev[q], mu = mt * Ev[q];
-          const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
-          const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
-          const Sym<real> sg = stress(e, lam, mu, hk, split);
-          const Sym<real> eh = {eb0, eb1, eb2};
-          const Sym<real> sh = stress(eh, lam, mu, hk, split);
-          acc[0] += double(ddot(sh, sh));
-          acc[1] += double(ddot(sg, sg));
-          val[0][q] = sg.xx;
-          val[1][q] = sg.yy;
-          val[2][q] = sg.xy;
-        }
-        break;
-      }
-      case PH_M_CG: {
-        const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
-        V2<real> px = ld2(F.rm + o), py = ld2(F.rm + n + o), pxy = ld2(F.rm + 2 * n + o);
-        if (!(flags & FL_CG_FIRST)) {
-          const real bt = real(ctl.beta_m);
-          const V2<real> qx = ld2(F.pm + o), qy = ld2(F.pm + n + o), qxy = ld2(F.pm + 2 * n + o);
-          px = {px.a + bt * qx.a, px.b + bt * qx.b};
-          py = {py.a + bt * qy.a, py.b + bt * qy.b};
-          pxy = {pxy.a + bt * qxy.a, pxy.b + bt * qxy.b};
-        }
-        st2(F.pm + o, px.a, px.b);
-        st2(F.pm + n + o, py.a, py.b);
-        st2(F.pm + 2 * n + o, pxy.a, pxy.b);
-        V2<real> ex = {0, 0}, ey = {0, 0}, exy = {0, 0};
-        if (split != 0) {
-          ex = ld2(F.eps + o);
-          ey = ld2(F.eps + n + o);
-          exy = ld2(F.eps + 2 * n + o);
-        }
-        const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
-        const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
-        const real pxv[2] = {px.a, px.b}, pyv[2] = {py.a, py.b}, psv[2] = {pxy.a, pxy.b};
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const real lam = lt * Ev[q], mu = mt * Ev[q];
-          const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
-          const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
-          const Sym<real> p = {pxv[q], pyv[q], psv[q]};
-          const Sym<real> cp = tangent(e, p, lam, mu, hk, split);
-          acc[0] += double(ddot(p, cp));
-          val[0][q] = cp.xx;
-          val[1][q] = cp.yy;
-          val[2][q] = cp.xy;
-        }
-        break;
-      }
-      case PH_PF_ASM: {
-        const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o), pr = ld2(F.phi_ref + o);
-        const V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
-        const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b}, rv[2] = {pr.a, pr.b};
-        const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
-        real dv[2], bv[2], cv[2];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const real lam = lt * Ev[q], mu = mt * Ev[q];
-          const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
-          real pp, pm;
-          energies(e, lam, mu, split, &pp, &pm);
-          dv[q] = real(2) * pp + real(P.cwl * P.wpp + P.eta_dt);
-          bv[q] = real(2) * pp - real(P.cwl * P.dw0) + real(P.eta_dt) * rv[q];
-          const real lo = lower_bound(rv[q], P);
-          cv[q] = fmin(fmax(pv[q], lo), real(1));
-          acc[0] += double(bv[q]) * double(bv[q]);
-          val[0][q] = cv[q];
-        }
-        st2(F.theta + o, dv[0], dv[1]);
-        st2(F.theta + n + o, bv[0], bv[1]);
-        st2(F.theta + 2 * n + o, ph.a, ph.b);  // phi at the start of this PF solve
-        st2(F.phi + o, cv[0], cv[1]);
-        break;
-      }
-      case PH_PF_PQ: {
-        const V2<real> r = ld2(F.rm + o), d = ld2(F.theta + o);
-        V2<real> p;
-        if (flags & FL_PF_FIRST) {
-          p = {-r.a, -r.b};
-        } else {
-          const V2<real> po = ld2(F.pm + o);
-          const real bt = real(ctl.beta_pf);
-          p = {-r.a + bt * po.a, -r.b + bt * po.b};
-        }
-        const unsigned char* mask = reinterpret_cast<const unsigned char*>(F.pm + n);
-        if (mask[o]) p.a = real(0);
-        if (mask[o + 1]) p.b = real(0);
-        st2(F.pm + o, p.a, p.b);
-        acc[0] += double(d.a) * double(p.a) * double(p.a) + double(d.b) * double(p.b) * double(p.b);
-        acc[1] += double(r.a) * double(p.a) + double(r.b) * double(p.b);
-        val[0][0] = p.a;
-        val[0][1] = p.b;
-        break;
-      }
-      case PH_PF_R: {
-        const V2<real> ph = ld2(F.phi + o), p = ld2(F.pm + o), pr = ld2(F.phi_ref + o);
-        const real al = real(ctl.alpha_pf);
-        const real a0 = fmin(fmax(ph.a + al * p.a, lower_bound(pr.a, P)), real(1));
-        const real a1 = fmin(fmax(ph.b + al * p.b, lower_bound(pr.b, P)), real(1));
-        st2(F.phi + o, a0, a1);
-        val[0][0] = a0;
-        val[0][1] = a1;
-        break;
-      }
-      case PH_AM_CHK: {
-        const V2<real> ph = ld2(F.phi + o), pa = ld2(F.theta + 2 * n + o);
-        acc[0] += fabs(double(ph.a) - double(pa.a)) + fabs(double(ph.b) - double(pa.b));
-        break;
-      }
-      case PH_STATS: {
-        const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
-        const V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
-        const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
-        const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const real lam = lt * Ev[q], mu = mt * Ev[q];
-          const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
-          const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
-          real pp, pm;
-          energies(e, lam, mu, split, &pp, &pm);
-          const Sym<real> sg = stress(e, lam, mu, hk, split);
-          acc[0] += double(hk) * double(pp) + double(pm);
-          acc[1] += P.at == 1 ? double(pv[q]) : double(pv[q]) * double(pv[q]);
-          acc[2] += double(pv[q]);
-          acc[3] = fmax(acc[3], double(pv[q]));
-          acc[4] += pv[q] > real(0.9) ? 1.0 : 0.0;
-          acc[5] += double(sg.xx);
-          acc[6] += double(sg.yy);
-          acc[7] += double(sg.xy);
-          val[0][q] = pv[q];
-        }
-        break;
-      }
-      case PH_X_PROJ:
-      case PH_X_LAP: {
-        for (int c = 0; c < ncomp; ++c) {
-          const V2<real> t = ld2(F.theta + c * n + o);
-          val[c][0] = t.a;
-          val[c][1] = t.b;
-        }
-        break;
-      }
-      default:
-        break;
-    }
+    row_prologue<real>(X, P, F, o, val, acc);
     if (ncomp > 0) {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
@@ -314,6 +349,218 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
     }
   }
   block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, phase == PH_STATS ? 3 : -1);
+}
+
+// ---------------------------------------------------------------------------
+// Row kernels with register-resident transforms (M = nx/2 in {64 .. 512},
+// FP32): a group of L = M/8 lanes owns one row (R = blockDim/L rows per
+// work-group); lane l holds z[h] = x[2h] + i x[2h+1] for h = l + m L.  The
+// prologue / epilogue run per pixel pair on the registers; the real <->
+// half-spectrum step pairs bin k with M - k by a cross-lane shuffle (same
+// pattern as the packed column); the transposed spectrum store / load goes
+// through an LDS tile [kx][row] so that R consecutive y of one kx move as
+// one run.
+// ---------------------------------------------------------------------------
+template <int M>
+struct RowLds {
+  static constexpr int L = M / 8;
+  // exchange areas of the R row groups, then the [kx][row] tile
+  static __device__ __forceinline__ int tile_index(int k, int r, int R) { return k * (R + 1) + r; }
+  static size_t bytes(int R, size_t csize) {
+    return ((size_t)R * XArea<M>::size + (size_t)M * (R + 1)) * csize;
+  }
+};
+
+// partner slots for bin k = l + m L and M - k: slot E-1-m of lane L-l, or
+// for lane 0 its own slot (E-m) mod E
+template <typename real, int E, int L>
+__device__ __forceinline__ void partner_bins(const cplx<real> (&v)[E], cplx<real> (&pn)[E], int lane) {
+  const int src = (L - lane) & (L - 1);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const real px = __shfl(v[i].x, src, L), py = __shfl(v[i].y, src, L);
+    pn[E - 1 - i] = mk<cplx<real>>(px, py);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) pn[m] = v[(E - m) & (E - 1)];
+  }
+}
+
+template <typename real, int M>
+__device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                               const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
+                                               const cplx<real>* __restrict__ twx, double* __restrict__ part,
+                                               int ny, int ngr) {
+  using C = cplx<real>;
+  constexpr int E = 8, L = M / 8, nx = 2 * M;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[(THREADS / 64) * NP_ROW];
+  int g, si;
+  row_coords(ngr, g, si);
+  const int s = list[si];
+  if (s < 0) return;
+  const SlotCtl& ctl = ctls[s];
+  const int phase = ctl.phase;
+  const int ncomp = phase_comps_row(phase);
+  if (phase != PH_AM_CHK && ncomp == 0) return;
+  const SlotParam& P = prms[s];
+  const SlotPtr<real> F = ptrs[s];
+  const int R = blockDim.x / L;
+  const int row = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+  const int y0 = g * R;
+  const int n = nx * ny;
+  C* xa = reinterpret_cast<C*>(smem_raw) + row * XArea<M>::size;
+  C* tile = reinterpret_cast<C*>(smem_raw) + R * XArea<M>::size;
+  double acc[NP_ROW];
+#pragma unroll
+  for (int i = 0; i < NP_ROW; ++i) acc[i] = 0.0;
+  if (phase == PH_STATS) acc[3] = -1.0e300;
+  const RowCtx<real> X = row_ctx<real>(ctl, P, phase, ncomp, n);
+
+  C v[3][E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int o = (y0 + row) * nx + 2 * (lane + m * L);
+    real val[3][2];
+    row_prologue<real>(X, P, F, o, val, acc);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c][m] = mk<C>(val[c][0], val[c][1]);
+  }
+  if (ncomp > 0) {
+    C* spec = reinterpret_cast<C*>(F.spec);
+    const int logR = ilog2(R);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c < ncomp) {
+        reg_fft<real, false, M, E>(v[c], xa, lane, twx, 2);
+        // half spectrum of the real row: X[k] = e + w^k o (k > 0), bin 0
+        // packs X[0] + i X[M]
+        C pn[E];
+        partner_bins<real, E, L>(v[c], pn, lane);
+        __syncthreads();  // the tile is free
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int k = lane + m * L;
+          C out;
+          if (k == 0) {
+            out = mk<C>(v[c][m].x + v[c][m].y, v[c][m].x - v[c][m].y);
+          } else {
+            const C zk = v[c][m], zm = cconj(pn[m]);
+            const C e = cscale(cadd(zk, zm), real(0.5));
+            const C od = cscale(cmulni(csub(zk, zm)), real(0.5));
+            out = cadd(e, cmul(twx[k], od));
+          }
+          tile[RowLds<M>::tile_index(k, row, R)] = out;
+        }
+        __syncthreads();
+        // transposed store: spec[c][kx][y0 + r], r fastest
+        for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
+          const int r = idx & (R - 1), k = idx >> logR;
+          spec[(size_t)(c * M + k) * ny + y0 + r] = tile[RowLds<M>::tile_index(k, r, R)];
+        }
+      }
+    }
+  }
+  block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, phase == PH_STATS ? 3 : -1);
+}
+
+template <typename real, int M>
+__device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                               const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
+                                               const cplx<real>* __restrict__ twx,
+                                               const double* __restrict__ part_row, double* __restrict__ part,
+                                               int ny, int ngr) {
+  using C = cplx<real>;
+  constexpr int E = 8, L = M / 8, nx = 2 * M;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[(THREADS / 64) * NP_INV];
+  __shared__ double scal[1];
+  int g, si;
+  row_coords(ngr, g, si);
+  const int s = list[si];
+  if (s < 0) return;
+  const SlotCtl& ctl = ctls[s];
+  const int phase = ctl.phase;
+  int ncomp;
+  switch (phase) {
+    case PH_M_RES:
+    case PH_M_CG:
+    case PH_X_PROJ:
+      ncomp = 3;
+      break;
+    case PH_PF_ASM:
+    case PH_PF_R:
+    case PH_X_LAP:
+      ncomp = 1;
+      break;
+    default:
+      return;
+  }
+  const SlotParam& P = prms[s];
+  const SlotPtr<real> F = ptrs[s];
+  const int R = blockDim.x / L;
+  const int row = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+  const int y0 = g * R;
+  const int n = nx * ny;
+  const RowCtx<real> X = row_ctx<real>(ctl, P, phase, ncomp, n);
+  C* xa = reinterpret_cast<C*>(smem_raw) + row * XArea<M>::size;
+  C* tile = reinterpret_cast<C*>(smem_raw) + R * XArea<M>::size;
+  const C* spec = reinterpret_cast<const C*>(F.spec);
+
+  // CG step length from this tick's row-forward partials (same fixed-order
+  // reduction as the controller)
+  real alpha = 0;
+  if (phase == PH_M_CG) {
+    if (threadIdx.x < 64) {
+      const double pcp = wave_reduce_partials(part_row + (size_t)s * NP_ROW * ngr, ngr);
+      if (threadIdx.x == 0) scal[0] = (pcp > 0.0 && isfinite(pcp)) ? ctl.rr / pcp : 0.0;
+    }
+    __syncthreads();
+    alpha = real(scal[0]);
+  }
+
+  const int logR = ilog2(R);
+  C v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c < ncomp) {
+      if (c > 0) __syncthreads();  // the previous component's tile reads are done
+      for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
+        const int r = idx & (R - 1), k = idx >> logR;
+        tile[RowLds<M>::tile_index(k, r, R)] = spec[(size_t)(c * M + k) * ny + y0 + r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[c][m] = tile[RowLds<M>::tile_index(lane + m * L, row, R)];
+      // from the packed half spectrum to Z whose unnormalised inverse FFT
+      // gives nx (x[2h] + i x[2h+1])
+      C pn[E];
+      partner_bins<real, E, L>(v[c], pn, lane);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int k = lane + m * L;
+        if (k == 0) {
+          v[c][m] = mk<C>(v[c][m].x + v[c][m].y, v[c][m].x - v[c][m].y);
+        } else {
+          const C xk = v[c][m], xm = cconj(pn[m]);
+          const C a = cadd(xk, xm), b = csub(xk, xm);
+          v[c][m] = cadd(a, cmuli(cmul(cconj(twx[k]), b)));
+        }
+      }
+      reg_fft<real, true, M, E>(v[c], xa, lane, twx, 2);
+    }
+  }
+  double acc[NP_INV] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int o = (y0 + row) * nx + 2 * (lane + m * L);
+    C q[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[c] = c < ncomp ? v[c][m] : mk<C>(real(0), real(0));
+    row_epilogue<real>(X, P, F, o, q, alpha, acc);
+  }
+  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr);
 }
 
 // ===========================================================================
@@ -652,6 +899,75 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
   block_reduce_store<NP_COL>(acc, red, part + (size_t)s * NP_COL * ngc + g, ngc);
 }
 
+// Row-inverse epilogue for the pixel pair (o, o + 1): q[c] holds the
+// transformed values of component c at the pair (x: o, y: o + 1).
+template <typename real>
+__device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotParam& P, const SlotPtr<real>& F,
+                                             int o, const cplx<real> (&q)[3], real alpha, double (&acc)[NP_INV]) {
+  using C = cplx<real>;
+  const int phase = X.phase, n = X.n, ncomp = X.ncomp;
+  switch (phase) {
+    case PH_M_RES: {
+      const C q0 = q[0], q1 = q[1], q2 = q[2];
+      st2(F.rm + o, -q0.x, -q0.y);
+      st2(F.rm + n + o, -q1.x, -q1.y);
+      st2(F.rm + 2 * n + o, -q2.x, -q2.y);
+      acc[0] += double(q0.x) * q0.x + double(q0.y) * q0.y + double(q1.x) * q1.x + double(q1.y) * q1.y +
+                2.0 * (double(q2.x) * q2.x + double(q2.y) * q2.y);
+      break;
+    }
+    case PH_M_CG: {
+      const bool first = X.flags & FL_CG_FIRST;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const V2<real> p = ld2(F.pm + c * n + o);
+        V2<real> r2 = ld2(F.rm + c * n + o);
+        V2<real> th = first ? V2<real>{0, 0} : ld2(F.theta + c * n + o);
+        th = {th.a + alpha * p.a, th.b + alpha * p.b};
+        r2 = {r2.a - alpha * q[c].x, r2.b - alpha * q[c].y};
+        st2(F.theta + c * n + o, th.a, th.b);
+        st2(F.rm + c * n + o, r2.a, r2.b);
+        const double wc = c == 2 ? 2.0 : 1.0;
+        acc[0] += wc * (double(r2.a) * r2.a + double(r2.b) * r2.b);
+      }
+      break;
+    }
+    case PH_PF_ASM:
+    case PH_PF_R: {
+      const C lap = q[0];
+      const V2<real> ph = ld2(F.phi + o), d = ld2(F.theta + o), b = ld2(F.theta + n + o);
+      const V2<real> pr = ld2(F.phi_ref + o);
+      const real rr0 = d.a * ph.a + lap.x - b.a;
+      const real rr1 = d.b * ph.b + lap.y - b.b;
+      const real lo0 = lower_bound(pr.a, P), lo1 = lower_bound(pr.b, P);
+      const bool a0 = (ph.a <= lo0 && rr0 > real(0)) || (ph.a >= real(1) && rr0 < real(0));
+      const bool a1 = (ph.b <= lo1 && rr1 > real(0)) || (ph.b >= real(1) && rr1 < real(0));
+      const real r0 = a0 ? real(0) : rr0, r1 = a1 ? real(0) : rr1;
+      if (phase == PH_PF_R) {
+        const V2<real> ro = ld2(F.rm + o);
+        acc[1] += double(r0) * ro.a + double(r1) * ro.b;
+      }
+      st2(F.rm + o, r0, r1);
+      unsigned char* mask = reinterpret_cast<unsigned char*>(F.pm + n);
+      mask[o] = a0 ? 1 : 0;
+      mask[o + 1] = a1 ? 1 : 0;
+      acc[0] += double(r0) * r0 + double(r1) * r1;
+      acc[2] += double(ph.a) * ph.a + double(ph.b) * ph.b;
+      acc[3] += double(d.a * ph.a) * double(d.a * ph.a) + double(d.b * ph.b) * double(d.b * ph.b);
+      break;
+    }
+    case PH_X_PROJ:
+    case PH_X_LAP: {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (c < ncomp) st2(F.rm + c * n + o, q[c].x, q[c].y);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
 // ===========================================================================
 // Row-inverse kernel: transposed load -> C2R row FFTs -> epilogue (per
 // phase); FP64 partial sums per work-group.
@@ -691,10 +1007,10 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
   }
   const SlotParam& P = prms[s];
   const SlotPtr<real> F = ptrs[s];
-  const int flags = ctl.flags;
   const int M = nx >> 1, stride = M + PAD;
   const int y0 = g * R;
   const int n = nx * ny;
+  const RowCtx<real> X = row_ctx<real>(ctl, P, phase, ncomp, n);
   C* buf = reinterpret_cast<C*>(smem_raw);
   const C* spec = reinterpret_cast<const C*>(F.spec);
 
@@ -727,68 +1043,10 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
     const int r = idx >> logM, h = idx & (M - 1);
     const int o = (y0 + r) * nx + 2 * h;
     const int li = r * stride + h;
-    switch (phase) {
-      case PH_M_RES: {
-        const C q0 = buf[li], q1 = buf[R * stride + li], q2 = buf[2 * R * stride + li];
-        st2(F.rm + o, -q0.x, -q0.y);
-        st2(F.rm + n + o, -q1.x, -q1.y);
-        st2(F.rm + 2 * n + o, -q2.x, -q2.y);
-        acc[0] += double(q0.x) * q0.x + double(q0.y) * q0.y + double(q1.x) * q1.x + double(q1.y) * q1.y +
-                  2.0 * (double(q2.x) * q2.x + double(q2.y) * q2.y);
-        break;
-      }
-      case PH_M_CG: {
-        const C q[3] = {buf[li], buf[R * stride + li], buf[2 * R * stride + li]};
-        const bool first = flags & FL_CG_FIRST;
+    C q[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const V2<real> p = ld2(F.pm + c * n + o);
-          V2<real> r2 = ld2(F.rm + c * n + o);
-          V2<real> th = first ? V2<real>{0, 0} : ld2(F.theta + c * n + o);
-          th = {th.a + alpha * p.a, th.b + alpha * p.b};
-          r2 = {r2.a - alpha * q[c].x, r2.b - alpha * q[c].y};
-          st2(F.theta + c * n + o, th.a, th.b);
-          st2(F.rm + c * n + o, r2.a, r2.b);
-          const double wc = c == 2 ? 2.0 : 1.0;
-          acc[0] += wc * (double(r2.a) * r2.a + double(r2.b) * r2.b);
-        }
-        break;
-      }
-      case PH_PF_ASM:
-      case PH_PF_R: {
-        const C lap = buf[li];
-        const V2<real> ph = ld2(F.phi + o), d = ld2(F.theta + o), b = ld2(F.theta + n + o);
-        const V2<real> pr = ld2(F.phi_ref + o);
-        const real rr0 = d.a * ph.a + lap.x - b.a;
-        const real rr1 = d.b * ph.b + lap.y - b.b;
-        const real lo0 = lower_bound(pr.a, P), lo1 = lower_bound(pr.b, P);
-        const bool a0 = (ph.a <= lo0 && rr0 > real(0)) || (ph.a >= real(1) && rr0 < real(0));
-        const bool a1 = (ph.b <= lo1 && rr1 > real(0)) || (ph.b >= real(1) && rr1 < real(0));
-        const real r0 = a0 ? real(0) : rr0, r1 = a1 ? real(0) : rr1;
-        if (phase == PH_PF_R) {
-          const V2<real> ro = ld2(F.rm + o);
-          acc[1] += double(r0) * ro.a + double(r1) * ro.b;
-        }
-        st2(F.rm + o, r0, r1);
-        unsigned char* mask = reinterpret_cast<unsigned char*>(F.pm + n);
-        mask[o] = a0 ? 1 : 0;
-        mask[o + 1] = a1 ? 1 : 0;
-        acc[0] += double(r0) * r0 + double(r1) * r1;
-        acc[2] += double(ph.a) * ph.a + double(ph.b) * ph.b;
-        acc[3] += double(d.a * ph.a) * double(d.a * ph.a) + double(d.b * ph.b) * double(d.b * ph.b);
-        break;
-      }
-      case PH_X_PROJ:
-      case PH_X_LAP: {
-        for (int c = 0; c < ncomp; ++c) {
-          const C q = buf[c * R * stride + li];
-          st2(F.rm + c * n + o, q.x, q.y);
-        }
-        break;
-      }
-      default:
-        break;
-    }
+    for (int c = 0; c < 3; ++c) q[c] = c < ncomp ? buf[c * R * stride + li] : mk<C>(real(0), real(0));
+    row_epilogue<real>(X, P, F, o, q, alpha, acc);
   }
   block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr);
 }
@@ -1188,6 +1446,31 @@ __global__ __launch_bounds__(THREADS) void k_colr(const int* __restrict__ list, 
   kt_end(kt);
 }
 
+template <typename real, int M>
+__global__ __launch_bounds__(THREADS) void k_rowfwdr(const int* __restrict__ list,
+                                                     const SlotPtr<real>* __restrict__ ptrs,
+                                                     const SlotParam* __restrict__ prms,
+                                                     const SlotCtl* __restrict__ ctls,
+                                                     const cplx<real>* __restrict__ twx, double* __restrict__ part,
+                                                     int ny, int ngr, KTime* kt) {
+  kt_begin(kt);
+  k_rowfwdr_body<real, M>(list, ptrs, prms, ctls, twx, part, ny, ngr);
+  kt_end(kt);
+}
+
+template <typename real, int M>
+__global__ __launch_bounds__(THREADS) void k_rowinvr(const int* __restrict__ list,
+                                                     const SlotPtr<real>* __restrict__ ptrs,
+                                                     const SlotParam* __restrict__ prms,
+                                                     const SlotCtl* __restrict__ ctls,
+                                                     const cplx<real>* __restrict__ twx,
+                                                     const double* __restrict__ part_row, double* __restrict__ part,
+                                                     int ny, int ngr, KTime* kt) {
+  kt_begin(kt);
+  k_rowinvr_body<real, M>(list, ptrs, prms, ctls, twx, part_row, part, ny, ngr);
+  kt_end(kt);
+}
+
 template <typename real>
 __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                                     const SlotParam* __restrict__ prms,
@@ -1295,8 +1578,27 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
                        double* prof, SlotSeq* seqs, StepRec* recs, KTime* kt, unsigned long long* ktsum,
                        hipStream_t st) {
   dim3 grow(G.ngr, G.S), gcol(G.ngc, G.S);
-  hipLaunchKernelGGL(k_rowfwd<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, G.nx,
-                     G.ny, G.R, G.ngr, kt ? kt + 0 : nullptr);
+  KTime* ktf = kt ? kt + 0 : nullptr;
+  KTime* kti = kt ? kt + 2 : nullptr;
+  bool row_done = false;
+  if constexpr (std::is_same<real, float>::value) {
+    if (G.row_reg) {
+      row_done = true;
+#define SPFF_ROWS_FWD(MM)                                                                                      \
+  hipLaunchKernelGGL((k_rowfwdr<real, MM>), grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, \
+                     prow, G.ny, G.ngr, ktf)
+      switch (G.nx) {
+        case 128: SPFF_ROWS_FWD(64); break;
+        case 256: SPFF_ROWS_FWD(128); break;
+        case 512: SPFF_ROWS_FWD(256); break;
+        default: SPFF_ROWS_FWD(512); break;
+      }
+#undef SPFF_ROWS_FWD
+    }
+  }
+  if (!row_done)
+    hipLaunchKernelGGL(k_rowfwd<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow,
+                       G.nx, G.ny, G.R, G.ngr, ktf);
   KTime* ktc = kt ? kt + 1 : nullptr;
   bool col_done = false;
   if constexpr (std::is_same<real, float>::value) {
@@ -1321,8 +1623,23 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
   if (!col_done)
     hipLaunchKernelGGL(k_col<real>, gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls, twy, pcol,
                        G.nx, G.ny, G.W, G.ngc, ktc);
-  hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow, pinv,
-                     G.nx, G.ny, G.R, G.ngr, kt ? kt + 2 : nullptr);
+  if (row_done) {
+    if constexpr (std::is_same<real, float>::value) {
+#define SPFF_ROWS_INV(MM)                                                                                      \
+  hipLaunchKernelGGL((k_rowinvr<real, MM>), grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, \
+                     prow, pinv, G.ny, G.ngr, kti)
+      switch (G.nx) {
+        case 128: SPFF_ROWS_INV(64); break;
+        case 256: SPFF_ROWS_INV(128); break;
+        case 512: SPFF_ROWS_INV(256); break;
+        default: SPFF_ROWS_INV(512); break;
+      }
+#undef SPFF_ROWS_INV
+    }
+  } else {
+    hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow,
+                       pinv, G.nx, G.ny, G.R, G.ngr, kti);
+  }
   hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(64), 0, st, list, prms, ctls, prow, pcol, pinv, prof, seqs,
                      recs, G.nx, G.ny, G.ngr, G.ngc, kt, ktsum);
   return hipGetLastError();
