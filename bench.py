@@ -14,11 +14,20 @@ are run untimed to reach the window (preparation), then W warmup steps, then
 K timed steps.  value = (mechanics CG + BCCG iterations) x grid points per
 second over the timed steps.
 
+Before the timed steps the launch plans of the FFT kernels are autotuned
+per bucket of active problems (untimed; reported under "autotune"), and a
+steady window of load steps before any realization nucleates (all 64 active)
+is measured on its own (reported under breakdown.steady_all_active).
+
 Also reported on the same line:
-  roofline      dominant kernel's algorithmic HBM bytes / its event time
-                (HIP events on the solver stream during the timed steps)
-  plain_gpu     the plain single-instance path (256x256, one problem,
-                host check after every tick) over its full 200-step ramp
+  roofline      dominant kernel's algorithmic HBM bytes per launch / its
+                average execution time per launch, both over the timed
+                steps (the library's device-clock kernel timers on the
+                solver stream: first work-group start to last work-group
+                end of every launch, also inside captured graphs)
+  plain_gpu     the plain single-instance path (256x256, one problem, host
+                check after every tick, no graph) over its full 200-step
+                ramp, for each of AT1/AT2 x no split/spectral split
   serving       continuous batching of load-step requests over resident
                 problems of mixed grid sizes: saturation rate, then p50/p99
                 latency and throughput under Poisson arrivals
@@ -59,11 +68,44 @@ def batched_leg(args):
     n, B = args.grid, args.batch
     E = np.stack([si.young_modulus(n, args.corr, args.amp, 3000 + i) for i in range(B)])
     ramp = si.uniaxial_ramp(200, 0.2, 2.0)
+    tuned = None
+    if args.autotune:
+        from paper_2203_16467_amd import autotune
+        t = time.time()
+        plans, timing, source = autotune.tune(n, n, B, cache=args.plan_cache, log=log if args.verbose else None)
+        tuned = {"source": source, "seconds": time.time() - t,
+                 "plans": {str(v): plans[v] for v in plans}, "timing_us_per_tick": {str(v): timing[v] for v in timing}}
+        log(f"[bench] autotuned launch plans for {len(plans)} buckets ({source}) in {tuned['seconds']:.1f}s")
     cfg = spff.default_config(nx=n, ny=n, use_graph=1, ticks_per_sync=16)
     p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
+    if tuned:
+        autotune.apply(p, plans)
+    steady = None
     s0 = args.start - args.warmup
     t = time.time()
-    if s0 > 0:
+    if args.steady and s0 > args.steady_start + args.steady_steps:
+        # all realizations active (before any nucleates): the batched
+        # kernels at full occupancy
+        p.run_sequence(ramp[:args.steady_start])
+        p.profile_enable(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, stats = p.run_sequence(ramp[args.steady_start:args.steady_start + args.steady_steps])
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t1
+        pr = p.profile_read()
+        p.profile_enable(False)
+        cg1, pf1 = iters(stats)
+        steady = {"steps": [args.steady_start, args.steady_start + args.steady_steps - 1], "seconds": dt1,
+                  "value": (cg1 + pf1) * n * n / dt1, "unit": "grid-pt-iters/s", "cg_iters": cg1,
+                  "bccg_iters": pf1, "kernel_ms": pr["kernel_ms"], "kernel_alg_bytes": pr["alg_bytes"],
+                  "kernel_alg_GBs": {k: pr["alg_bytes"][k] / (pr["kernel_ms"][k] * 1e-3) / 1e9
+                                     for k in KERNELS if pr["kernel_ms"][k] > 0}}
+        log(f"[bench] steady window {steady['steps']}: {steady['value']:.3e} grid-pt-iters/s, "
+            f"kernel GB/s {steady['kernel_alg_GBs']}")
+        if s0 > args.steady_start + args.steady_steps:
+            p.run_sequence(ramp[args.steady_start + args.steady_steps:s0])
+    elif s0 > 0:
         p.run_sequence(ramp[:s0])
     log(f"[bench] prepared {B}x{n}^2 to load step {s0} in {time.time() - t:.1f}s")
     p.profile_enable(True)
@@ -82,7 +124,7 @@ def batched_leg(args):
     log(f"[bench] timed {args.steps} steps in {dt:.2f}s: cg {cg} bccg {pf}, cracked {ncrack}/{B}, status {st}")
     p.close()
     return {"dt": dt, "cg": cg, "pf": pf, "status": st, "prof": prof, "ncrack": ncrack, "E0": E[0],
-            "ramp": ramp, "n": n, "B": B}
+            "ramp": ramp, "n": n, "B": B, "tuned": tuned, "steady": steady}
 
 
 def plain_leg(args):
@@ -94,24 +136,35 @@ def plain_leg(args):
     n = 256
     E = si.young_modulus(n, 8.0, 0.1, 2000)
     ramp = si.uniaxial_ramp(200, 0.2, 2.0)
-    cfg = spff.default_config(nx=n, ny=n, use_graph=0, ticks_per_sync=1)
-    p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
-    p.run_sequence(ramp[:2])  # warmup
-    p.close()
-    p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, stats = p.run_sequence(ramp)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    cg, pf = iters(stats)
-    p.close()
-    log(f"[bench] plain 256^2 single: 200 steps in {dt:.2f}s, cg {cg} bccg {pf}")
-    return {"value": (cg + pf) * n * n / dt, "unit": "grid-pt-iters/s",
-            "workload": "plain: one 256x256 problem (E = max(1+0.1z,0.5), corr 8 px, seed 2000), AT1, "
-                        "strain-spectral, l = 2 px, crack-set, 200-step ramp to 1.5 eps_M; host status check "
-                        "after every tick, no graph",
-            "seconds": dt, "cg_iters": cg, "bccg_iters": pf}
+    runs, tot_it, tot_s = {}, 0, 0.0
+    for at in (1, 2):
+        for split in (spff.SPLIT_NONE, spff.SPLIT_SPECTRAL):
+            cfg = spff.default_config(nx=n, ny=n, at=at, split=split, use_graph=0, ticks_per_sync=1)
+            p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
+            p.run_sequence(ramp[:2])  # warmup
+            p.close()
+            p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, stats = p.run_sequence(ramp)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            cg, pf = iters(stats)
+            p.close()
+            name = f"AT{at}-{'spectral' if split else 'none'}"
+            runs[name] = {"seconds": dt, "cg_iters": cg, "bccg_iters": pf, "status": st,
+                          "value": (cg + pf) * n * n / dt}
+            tot_it += cg + pf
+            tot_s += dt
+            log(f"[bench] plain 256^2 single {name}: 200 steps in {dt:.2f}s, cg {cg} bccg {pf}")
+    return {"value": runs["AT1-spectral"]["value"], "unit": "grid-pt-iters/s",
+            "value_all_variants": tot_it * n * n / tot_s,
+            "workload": "plain: one 256x256 problem (E = max(1+0.1z,0.5), corr 8 px, seed 2000), l = 2 px, "
+                        "crack-set, 200-step ramp to 1.5 eps_M, run for AT1/AT2 x no split/spectral split; host "
+                        "status check after every tick, no graph; value = the AT1 spectral-split run (the "
+                        "batched workload's model), value_all_variants = all four runs' iterations x grid "
+                        "points / their summed time",
+            "seconds": tot_s, "runs": runs}
 
 
 def serving_leg(args):
@@ -218,6 +271,12 @@ def main():
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
     ap.add_argument("--serve-arena-gb", type=float, default=8.0)
     ap.add_argument("--serve-scratch-gb", type=float, default=1.0)
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false")
+    ap.add_argument("--plan-cache", default=None, help="JSON cache of autotuned launch plans")
+    ap.add_argument("--no-steady", dest="steady", action="store_false")
+    ap.add_argument("--steady-start", type=int, default=40)
+    ap.add_argument("--steady-steps", type=int, default=10)
+    ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs one process on one MI355X "
@@ -259,7 +318,9 @@ def main():
                       "realizations_cracked": res["ncrack"], "status": res["status"],
                       "kernel_ms": prof["kernel_ms"], "kernel_launches": prof["launches"],
                       "kernel_alg_bytes": prof["alg_bytes"],
-                      "alg_GBs_all_fft_kernels": all_b / (all_ms * 1e-3) / 1e9 if all_ms > 0 else None},
+                      "alg_GBs_all_fft_kernels": all_b / (all_ms * 1e-3) / 1e9 if all_ms > 0 else None,
+                      "steady_all_active": res["steady"]},
+        "autotune": res["tuned"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }

@@ -228,6 +228,37 @@ typedef struct spff_profile {
 spff_status spff_profile_enable(spff_problem* p, int32_t enable);
 spff_status spff_profile_read(spff_problem* p, spff_profile* out);
 
+/* Launch plans of the three FFT kernels, one per bucket of active problems
+ * (the launch covers a power-of-two number of problem slots: bucket i has
+ * min(2^i, nbatch) slots).  The handle starts with a built-in heuristic
+ * plan per bucket; an autotuner may time alternatives and install the
+ * fastest.  Plans change launch shapes and the grouping of the FP64 partial
+ * sums (so results by rounding only), never the arithmetic.
+ *   row_kind / col_kind: SPFF_FFT_LDS -- Stockham radix-4/2 passes through
+ *     LDS, one point pair per thread (any size); SPFF_FFT_REG -- radix-8
+ *     Stockham on registers, 8 points per lane, wavefront-local LDS
+ *     exchanges (FP32 only; rows: 128 <= nx <= 1024, columns: ny in
+ *     {128, 256, 512}).
+ *   rows / cols: rows per row work-group, columns per column work-group
+ *     (powers of two).
+ *   row_threads / col_threads: threads per work-group for the LDS kind
+ *     (64, 128 or 256, times 8 covering the transform); for the register
+ *     kind derived as rows * nx/16 (cols * ny/8), which must be a power of
+ *     two in [64, 256] -- filled in on return. */
+enum { SPFF_FFT_LDS = 1, SPFF_FFT_REG = 2 };
+typedef struct spff_plan {
+  int32_t row_kind, rows, row_threads;
+  int32_t col_kind, cols, col_threads;
+} spff_plan;
+/* Number of buckets and their slot counts (sizes may be NULL). */
+spff_status spff_plan_buckets(const spff_problem* p, int32_t* count, int32_t* sizes);
+/* The plan in use for bucket `bucket`. */
+spff_status spff_get_plan(const spff_problem* p, int32_t bucket, spff_plan* out);
+/* Install a plan for bucket `bucket` (NULL restores the heuristic).  The
+ * plan is validated (SPFF_E_INVALID on a bad plan, state unchanged) and the
+ * bucket's captured graph is dropped.  Synchronises the stream. */
+spff_status spff_set_plan(spff_problem* p, int32_t bucket, spff_plan* plan);
+
 /* Number of problems, grid and precision of a handle. */
 spff_status spff_problem_info(const spff_problem* p, int32_t* nbatch, int32_t* nx, int32_t* ny,
                               int32_t* precision);

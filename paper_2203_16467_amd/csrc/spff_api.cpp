@@ -92,14 +92,24 @@ spff_status check_config(const spff_config* c) {
   return SPFF_OK;
 }
 
-// Launch geometry: rows per row work-group R and columns per column
-// work-group W are the largest powers of two whose LDS tiles (3 components,
-// padded) stay within LDS_TARGET (at least one row / column).
-LaunchGeom plan(const spff_config* c, int S, size_t csize) {
-  LaunchGeom G{};
-  G.nx = c->nx;
-  G.ny = c->ny;
-  G.S = S;
+// ---------------------------------------------------------------------------
+// Launch plans.  A plan fixes, for one bucket of active problems, the kind
+// of FFT kernel for rows and for columns (LDS Stockham radix-4/2 with one
+// point pair per thread, or register-resident radix-8 with 8 points per
+// lane), the rows / columns per work-group and the threads per work-group.
+// auto_plan() is the built-in heuristic; the autotuner replaces it per
+// bucket through spff_set_plan().
+// ---------------------------------------------------------------------------
+bool reg_rows_ok(const spff_config* c) {
+  const int M = c->nx / 2;
+  return c->precision == SPFF_FP32 && M >= 64 && M <= 512;
+}
+bool reg_cols_ok(const spff_config* c) {
+  return c->precision == SPFF_FP32 && (c->ny == 128 || c->ny == 256 || c->ny == 512);
+}
+
+spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
+  spff_plan pl{};
   const int M = c->nx / 2;
   // at least ~TARGET_WG work-groups per launch when the batch allows it
   const long TARGET_WG = 1024;
@@ -113,20 +123,18 @@ LaunchGeom plan(const spff_config* c, int S, size_t csize) {
     W *= 2;
   if (c->plan_rows > 0) R = c->plan_rows;
   if (c->plan_cols > 0) W = c->plan_cols;
-  G.threads = c->plan_threads > 0 ? c->plan_threads : THREADS;
-  G.R = R;
-  G.ngr = c->ny / R;
-  G.W = W;
-  G.ngc = M / W;
-  G.lds_row = 3 * (size_t)R * (M + PAD) * csize;
-  G.lds_col = 3 * (size_t)W * (c->ny + PAD) * csize;
-  G.threads_col = G.threads;
-  G.col_reg = 0;
+  const int T = c->plan_threads > 0 ? c->plan_threads : THREADS;
+  pl.row_kind = SPFF_FFT_LDS;
+  pl.rows = R;
+  pl.row_threads = T;
+  pl.col_kind = SPFF_FFT_LDS;
+  pl.cols = W;
+  pl.col_threads = T;
   // FP32 columns of 128..512 points: register-resident transforms, a group
   // of ny/8 lanes per column, W columns per work-group (at least one
   // wavefront, at most THREADS lanes); W is fixed by plan_cols if given so
   // that the partial sums (hence the results) do not depend on the batch
-  if (c->precision == SPFF_FP32 && (c->ny == 128 || c->ny == 256 || c->ny == 512)) {
+  if (reg_cols_ok(c)) {
     const int Lc = c->ny / 8;
     const int wmin = 64 / Lc, wmax = THREADS / Lc;
     if (wmin <= M) {
@@ -137,11 +145,9 @@ LaunchGeom plan(const spff_config* c, int S, size_t csize) {
         while (Wr * 2 <= wmax && Wr * 2 <= M && (long)(M / (2 * Wr)) * S >= TARGET_WG) Wr *= 2;
       }
       if (Wr <= M) {
-        G.col_reg = 1;
-        G.W = Wr;
-        G.ngc = M / Wr;
-        G.threads_col = Wr * Lc;
-        G.lds_col = (size_t)Wr * (c->ny + c->ny / 8) * csize;
+        pl.col_kind = SPFF_FFT_REG;
+        pl.cols = Wr;
+        pl.col_threads = Wr * Lc;
       }
     }
   }
@@ -152,9 +158,8 @@ LaunchGeom plan(const spff_config* c, int S, size_t csize) {
   // the path needs enough wavefronts in flight to hide that: below ~8 per
   // CU (a few problems of a small grid) the LDS row kernels, whose threads
   // take one pixel pair each, finish sooner.
-  G.row_reg = 0;
   const bool many_waves = (long)S * c->ny * (M / 8) / 64 >= 2048;
-  if (c->precision == SPFF_FP32 && M >= 64 && M <= 512 && (many_waves || c->plan_rows > 0)) {
+  if (reg_rows_ok(c) && (many_waves || c->plan_rows > 0)) {
     const int Lr = M / 8;
     const int rmin = std::max(1, 64 / Lr), rmax = THREADS / Lr;
     if (rmin <= c->ny) {
@@ -165,14 +170,71 @@ LaunchGeom plan(const spff_config* c, int S, size_t csize) {
         while (Rr * 2 <= rmax && Rr * 2 <= c->ny && (long)(c->ny / (2 * Rr)) * S >= TARGET_WG) Rr *= 2;
       }
       if (Rr <= c->ny) {
-        G.row_reg = 1;
-        G.R = Rr;
-        G.ngr = c->ny / Rr;
-        G.threads = Rr * Lr;
-        G.lds_row = ((size_t)Rr * (M + M / 8) + (size_t)M * (Rr + 1)) * csize;
+        pl.row_kind = SPFF_FFT_REG;
+        pl.rows = Rr;
+        pl.row_threads = Rr * Lr;
       }
     }
   }
+  return pl;
+}
+
+// Validate a plan for a configuration; fills the derived thread counts of
+// the register kinds.
+spff_status check_plan(const spff_config* c, spff_plan* pl, size_t csize) {
+  const int M = c->nx / 2;
+  if (pl->row_kind == SPFF_FFT_REG) {
+    if (!reg_rows_ok(c)) return fail(SPFF_E_INVALID, "register row FFT needs FP32 and 128 <= nx <= 1024");
+    const int Lr = M / 8;
+    if (!pow2(pl->rows) || pl->rows * Lr < 64 || pl->rows * Lr > THREADS || pl->rows > c->ny)
+      return fail(SPFF_E_INVALID, "register row FFT: rows * nx/16 must be a power of two in [64, %d]", THREADS);
+    pl->row_threads = pl->rows * Lr;
+  } else if (pl->row_kind == SPFF_FFT_LDS) {
+    if (!pow2(pl->rows) || pl->rows > c->ny) return fail(SPFF_E_INVALID, "rows must be a power of two <= ny");
+    if (pl->row_threads != 64 && pl->row_threads != 128 && pl->row_threads != 256)
+      return fail(SPFF_E_INVALID, "row_threads must be 64, 128 or 256");
+    if (pl->row_threads * MAXE < M) return fail(SPFF_E_INVALID, "row_threads * 8 must cover nx/2");
+    if (3 * (size_t)pl->rows * (M + PAD) * csize > LDS_MAX) return fail(SPFF_E_INVALID, "row tile exceeds LDS");
+  } else {
+    return fail(SPFF_E_INVALID, "bad row_kind");
+  }
+  if (pl->col_kind == SPFF_FFT_REG) {
+    if (!reg_cols_ok(c)) return fail(SPFF_E_INVALID, "register column FFT needs FP32 and ny in {128, 256, 512}");
+    const int Lc = c->ny / 8;
+    if (!pow2(pl->cols) || pl->cols * Lc < 64 || pl->cols * Lc > THREADS || pl->cols > M)
+      return fail(SPFF_E_INVALID, "register column FFT: cols * ny/8 must be a power of two in [64, %d]", THREADS);
+    pl->col_threads = pl->cols * Lc;
+  } else if (pl->col_kind == SPFF_FFT_LDS) {
+    if (!pow2(pl->cols) || pl->cols > M) return fail(SPFF_E_INVALID, "cols must be a power of two <= nx/2");
+    if (pl->col_threads != 64 && pl->col_threads != 128 && pl->col_threads != 256)
+      return fail(SPFF_E_INVALID, "col_threads must be 64, 128 or 256");
+    if (pl->col_threads * MAXE < c->ny) return fail(SPFF_E_INVALID, "col_threads * 8 must cover ny");
+    if (3 * (size_t)pl->cols * (c->ny + PAD) * csize > LDS_MAX)
+      return fail(SPFF_E_INVALID, "column tile exceeds LDS");
+  } else {
+    return fail(SPFF_E_INVALID, "bad col_kind");
+  }
+  return SPFF_OK;
+}
+
+LaunchGeom geom_from_plan(const spff_config* c, int S, size_t csize, const spff_plan& pl) {
+  LaunchGeom G{};
+  G.nx = c->nx;
+  G.ny = c->ny;
+  G.S = S;
+  const int M = c->nx / 2;
+  G.R = pl.rows;
+  G.ngr = c->ny / pl.rows;
+  G.threads = pl.row_threads;
+  G.row_reg = pl.row_kind == SPFF_FFT_REG;
+  G.lds_row = G.row_reg ? ((size_t)pl.rows * (M + M / 8) + (size_t)M * (pl.rows + 1)) * csize
+                        : 3 * (size_t)pl.rows * (M + PAD) * csize;
+  G.W = pl.cols;
+  G.ngc = M / pl.cols;
+  G.threads_col = pl.col_threads;
+  G.col_reg = pl.col_kind == SPFF_FFT_REG;
+  G.lds_col = G.col_reg ? (size_t)pl.cols * (c->ny + c->ny / 8) * csize
+                        : 3 * (size_t)pl.cols * (c->ny + PAD) * csize;
   return G;
 }
 
@@ -239,6 +301,7 @@ struct spff_problem {
   // bucket_size[b] slots (powers of two, the last one = S)
   std::vector<int> bucket_size;
   std::vector<LaunchGeom> geoms;
+  std::vector<spff_plan> plans;  // per bucket, geoms[i] derived from plans[i]
   std::vector<hipGraphExec_t> graphs;  // one captured tick block per bucket (lazy)
   int cur_bucket = -1;
   int32_t* host_list = nullptr;  // pinned staging of the device slot list
@@ -626,10 +689,13 @@ spff_status engine_create(const spff_config* cfg, int32_t nbatch, const void* E_
     if (v >= nbatch) break;
   }
   std::vector<LaunchGeom> geoms;
+  std::vector<spff_plan> plans;
   for (int v : bsize) {
-    LaunchGeom G = plan(cfg, v, 2 * rsize);
+    spff_plan pl = auto_plan(cfg, v, 2 * rsize);
+    LaunchGeom G = geom_from_plan(cfg, v, 2 * rsize, pl);
     if (G.lds_row > LDS_MAX || G.lds_col > LDS_MAX) return fail(SPFF_E_INVALID, "grid too large for LDS tiles");
     geoms.push_back(G);
+    plans.push_back(pl);
   }
   Layout L = layout(cfg, nbatch, rsize, scratch_only);
   if (workspace_bytes < L.total)
@@ -646,6 +712,7 @@ spff_status engine_create(const spff_config* cfg, int32_t nbatch, const void* E_
   p->cap_stream = nullptr;
   p->bucket_size = bsize;
   p->geoms = geoms;
+  p->plans = plans;
   p->graphs.assign(bsize.size(), nullptr);
   p->host_ctl = nullptr;
   p->prm.assign(nbatch, make_param(cfg));
@@ -976,6 +1043,40 @@ spff_status spff_profile_read(spff_problem* p, spff_profile* out) {
     out->launches[j] = p->launches[j];
   }
   out->ticks = p->prof_ticks;
+  return SPFF_OK;
+}
+
+spff_status spff_plan_buckets(const spff_problem* p, int32_t* count, int32_t* sizes) {
+  if (!p || !count) return fail(SPFF_E_INVALID, "NULL argument");
+  *count = (int32_t)p->bucket_size.size();
+  if (sizes)
+    for (size_t i = 0; i < p->bucket_size.size(); ++i) sizes[i] = p->bucket_size[i];
+  return SPFF_OK;
+}
+
+spff_status spff_get_plan(const spff_problem* p, int32_t bucket, spff_plan* out) {
+  if (!p || !out) return fail(SPFF_E_INVALID, "NULL argument");
+  if (bucket < 0 || bucket >= (int32_t)p->plans.size()) return fail(SPFF_E_INVALID, "bucket out of range");
+  *out = p->plans[bucket];
+  return SPFF_OK;
+}
+
+spff_status spff_set_plan(spff_problem* p, int32_t bucket, spff_plan* plan) {
+  if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
+  if (bucket < 0 || bucket >= (int32_t)p->plans.size()) return fail(SPFF_E_INVALID, "bucket out of range");
+  const size_t csize = 2 * p->rsize;
+  const int v = p->bucket_size[bucket];
+  spff_plan pl = plan ? *plan : auto_plan(&p->cfg, v, csize);
+  const spff_status st = check_plan(&p->cfg, &pl, csize);
+  if (st != SPFF_OK) return st;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->plans[bucket] = pl;
+  p->geoms[bucket] = geom_from_plan(&p->cfg, v, csize, pl);
+  if (p->graphs[bucket]) {
+    HIP_TRY(hipGraphExecDestroy(p->graphs[bucket]));
+    p->graphs[bucket] = nullptr;
+  }
+  if (plan) *plan = pl;
   return SPFF_OK;
 }
 

@@ -84,6 +84,22 @@ class Profile(ctypes.Structure):
                 "alg_bytes": dict(zip(self.KERNELS, self.alg_bytes)), "ticks": self.ticks}
 
 
+FFT_LDS, FFT_REG = 1, 2
+
+
+class Plan(ctypes.Structure):
+    """spff_plan: launch plan of the three FFT kernels for one bucket."""
+    _fields_ = [("row_kind", ctypes.c_int32), ("rows", ctypes.c_int32), ("row_threads", ctypes.c_int32),
+                ("col_kind", ctypes.c_int32), ("cols", ctypes.c_int32), ("col_threads", ctypes.c_int32)]
+
+    def to_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(**{k: int(d[k]) for k, _ in cls._fields_})
+
+
 _lib = None
 
 # C signatures: name -> (restype, argtypes)
@@ -121,6 +137,9 @@ _SIGS = {
     "spff_problem_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "spff_destroy_problem": (ctypes.c_int, [_P]),
+    "spff_plan_buckets": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "spff_get_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Plan)]),
+    "spff_set_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Plan)]),
     "spff_last_error": (ctypes.c_char_p, []),
     "spff_version": (ctypes.c_char_p, []),
 }
@@ -315,6 +334,29 @@ class Problem:
         out = Profile()
         _check(lib().spff_profile_read(self.handle, ctypes.byref(out)))
         return out.to_dict()
+
+    def plan_buckets(self):
+        """Slot counts of the launch buckets (spff_plan_buckets)."""
+        n = ctypes.c_int32(0)
+        _check(lib().spff_plan_buckets(self.handle, ctypes.byref(n), None))
+        sizes = (ctypes.c_int32 * n.value)()
+        _check(lib().spff_plan_buckets(self.handle, ctypes.byref(n), sizes))
+        return list(sizes)
+
+    def get_plan(self, bucket):
+        pl = Plan()
+        _check(lib().spff_get_plan(self.handle, int(bucket), ctypes.byref(pl)))
+        return pl.to_dict()
+
+    def set_plan(self, bucket, plan=None):
+        """Install a plan (dict of spff_plan fields) for a bucket; None
+        restores the built-in heuristic.  Returns the plan in use."""
+        if plan is None:
+            _check(lib().spff_set_plan(self.handle, int(bucket), None))
+            return self.get_plan(bucket)
+        pl = Plan.from_dict(plan)
+        _check(lib().spff_set_plan(self.handle, int(bucket), ctypes.byref(pl)))
+        return pl.to_dict()
 
     def get_state(self):
         """spff_get_state: (state tensor [B, 5, ny, nx], eps_bar (B, 3))."""

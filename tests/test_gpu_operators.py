@@ -62,3 +62,63 @@ def test_projection_idempotent_on_device():
     g2 = p.apply_operator(spff.OP_PROJECT, g1)
     assert float((g1 - g2).norm() / g1.norm()) < 2e-6
     p.close()
+
+
+def _check_ops(p, x3, x1, tol=2e-6):
+    import torch
+    out3 = p.apply_operator(spff.OP_PROJECT, torch.from_numpy(x3).to(device())).double().cpu().numpy()
+    out1 = p.apply_operator(spff.OP_NEG_LAPLACIAN, torch.from_numpy(x1).to(device())).double().cpu().numpy()
+    for b in range(p.B):
+        want3 = tensor_to_planes(osp.project(planes_to_tensor(x3[b].astype(np.float64))))
+        want1 = -osp.laplacian(x1[b].astype(np.float64))
+        assert rel_l2(out3[b], want3) < tol
+        assert rel_l2(out1[b], want1) < tol
+
+
+@pytest.mark.parametrize("nx,ny", [(128, 128), (256, 512), (512, 256), (1024, 128), (64, 512)])
+def test_every_plan_candidate_gives_the_operators(nx, ny):
+    """Every launch plan the autotuner may install (LDS and register FFT
+    kinds, all work-group shapes) computes the same operators."""
+    from paper_2203_16467_amd import autotune
+    print(f"plans {nx}x{ny}", flush=True)
+    p = _problem(nx, ny, "fp32", B=2)
+    rng = np.random.default_rng(nx + 3 * ny)
+    x3 = rng.standard_normal((p.B, 3, ny, nx)).astype(np.float32)
+    x1 = rng.standard_normal((p.B, ny, nx)).astype(np.float32)
+    bidx = len(p.plan_buckets()) - 1
+    base = p.get_plan(bidx)
+    kinds = set()
+    for kind, R, T in autotune.row_candidates(p.cfg):
+        got = p.set_plan(bidx, dict(base, row_kind=kind, rows=R, row_threads=T))
+        assert got["rows"] == R and got["row_kind"] == kind
+        _check_ops(p, x3, x1)
+        kinds.add(("row", kind))
+    p.set_plan(bidx, None)
+    for kind, W, T in autotune.col_candidates(p.cfg):
+        p.set_plan(bidx, dict(base, col_kind=kind, cols=W, col_threads=T))
+        _check_ops(p, x3, x1)
+        kinds.add(("col", kind))
+    assert ("row", spff.FFT_LDS) in kinds and ("col", spff.FFT_LDS) in kinds
+    if 128 <= nx <= 1024:
+        assert ("row", spff.FFT_REG) in kinds
+    if ny in (128, 256, 512):
+        assert ("col", spff.FFT_REG) in kinds
+    p.close()
+
+
+def test_invalid_plans_rejected():
+    p = _problem(64, 64, "fp32", B=2)
+    base = p.get_plan(0)
+    bad = [dict(base, row_kind=spff.FFT_REG, rows=8),        # register rows need nx >= 128
+           dict(base, rows=3),                                # not a power of two
+           dict(base, row_threads=96),
+           dict(base, col_kind=7),
+           dict(base, cols=64)]                               # more than nx/2 columns
+    for plan in bad:
+        with pytest.raises(spff.SpffError) as ei:
+            p.set_plan(0, plan)
+        assert ei.value.status == spff.E_INVALID
+    with pytest.raises(spff.SpffError):
+        p.set_plan(5, base)
+    assert p.get_plan(0) == base
+    p.close()
