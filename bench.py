@@ -52,6 +52,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+class _Roctx:
+    """roctx range around the timed steps, so that a profiler run (rocprofv3
+    --marker-trace) can restrict its kernel statistics to them; a no-op when
+    the library is absent."""
+
+    def __init__(self):
+        import ctypes
+        self.lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "libroctx64.so"):
+            try:
+                self.lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+
+    def push(self, name):
+        if self.lib:
+            self.lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self.lib:
+            self.lib.roctxRangePop()
+
+
+ROCTX = _Roctx()
+
+
 def iters(stats):
     cg = sum(s["cg_iters"] for row in stats for s in row)
     pf = sum(s["bccg_iters"] for row in stats for s in row)
@@ -72,7 +99,8 @@ def batched_leg(args):
     if args.autotune:
         from paper_2203_16467_amd import autotune
         t = time.time()
-        plans, timing, source = autotune.tune(n, n, B, cache=args.plan_cache, log=log if args.verbose else None)
+        plans, timing, source = autotune.tune(n, n, B, cache=args.plan_cache or autotune.DEFAULT_CACHE,
+                                              log=log if args.verbose else None)
         tuned = {"source": source, "seconds": time.time() - t,
                  "plans": {str(v): plans[v] for v in plans}, "timing_us_per_tick": {str(v): timing[v] for v in timing}}
         log(f"[bench] autotuned launch plans for {len(plans)} buckets ({source}) in {tuned['seconds']:.1f}s")
@@ -114,10 +142,12 @@ def batched_leg(args):
     log(f"[bench] warmup steps {s0}..{args.start - 1} done")
     p.profile_enable(True)  # reset the kernel totals for the timed region
     torch.cuda.synchronize()
+    ROCTX.push("bench_timed")
     t0 = time.perf_counter()
     st, stats = p.run_sequence(ramp[args.start:args.start + args.steps])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ROCTX.pop()
     prof = p.profile_read()
     cg, pf = iters(stats)
     ncrack = sum(1 for row in stats if row[-1]["crack_px"] > 0)
@@ -272,7 +302,9 @@ def main():
     ap.add_argument("--serve-arena-gb", type=float, default=8.0)
     ap.add_argument("--serve-scratch-gb", type=float, default=1.0)
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
-    ap.add_argument("--plan-cache", default=None, help="JSON cache of autotuned launch plans")
+    ap.add_argument("--plan-cache", default=None,
+                    help="JSON cache of autotuned launch plans (default: the package's gfx950 cache; buckets "
+                         "missing from it are tuned live)")
     ap.add_argument("--no-steady", dest="steady", action="store_false")
     ap.add_argument("--steady-start", type=int, default=40)
     ap.add_argument("--steady-steps", type=int, default=10)

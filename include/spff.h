@@ -238,14 +238,17 @@ spff_status spff_profile_read(spff_problem* p, spff_profile* out);
  *     LDS, one point pair per thread (any size); SPFF_FFT_REG -- radix-8
  *     Stockham on registers, 8 points per lane, wavefront-local LDS
  *     exchanges (FP32 only; rows: 128 <= nx <= 1024, columns: ny in
- *     {128, 256, 512}).
+ *     {128, 256, 512}); SPFF_FFT_REG4 (rows only) -- the same with 4
+ *     points per lane and radix-4 passes (twice the lanes per row, for
+ *     launches with few problems; 128 <= nx <= 512).
  *   rows / cols: rows per row work-group, columns per column work-group
  *     (powers of two).
  *   row_threads / col_threads: threads per work-group for the LDS kind
  *     (64, 128 or 256, times 8 covering the transform); for the register
- *     kind derived as rows * nx/16 (cols * ny/8), which must be a power of
- *     two in [64, 256] -- filled in on return. */
-enum { SPFF_FFT_LDS = 1, SPFF_FFT_REG = 2 };
+ *     kinds derived as rows * nx/16 (rows * nx/8 for SPFF_FFT_REG4;
+ *     cols * ny/8), which must be a power of two in [64, 256] -- filled in
+ *     on return. */
+enum { SPFF_FFT_LDS = 1, SPFF_FFT_REG = 2, SPFF_FFT_REG4 = 3 };
 typedef struct spff_plan {
   int32_t row_kind, rows, row_threads;
   int32_t col_kind, cols, col_threads;

@@ -4,7 +4,8 @@ A handle launches its three FFT kernels (row-forward, column, row-inverse)
 over a power-of-two bucket of active problem slots; for every bucket the
 library holds a launch plan (``spff_plan``): the kind of FFT kernel for rows
 and for columns (LDS Stockham radix-4/2 with one point pair per thread, or
-register-resident radix-8 with eight points per lane), rows / columns per
+register-resident radix-8 with eight points per lane, or for rows radix-4
+with four), rows / columns per
 work-group and threads per work-group.  The built-in plans come from a
 heuristic; this module times the alternatives on the device and installs the
 fastest.
@@ -49,11 +50,12 @@ def row_candidates(cfg):
         for T in (128, 256):
             if T * 8 >= M and 3 * R * (M + 1) * csize <= LDS_BYTES // 2:
                 out.append((spff.FFT_LDS, R, T))
-    if cfg.precision == spff.FP32 and 64 <= M <= 512:
-        L = M // 8
-        for R in _pow2_range(max(1, 64 // L), THREADS // L):
-            if R <= cfg.ny:
-                out.append((spff.FFT_REG, R, R * L))
+    for kind, E, Mmax in ((spff.FFT_REG, 8, 512), (spff.FFT_REG4, 4, 256)):
+        if cfg.precision == spff.FP32 and 64 <= M <= Mmax:
+            L = M // E
+            for R in _pow2_range(max(1, 64 // L), THREADS // L):
+                if R <= cfg.ny:
+                    out.append((kind, R, R * L))
     return out
 
 
@@ -140,10 +142,14 @@ def tune_bucket(nx, ny, v, precision=spff.FP32, seed=7, log=None):
     return plan, {"row_us_per_tick": best_row[0] * 1e3, "col_us_per_tick": best_col[0] * 1e3}
 
 
-def tune(nx, ny, batch, precision=spff.FP32, cache=None, log=None):
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "plans_gfx950.json")
+
+
+def tune(nx, ny, batch, precision=spff.FP32, cache=DEFAULT_CACHE, write_cache=False, log=None):
     """Plans for every bucket of a batch of `batch` problems; returns
     ({bucket size: plan}, {bucket size: timings}, source) where source is
-    "cache" if every bucket was found in the cache file."""
+    "cache" if every bucket was found in the cache file (buckets missing
+    from it are tuned; the file is rewritten only with write_cache)."""
     sizes = []
     v = 1
     while True:
@@ -168,7 +174,7 @@ def tune(nx, ny, batch, precision=spff.FP32, cache=None, log=None):
         store[k] = {"plan": plans[v], "timing": times[v]}
         if log:
             log(f"[autotune] {k}: {plans[v]} ({time.time() - t0:.1f} s)")
-    if cache:
+    if cache and write_cache and not hit:
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         with open(cache, "w") as f:
             json.dump(store, f, indent=1, sort_keys=True)
@@ -180,3 +186,26 @@ def apply(prob, plans):
     for i, v in enumerate(prob.plan_buckets()):
         if v in plans:
             prob.set_plan(i, plans[v])
+
+
+def main(argv=None):
+    """python -m paper_2203_16467_amd.autotune NX NY BATCH [--out FILE]:
+    tune every bucket and write the plans to FILE (default: the package's
+    gfx950 cache)."""
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser()
+    ap.add_argument("nx", type=int)
+    ap.add_argument("ny", type=int)
+    ap.add_argument("batch", type=int)
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--fp64", action="store_true")
+    a = ap.parse_args(argv)
+    log = lambda *m: print(*m, file=sys.stderr, flush=True)  # noqa: E731
+    plans, _, src = tune(a.nx, a.ny, a.batch, spff.FP64 if a.fp64 else spff.FP32, cache=a.out, write_cache=True,
+                         log=log)
+    print(json.dumps({str(k): v for k, v in plans.items()}), src)
+
+
+if __name__ == "__main__":
+    main()

@@ -100,9 +100,9 @@ spff_status check_config(const spff_config* c) {
 // auto_plan() is the built-in heuristic; the autotuner replaces it per
 // bucket through spff_set_plan().
 // ---------------------------------------------------------------------------
-bool reg_rows_ok(const spff_config* c) {
+bool reg_rows_ok(const spff_config* c, int kind = SPFF_FFT_REG) {
   const int M = c->nx / 2;
-  return c->precision == SPFF_FP32 && M >= 64 && M <= 512;
+  return c->precision == SPFF_FP32 && M >= 64 && M <= (kind == SPFF_FFT_REG4 ? 256 : 512);
 }
 bool reg_cols_ok(const spff_config* c) {
   return c->precision == SPFF_FP32 && (c->ny == 128 || c->ny == 256 || c->ny == 512);
@@ -175,6 +175,16 @@ spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
         pl.row_threads = Rr * Lr;
       }
     }
+  } else if (reg_rows_ok(c, SPFF_FFT_REG4) && c->plan_rows == 0) {
+    // few wavefronts: 4 points per lane (twice the lanes per row) hides the
+    // per-lane latency better than either 8 points per lane or the LDS path
+    const int Lr = M / 4;
+    const int Rr = std::max(1, 64 / Lr);
+    if (Rr <= c->ny) {
+      pl.row_kind = SPFF_FFT_REG4;
+      pl.rows = Rr;
+      pl.row_threads = Rr * Lr;
+    }
   }
   return pl;
 }
@@ -183,9 +193,10 @@ spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
 // the register kinds.
 spff_status check_plan(const spff_config* c, spff_plan* pl, size_t csize) {
   const int M = c->nx / 2;
-  if (pl->row_kind == SPFF_FFT_REG) {
-    if (!reg_rows_ok(c)) return fail(SPFF_E_INVALID, "register row FFT needs FP32 and 128 <= nx <= 1024");
-    const int Lr = M / 8;
+  if (pl->row_kind == SPFF_FFT_REG || pl->row_kind == SPFF_FFT_REG4) {
+    if (!reg_rows_ok(c, pl->row_kind))
+      return fail(SPFF_E_INVALID, "register row FFT needs FP32 and 128 <= nx <= 1024 (512 with 4 points per lane)");
+    const int Lr = M / (pl->row_kind == SPFF_FFT_REG4 ? 4 : 8);
     if (!pow2(pl->rows) || pl->rows * Lr < 64 || pl->rows * Lr > THREADS || pl->rows > c->ny)
       return fail(SPFF_E_INVALID, "register row FFT: rows * nx/16 must be a power of two in [64, %d]", THREADS);
     pl->row_threads = pl->rows * Lr;
@@ -226,7 +237,7 @@ LaunchGeom geom_from_plan(const spff_config* c, int S, size_t csize, const spff_
   G.R = pl.rows;
   G.ngr = c->ny / pl.rows;
   G.threads = pl.row_threads;
-  G.row_reg = pl.row_kind == SPFF_FFT_REG;
+  G.row_reg = pl.row_kind == SPFF_FFT_REG ? 1 : (pl.row_kind == SPFF_FFT_REG4 ? 2 : 0);
   G.lds_row = G.row_reg ? ((size_t)pl.rows * (M + M / 8) + (size_t)M * (pl.rows + 1)) * csize
                         : 3 * (size_t)pl.rows * (M + PAD) * csize;
   G.W = pl.cols;

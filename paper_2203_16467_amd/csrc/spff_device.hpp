@@ -362,7 +362,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // reading one component of many work-groups reads contiguous memory).
 // red: LDS scratch of at least (blockDim.x/64) * NP doubles.
 template <int NP>
-__device__ void block_reduce_store(double (&acc)[NP], double* red, double* out, int cstride, int maxslot = -1) {
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NP], double* red, double* out, int cstride, int maxslot = -1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int i = 0; i < NP; ++i) {

@@ -111,26 +111,31 @@ __device__ __forceinline__ RowCtx<real> row_ctx(const SlotCtl& ctl, const SlotPa
 // Row-forward prologue for the pixel pair (o, o + 1): the phase's pointwise
 // work, the values entering the transforms (val[c][0..1]) and the FP64
 // partial sums.
-template <typename real>
-__device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotParam& P, const SlotPtr<real>& F,
-                                             int o, real (&val)[3][2], double (&acc)[NP_ROW]) {
-  const int phase = X.phase, flags = X.flags, split = X.split, n = X.n, ncomp = X.ncomp;
+template <typename real, int PH = -1>
+__device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotParam& P, const real* __restrict__ Ep,
+                                             real* __restrict__ phip, real* __restrict__ prefp,
+                                             real* __restrict__ epsp, real* __restrict__ thp,
+                                             real* __restrict__ rmp, real* __restrict__ pmp, int o,
+                                             real (&val)[3][2], double (&acc)[NP_ROW]) {
+  // PH >= 0: the phase is known at compile time (the other cases fold away)
+  const int phase = PH >= 0 ? PH : X.phase;
+  const int flags = X.flags, split = X.split, n = X.n, ncomp = X.ncomp;
   const real lt = X.lt, mt = X.mt, kres = X.kres, eb0 = X.eb0, eb1 = X.eb1, eb2 = X.eb2;
 #pragma unroll
   for (int q = 0; q < 2; ++q) val[0][q] = val[1][q] = val[2][q] = real(0);
   switch (phase) {
     case PH_M_RES: {
-      const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
-      if (flags & FL_FIRST_OF_STEP) st2(F.phi_ref + o, ph.a, ph.b);
-      V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
+      const V2<real> E = ld2(Ep + o), ph = ld2(phip + o);
+      if (flags & FL_FIRST_OF_STEP) st2(prefp + o, ph.a, ph.b);
+      V2<real> ex = ld2(epsp + o), ey = ld2(epsp + n + o), exy = ld2(epsp + 2 * n + o);
       if (flags & FL_THETA_PENDING) {
-        const V2<real> tx = ld2(F.theta + o), ty = ld2(F.theta + n + o), txy = ld2(F.theta + 2 * n + o);
+        const V2<real> tx = ld2(thp + o), ty = ld2(thp + n + o), txy = ld2(thp + 2 * n + o);
         ex = {ex.a + tx.a, ex.b + tx.b};
         ey = {ey.a + ty.a, ey.b + ty.b};
         exy = {exy.a + txy.a, exy.b + txy.b};
-        st2(F.eps + o, ex.a, ex.b);
-        st2(F.eps + n + o, ey.a, ey.b);
-        st2(F.eps + 2 * n + o, exy.a, exy.b);
+        st2(epsp + o, ex.a, ex.b);
+        st2(epsp + n + o, ey.a, ey.b);
+        st2(epsp + 2 * n + o, exy.a, exy.b);
       }
       const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
       const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
@@ -151,23 +156,23 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       break;
     }
     case PH_M_CG: {
-      const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
-      V2<real> px = ld2(F.rm + o), py = ld2(F.rm + n + o), pxy = ld2(F.rm + 2 * n + o);
+      const V2<real> E = ld2(Ep + o), ph = ld2(phip + o);
+      V2<real> px = ld2(rmp + o), py = ld2(rmp + n + o), pxy = ld2(rmp + 2 * n + o);
       if (!(flags & FL_CG_FIRST)) {
         const real bt = real(X.beta_m);
-        const V2<real> qx = ld2(F.pm + o), qy = ld2(F.pm + n + o), qxy = ld2(F.pm + 2 * n + o);
+        const V2<real> qx = ld2(pmp + o), qy = ld2(pmp + n + o), qxy = ld2(pmp + 2 * n + o);
         px = {px.a + bt * qx.a, px.b + bt * qx.b};
         py = {py.a + bt * qy.a, py.b + bt * qy.b};
         pxy = {pxy.a + bt * qxy.a, pxy.b + bt * qxy.b};
       }
-      st2(F.pm + o, px.a, px.b);
-      st2(F.pm + n + o, py.a, py.b);
-      st2(F.pm + 2 * n + o, pxy.a, pxy.b);
+      st2(pmp + o, px.a, px.b);
+      st2(pmp + n + o, py.a, py.b);
+      st2(pmp + 2 * n + o, pxy.a, pxy.b);
       V2<real> ex = {0, 0}, ey = {0, 0}, exy = {0, 0};
       if (split != 0) {
-        ex = ld2(F.eps + o);
-        ey = ld2(F.eps + n + o);
-        exy = ld2(F.eps + 2 * n + o);
+        ex = ld2(epsp + o);
+        ey = ld2(epsp + n + o);
+        exy = ld2(epsp + 2 * n + o);
       }
       const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
       const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
@@ -187,8 +192,8 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       break;
     }
     case PH_PF_ASM: {
-      const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o), pr = ld2(F.phi_ref + o);
-      const V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
+      const V2<real> E = ld2(Ep + o), ph = ld2(phip + o), pr = ld2(prefp + o);
+      const V2<real> ex = ld2(epsp + o), ey = ld2(epsp + n + o), exy = ld2(epsp + 2 * n + o);
       const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b}, rv[2] = {pr.a, pr.b};
       const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
       real dv[2], bv[2], cv[2];
@@ -205,26 +210,26 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
         acc[0] += double(bv[q]) * double(bv[q]);
         val[0][q] = cv[q];
       }
-      st2(F.theta + o, dv[0], dv[1]);
-      st2(F.theta + n + o, bv[0], bv[1]);
-      st2(F.theta + 2 * n + o, ph.a, ph.b);  // phi at the start of this PF solve
-      st2(F.phi + o, cv[0], cv[1]);
+      st2(thp + o, dv[0], dv[1]);
+      st2(thp + n + o, bv[0], bv[1]);
+      st2(thp + 2 * n + o, ph.a, ph.b);  // phi at the start of this PF solve
+      st2(phip + o, cv[0], cv[1]);
       break;
     }
     case PH_PF_PQ: {
-      const V2<real> r = ld2(F.rm + o), d = ld2(F.theta + o);
+      const V2<real> r = ld2(rmp + o), d = ld2(thp + o);
       V2<real> p;
       if (flags & FL_PF_FIRST) {
         p = {-r.a, -r.b};
       } else {
-        const V2<real> po = ld2(F.pm + o);
+        const V2<real> po = ld2(pmp + o);
         const real bt = real(X.beta_pf);
         p = {-r.a + bt * po.a, -r.b + bt * po.b};
       }
-      const unsigned char* mask = reinterpret_cast<const unsigned char*>(F.pm + n);
+      const unsigned char* mask = reinterpret_cast<const unsigned char*>(pmp + n);
       if (mask[o]) p.a = real(0);
       if (mask[o + 1]) p.b = real(0);
-      st2(F.pm + o, p.a, p.b);
+      st2(pmp + o, p.a, p.b);
       acc[0] += double(d.a) * double(p.a) * double(p.a) + double(d.b) * double(p.b) * double(p.b);
       acc[1] += double(r.a) * double(p.a) + double(r.b) * double(p.b);
       val[0][0] = p.a;
@@ -232,23 +237,23 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       break;
     }
     case PH_PF_R: {
-      const V2<real> ph = ld2(F.phi + o), p = ld2(F.pm + o), pr = ld2(F.phi_ref + o);
+      const V2<real> ph = ld2(phip + o), p = ld2(pmp + o), pr = ld2(prefp + o);
       const real al = real(X.alpha_pf);
       const real a0 = fmin(fmax(ph.a + al * p.a, lower_bound(pr.a, P)), real(1));
       const real a1 = fmin(fmax(ph.b + al * p.b, lower_bound(pr.b, P)), real(1));
-      st2(F.phi + o, a0, a1);
+      st2(phip + o, a0, a1);
       val[0][0] = a0;
       val[0][1] = a1;
       break;
     }
     case PH_AM_CHK: {
-      const V2<real> ph = ld2(F.phi + o), pa = ld2(F.theta + 2 * n + o);
+      const V2<real> ph = ld2(phip + o), pa = ld2(thp + 2 * n + o);
       acc[0] += fabs(double(ph.a) - double(pa.a)) + fabs(double(ph.b) - double(pa.b));
       break;
     }
     case PH_STATS: {
-      const V2<real> E = ld2(F.E + o), ph = ld2(F.phi + o);
-      const V2<real> ex = ld2(F.eps + o), ey = ld2(F.eps + n + o), exy = ld2(F.eps + 2 * n + o);
+      const V2<real> E = ld2(Ep + o), ph = ld2(phip + o);
+      const V2<real> ex = ld2(epsp + o), ey = ld2(epsp + n + o), exy = ld2(epsp + 2 * n + o);
       const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
       const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
 #pragma unroll
@@ -273,16 +278,52 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
     }
     case PH_X_PROJ:
     case PH_X_LAP: {
-      for (int c = 0; c < ncomp; ++c) {
-        const V2<real> t = ld2(F.theta + c * n + o);
-        val[c][0] = t.a;
-        val[c][1] = t.b;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c < ncomp) {
+          const V2<real> t = ld2(thp + c * n + o);
+          val[c][0] = t.a;
+          val[c][1] = t.b;
+        }
       }
       break;
     }
     default:
       break;
   }
+}
+
+// The prologue for NQ pixel pairs o0 + q OSTEP of one lane.  The field
+// pointers are restrict-qualified here so that the loads of later pairs may
+// be issued before the stores of earlier ones (the pairs never overlap).
+template <typename real, int NQ, int OSTEP>
+__device__ __forceinline__ void row_prologue_n(const RowCtx<real>& X, const SlotParam& P, const real* __restrict__ Ep,
+                                               real* __restrict__ phip, real* __restrict__ prefp,
+                                               real* __restrict__ epsp, real* __restrict__ thp,
+                                               real* __restrict__ rmp, real* __restrict__ pmp, int o0,
+                                               real (&val)[NQ][3][2], double (&acc)[NP_ROW]) {
+#define SPFF_PRO_CASE(PHC)                                                                                 \
+  case PHC:                                                                                               \
+    _Pragma("unroll") for (int q = 0; q < NQ; ++q)                                                        \
+        row_prologue<real, PHC>(X, P, Ep, phip, prefp, epsp, thp, rmp, pmp, o0 + q * OSTEP, val[q], acc); \
+    break;
+  switch (X.phase) {
+    SPFF_PRO_CASE(PH_M_RES)
+    SPFF_PRO_CASE(PH_M_CG)
+    SPFF_PRO_CASE(PH_PF_ASM)
+    SPFF_PRO_CASE(PH_PF_PQ)
+    SPFF_PRO_CASE(PH_PF_R)
+    SPFF_PRO_CASE(PH_AM_CHK)
+    SPFF_PRO_CASE(PH_STATS)
+    SPFF_PRO_CASE(PH_X_PROJ)
+    SPFF_PRO_CASE(PH_X_LAP)
+    default:
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        val[q][0][0] = val[q][0][1] = val[q][1][0] = val[q][1][1] = val[q][2][0] = val[q][2][1] = real(0);
+      break;
+  }
+#undef SPFF_PRO_CASE
 }
 
 // ===========================================================================
@@ -327,7 +368,7 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
     const int o = (y0 + r) * nx + 2 * h;
     const int li = r * stride + h;  // LDS index of component 0
     real val[3][2];
-    row_prologue<real>(X, P, F, o, val, acc);
+    row_prologue<real>(X, P, F.E, F.phi, F.phi_ref, F.eps, F.theta, F.rm, F.pm, o, val, acc);
     if (ncomp > 0) {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
@@ -353,8 +394,9 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
 
 // ---------------------------------------------------------------------------
 // Row kernels with register-resident transforms (M = nx/2 in {64 .. 512},
-// FP32): a group of L = M/8 lanes owns one row (R = blockDim/L rows per
-// work-group); lane l holds z[h] = x[2h] + i x[2h+1] for h = l + m L.  The
+// FP32): a group of L = M/E lanes (E = 8 or 4 points per lane) owns one row
+// (R = blockDim/L rows per work-group); lane l holds z[h] = x[2h] + i x[2h+1]
+// for h = l + m L.  The
 // prologue / epilogue run per pixel pair on the registers; the real <->
 // half-spectrum step pairs bin k with M - k by a cross-lane shuffle (same
 // pattern as the packed column); the transposed spectrum store / load goes
@@ -363,7 +405,6 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
 // ---------------------------------------------------------------------------
 template <int M>
 struct RowLds {
-  static constexpr int L = M / 8;
   // exchange areas of the R row groups, then the [kx][row] tile
   static __device__ __forceinline__ int tile_index(int k, int r, int R) { return k * (R + 1) + r; }
   static size_t bytes(int R, size_t csize) {
@@ -387,13 +428,13 @@ __device__ __forceinline__ void partner_bins(const cplx<real> (&v)[E], cplx<real
   }
 }
 
-template <typename real, int M>
+template <typename real, int M, int E>
 __device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                                const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
                                                const cplx<real>* __restrict__ twx, double* __restrict__ part,
                                                int ny, int ngr) {
   using C = cplx<real>;
-  constexpr int E = 8, L = M / 8, nx = 2 * M;
+  constexpr int L = M / E, nx = 2 * M;
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_ROW];
   int g, si;
@@ -419,13 +460,14 @@ __device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, con
   const RowCtx<real> X = row_ctx<real>(ctl, P, phase, ncomp, n);
 
   C v[3][E];
+  {
+    real val[E][3][2];
+    row_prologue_n<real, E, 2 * L>(X, P, F.E, F.phi, F.phi_ref, F.eps, F.theta, F.rm, F.pm,
+                                   (y0 + row) * nx + 2 * lane, val, acc);
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int o = (y0 + row) * nx + 2 * (lane + m * L);
-    real val[3][2];
-    row_prologue<real>(X, P, F, o, val, acc);
+    for (int m = 0; m < E; ++m)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[c][m] = mk<C>(val[c][0], val[c][1]);
+      for (int c = 0; c < 3; ++c) v[c][m] = mk<C>(val[m][c][0], val[m][c][1]);
   }
   if (ncomp > 0) {
     C* spec = reinterpret_cast<C*>(F.spec);
@@ -465,14 +507,14 @@ __device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, con
   block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, phase == PH_STATS ? 3 : -1);
 }
 
-template <typename real, int M>
+template <typename real, int M, int E>
 __device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                                const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
                                                const cplx<real>* __restrict__ twx,
                                                const double* __restrict__ part_row, double* __restrict__ part,
                                                int ny, int ngr) {
   using C = cplx<real>;
-  constexpr int E = 8, L = M / 8, nx = 2 * M;
+  constexpr int L = M / E, nx = 2 * M;
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_INV];
   __shared__ double scal[1];
@@ -552,13 +594,14 @@ __device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, con
     }
   }
   double acc[NP_INV] = {0.0, 0.0, 0.0, 0.0};
+  {
+    C q[E][3];
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int o = (y0 + row) * nx + 2 * (lane + m * L);
-    C q[3];
+    for (int m = 0; m < E; ++m)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) q[c] = c < ncomp ? v[c][m] : mk<C>(real(0), real(0));
-    row_epilogue<real>(X, P, F, o, q, alpha, acc);
+      for (int c = 0; c < 3; ++c) q[m][c] = c < ncomp ? v[c][m] : mk<C>(real(0), real(0));
+    row_epilogue_n<real, E, 2 * L>(X, P, F.phi, F.phi_ref, F.theta, F.rm, F.pm, (y0 + row) * nx + 2 * lane, q,
+                                   alpha, acc);
   }
   block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr);
 }
@@ -901,17 +944,20 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
 
 // Row-inverse epilogue for the pixel pair (o, o + 1): q[c] holds the
 // transformed values of component c at the pair (x: o, y: o + 1).
-template <typename real>
-__device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotParam& P, const SlotPtr<real>& F,
-                                             int o, const cplx<real> (&q)[3], real alpha, double (&acc)[NP_INV]) {
+template <typename real, int PH = -1>
+__device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotParam& P, real* __restrict__ phip,
+                                             real* __restrict__ prefp, real* __restrict__ thp,
+                                             real* __restrict__ rmp, real* __restrict__ pmp, int o,
+                                             const cplx<real> (&q)[3], real alpha, double (&acc)[NP_INV]) {
   using C = cplx<real>;
-  const int phase = X.phase, n = X.n, ncomp = X.ncomp;
+  const int phase = PH >= 0 ? PH : X.phase;
+  const int n = X.n, ncomp = X.ncomp;
   switch (phase) {
     case PH_M_RES: {
       const C q0 = q[0], q1 = q[1], q2 = q[2];
-      st2(F.rm + o, -q0.x, -q0.y);
-      st2(F.rm + n + o, -q1.x, -q1.y);
-      st2(F.rm + 2 * n + o, -q2.x, -q2.y);
+      st2(rmp + o, -q0.x, -q0.y);
+      st2(rmp + n + o, -q1.x, -q1.y);
+      st2(rmp + 2 * n + o, -q2.x, -q2.y);
       acc[0] += double(q0.x) * q0.x + double(q0.y) * q0.y + double(q1.x) * q1.x + double(q1.y) * q1.y +
                 2.0 * (double(q2.x) * q2.x + double(q2.y) * q2.y);
       break;
@@ -920,13 +966,13 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
       const bool first = X.flags & FL_CG_FIRST;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const V2<real> p = ld2(F.pm + c * n + o);
-        V2<real> r2 = ld2(F.rm + c * n + o);
-        V2<real> th = first ? V2<real>{0, 0} : ld2(F.theta + c * n + o);
+        const V2<real> p = ld2(pmp + c * n + o);
+        V2<real> r2 = ld2(rmp + c * n + o);
+        V2<real> th = first ? V2<real>{0, 0} : ld2(thp + c * n + o);
         th = {th.a + alpha * p.a, th.b + alpha * p.b};
         r2 = {r2.a - alpha * q[c].x, r2.b - alpha * q[c].y};
-        st2(F.theta + c * n + o, th.a, th.b);
-        st2(F.rm + c * n + o, r2.a, r2.b);
+        st2(thp + c * n + o, th.a, th.b);
+        st2(rmp + c * n + o, r2.a, r2.b);
         const double wc = c == 2 ? 2.0 : 1.0;
         acc[0] += wc * (double(r2.a) * r2.a + double(r2.b) * r2.b);
       }
@@ -935,8 +981,8 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
     case PH_PF_ASM:
     case PH_PF_R: {
       const C lap = q[0];
-      const V2<real> ph = ld2(F.phi + o), d = ld2(F.theta + o), b = ld2(F.theta + n + o);
-      const V2<real> pr = ld2(F.phi_ref + o);
+      const V2<real> ph = ld2(phip + o), d = ld2(thp + o), b = ld2(thp + n + o);
+      const V2<real> pr = ld2(prefp + o);
       const real rr0 = d.a * ph.a + lap.x - b.a;
       const real rr1 = d.b * ph.b + lap.y - b.b;
       const real lo0 = lower_bound(pr.a, P), lo1 = lower_bound(pr.b, P);
@@ -944,11 +990,11 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
       const bool a1 = (ph.b <= lo1 && rr1 > real(0)) || (ph.b >= real(1) && rr1 < real(0));
       const real r0 = a0 ? real(0) : rr0, r1 = a1 ? real(0) : rr1;
       if (phase == PH_PF_R) {
-        const V2<real> ro = ld2(F.rm + o);
+        const V2<real> ro = ld2(rmp + o);
         acc[1] += double(r0) * ro.a + double(r1) * ro.b;
       }
-      st2(F.rm + o, r0, r1);
-      unsigned char* mask = reinterpret_cast<unsigned char*>(F.pm + n);
+      st2(rmp + o, r0, r1);
+      unsigned char* mask = reinterpret_cast<unsigned char*>(pmp + n);
       mask[o] = a0 ? 1 : 0;
       mask[o + 1] = a1 ? 1 : 0;
       acc[0] += double(r0) * r0 + double(r1) * r1;
@@ -960,12 +1006,37 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
     case PH_X_LAP: {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        if (c < ncomp) st2(F.rm + c * n + o, q[c].x, q[c].y);
+        if (c < ncomp) st2(rmp + c * n + o, q[c].x, q[c].y);
       break;
     }
     default:
       break;
   }
+}
+
+// The epilogue for NQ pixel pairs o0 + q OSTEP of one lane (restrict
+// pointers: see row_prologue_n).
+template <typename real, int NQ, int OSTEP>
+__device__ __forceinline__ void row_epilogue_n(const RowCtx<real>& X, const SlotParam& P, real* __restrict__ phip,
+                                               real* __restrict__ prefp, real* __restrict__ thp,
+                                               real* __restrict__ rmp, real* __restrict__ pmp, int o0,
+                                               const cplx<real> (&q)[NQ][3], real alpha, double (&acc)[NP_INV]) {
+#define SPFF_EPI_CASE(PHC)                                                                             \
+  case PHC:                                                                                           \
+    _Pragma("unroll") for (int i = 0; i < NQ; ++i)                                                    \
+        row_epilogue<real, PHC>(X, P, phip, prefp, thp, rmp, pmp, o0 + i * OSTEP, q[i], alpha, acc); \
+    break;
+  switch (X.phase) {
+    SPFF_EPI_CASE(PH_M_RES)
+    SPFF_EPI_CASE(PH_M_CG)
+    SPFF_EPI_CASE(PH_PF_ASM)
+    SPFF_EPI_CASE(PH_PF_R)
+    SPFF_EPI_CASE(PH_X_PROJ)
+    SPFF_EPI_CASE(PH_X_LAP)
+    default:
+      break;
+  }
+#undef SPFF_EPI_CASE
 }
 
 // ===========================================================================
@@ -1046,7 +1117,7 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
     C q[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) q[c] = c < ncomp ? buf[c * R * stride + li] : mk<C>(real(0), real(0));
-    row_epilogue<real>(X, P, F, o, q, alpha, acc);
+    row_epilogue<real>(X, P, F.phi, F.phi_ref, F.theta, F.rm, F.pm, o, q, alpha, acc);
   }
   block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr);
 }
@@ -1446,7 +1517,7 @@ __global__ __launch_bounds__(THREADS) void k_colr(const int* __restrict__ list, 
   kt_end(kt);
 }
 
-template <typename real, int M>
+template <typename real, int M, int E>
 __global__ __launch_bounds__(THREADS) void k_rowfwdr(const int* __restrict__ list,
                                                      const SlotPtr<real>* __restrict__ ptrs,
                                                      const SlotParam* __restrict__ prms,
@@ -1454,11 +1525,11 @@ __global__ __launch_bounds__(THREADS) void k_rowfwdr(const int* __restrict__ lis
                                                      const cplx<real>* __restrict__ twx, double* __restrict__ part,
                                                      int ny, int ngr, KTime* kt) {
   kt_begin(kt);
-  k_rowfwdr_body<real, M>(list, ptrs, prms, ctls, twx, part, ny, ngr);
+  k_rowfwdr_body<real, M, E>(list, ptrs, prms, ctls, twx, part, ny, ngr);
   kt_end(kt);
 }
 
-template <typename real, int M>
+template <typename real, int M, int E>
 __global__ __launch_bounds__(THREADS) void k_rowinvr(const int* __restrict__ list,
                                                      const SlotPtr<real>* __restrict__ ptrs,
                                                      const SlotParam* __restrict__ prms,
@@ -1467,7 +1538,7 @@ __global__ __launch_bounds__(THREADS) void k_rowinvr(const int* __restrict__ lis
                                                      const double* __restrict__ part_row, double* __restrict__ part,
                                                      int ny, int ngr, KTime* kt) {
   kt_begin(kt);
-  k_rowinvr_body<real, M>(list, ptrs, prms, ctls, twx, part_row, part, ny, ngr);
+  k_rowinvr_body<real, M, E>(list, ptrs, prms, ctls, twx, part_row, part, ny, ngr);
   kt_end(kt);
 }
 
@@ -1584,14 +1655,22 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
   if constexpr (std::is_same<real, float>::value) {
     if (G.row_reg) {
       row_done = true;
-#define SPFF_ROWS_FWD(MM)                                                                                      \
-  hipLaunchKernelGGL((k_rowfwdr<real, MM>), grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, \
+#define SPFF_ROWS_FWD(MM, EE)                                                                                   \
+  hipLaunchKernelGGL((k_rowfwdr<real, MM, EE>), grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, \
                      prow, G.ny, G.ngr, ktf)
-      switch (G.nx) {
-        case 128: SPFF_ROWS_FWD(64); break;
-        case 256: SPFF_ROWS_FWD(128); break;
-        case 512: SPFF_ROWS_FWD(256); break;
-        default: SPFF_ROWS_FWD(512); break;
+      if (G.row_reg == 2) {
+        switch (G.nx) {
+          case 128: SPFF_ROWS_FWD(64, 4); break;
+          case 256: SPFF_ROWS_FWD(128, 4); break;
+          default: SPFF_ROWS_FWD(256, 4); break;
+        }
+      } else {
+        switch (G.nx) {
+          case 128: SPFF_ROWS_FWD(64, 8); break;
+          case 256: SPFF_ROWS_FWD(128, 8); break;
+          case 512: SPFF_ROWS_FWD(256, 8); break;
+          default: SPFF_ROWS_FWD(512, 8); break;
+        }
       }
 #undef SPFF_ROWS_FWD
     }
@@ -1625,14 +1704,22 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
                        G.nx, G.ny, G.W, G.ngc, ktc);
   if (row_done) {
     if constexpr (std::is_same<real, float>::value) {
-#define SPFF_ROWS_INV(MM)                                                                                      \
-  hipLaunchKernelGGL((k_rowinvr<real, MM>), grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, \
+#define SPFF_ROWS_INV(MM, EE)                                                                                   \
+  hipLaunchKernelGGL((k_rowinvr<real, MM, EE>), grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, \
                      prow, pinv, G.ny, G.ngr, kti)
-      switch (G.nx) {
-        case 128: SPFF_ROWS_INV(64); break;
-        case 256: SPFF_ROWS_INV(128); break;
-        case 512: SPFF_ROWS_INV(256); break;
-        default: SPFF_ROWS_INV(512); break;
+      if (G.row_reg == 2) {
+        switch (G.nx) {
+          case 128: SPFF_ROWS_INV(64, 4); break;
+          case 256: SPFF_ROWS_INV(128, 4); break;
+          default: SPFF_ROWS_INV(256, 4); break;
+        }
+      } else {
+        switch (G.nx) {
+          case 128: SPFF_ROWS_INV(64, 8); break;
+          case 256: SPFF_ROWS_INV(128, 8); break;
+          case 512: SPFF_ROWS_INV(256, 8); break;
+          default: SPFF_ROWS_INV(512, 8); break;
+        }
       }
 #undef SPFF_ROWS_INV
     }

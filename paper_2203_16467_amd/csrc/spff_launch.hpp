@@ -18,7 +18,7 @@ struct LaunchGeom {
   int threads;      // threads per row work-group
   int threads_col;  // threads per column work-group
   int col_reg;      // column kernel with register-resident transforms
-  int row_reg;      // row kernels with register-resident transforms
+  int row_reg;      // row kernels with register-resident transforms: 1 = 8, 2 = 4 points per lane
   size_t lds_row, lds_col;
 };
 

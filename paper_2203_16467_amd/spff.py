@@ -84,7 +84,7 @@ class Profile(ctypes.Structure):
                 "alg_bytes": dict(zip(self.KERNELS, self.alg_bytes)), "ticks": self.ticks}
 
 
-FFT_LDS, FFT_REG = 1, 2
+FFT_LDS, FFT_REG, FFT_REG4 = 1, 2, 3
 
 
 class Plan(ctypes.Structure):

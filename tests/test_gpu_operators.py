@@ -101,6 +101,8 @@ def test_every_plan_candidate_gives_the_operators(nx, ny):
     assert ("row", spff.FFT_LDS) in kinds and ("col", spff.FFT_LDS) in kinds
     if 128 <= nx <= 1024:
         assert ("row", spff.FFT_REG) in kinds
+    if 128 <= nx <= 512:
+        assert ("row", spff.FFT_REG4) in kinds
     if ny in (128, 256, 512):
         assert ("col", spff.FFT_REG) in kinds
     p.close()
