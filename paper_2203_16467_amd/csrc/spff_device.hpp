@@ -345,15 +345,44 @@ __device__ void c2r_pre(cplx<real>* buf, int M, int ntrans, int stride, const cp
 // ---------------------------------------------------------------------------
 // Deterministic FP64 reductions.
 // ---------------------------------------------------------------------------
+// A wavefront (all 64 lanes active) combines its values in a fixed pattern:
+// four DPP steps inside each row of 16 lanes (partner lane i^1, i^2, then the
+// mirrored half-row and half of the row), after which every lane of a row
+// holds the row's total; the four row totals are then read out and combined
+// as (r0 + r1) + (r2 + r3).  Each step adds two values that both partners
+// hold, so every lane of a row computes the identical sum; the result is the
+// same in every lane and independent of timing.  DPP moves cost a few cycles
+// where a cross-lane shuffle through the LDS crossbar costs ~100.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi2, lo2);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8
+constexpr int DPP_ROW_MIRROR = 0x140;   // lane i <-> 15 - i within 16
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_move<DPP_QUAD_XOR1>(v);
+  v += dpp_move<DPP_QUAD_XOR2>(v);
+  v += dpp_move<DPP_HALF_MIRROR>(v);
+  v += dpp_move<DPP_ROW_MIRROR>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
+  v = fmax(v, dpp_move<DPP_QUAD_XOR1>(v));
+  v = fmax(v, dpp_move<DPP_QUAD_XOR2>(v));
+  v = fmax(v, dpp_move<DPP_HALF_MIRROR>(v));
+  v = fmax(v, dpp_move<DPP_ROW_MIRROR>(v));
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
 }
 
 // Reduce NP per-thread accumulators over the block; slot MAXSLOT (if >= 0)
@@ -361,21 +390,29 @@ __device__ __forceinline__ double wave_max(double v) {
 // out[i * cstride] (partials are stored component-major, so a wavefront
 // reading one component of many work-groups reads contiguous memory).
 // red: LDS scratch of at least (blockDim.x/64) * NP doubles.
+// Only the first `nused` accumulators (the ones the phase's controller step
+// reads) are reduced and stored: each costs a chain of cross-lane steps.
 template <int NP>
-__device__ __forceinline__ void block_reduce_store(double (&acc)[NP], double* red, double* out, int cstride, int maxslot = -1) {
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NP], double* red, double* out, int cstride,
+                                                   int nused, int maxslot = -1) {
+  if (nused <= 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
-    const double v = (i == maxslot) ? wave_max(acc[i]) : wave_sum(acc[i]);
-    if (lane == 0) red[wave * NP + i] = v;
+    if (i < nused) {
+      const double v = (i == maxslot) ? wave_max(acc[i]) : wave_sum(acc[i]);
+      if (lane == 0) red[wave * NP + i] = v;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
-      double s = red[i];
-      for (int w = 1; w < nw; ++w) s = (i == maxslot) ? fmax(s, red[w * NP + i]) : s + red[w * NP + i];
-      out[(size_t)i * cstride] = s;
+      if (i < nused) {
+        double s = red[i];
+        for (int w = 1; w < nw; ++w) s = (i == maxslot) ? fmax(s, red[w * NP + i]) : s + red[w * NP + i];
+        out[(size_t)i * cstride] = s;
+      }
     }
   }
 }

@@ -44,6 +44,36 @@ __device__ __forceinline__ int phase_comps_row(int phase) {
   }
 }
 
+// Number of FP64 partial sums a kernel's phase produces for the controller
+// (the leading entries of its accumulator array).
+__device__ __forceinline__ int nacc_rowfwd(int phase) {
+  switch (phase) {
+    case PH_M_RES:
+    case PH_PF_PQ:
+      return 2;
+    case PH_M_CG:
+    case PH_PF_ASM:
+    case PH_AM_CHK:
+      return 1;
+    case PH_STATS:
+      return NP_ROW;
+    default:
+      return 0;
+  }
+}
+__device__ __forceinline__ int nacc_rowinv(int phase) {
+  switch (phase) {
+    case PH_M_RES:
+    case PH_M_CG:
+      return 1;
+    case PH_PF_ASM:
+    case PH_PF_R:
+      return NP_INV;
+    default:
+      return 0;
+  }
+}
+
 // Row-kernel coordinates (row group g, list index si) of this work-group.
 // Work-groups are dispatched to the 8 XCDs round-robin by linear id; the
 // remap gives consecutive row groups of a slot to one XCD, so the short
@@ -389,221 +419,8 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
       spec[(size_t)(rest) * ny + y0 + r] = buf[(c * R + r) * stride + kx];
     }
   }
-  block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, phase == PH_STATS ? 3 : -1);
-}
-
-// ---------------------------------------------------------------------------
-// Row kernels with register-resident transforms (M = nx/2 in {64 .. 512},
-// FP32): a group of L = M/E lanes (E = 8 or 4 points per lane) owns one row
-// (R = blockDim/L rows per work-group); lane l holds z[h] = x[2h] + i x[2h+1]
-// for h = l + m L.  The
-// prologue / epilogue run per pixel pair on the registers; the real <->
-// half-spectrum step pairs bin k with M - k by a cross-lane shuffle (same
-// pattern as the packed column); the transposed spectrum store / load goes
-// through an LDS tile [kx][row] so that R consecutive y of one kx move as
-// one run.
-// ---------------------------------------------------------------------------
-template <int M>
-struct RowLds {
-  // exchange areas of the R row groups, then the [kx][row] tile
-  static __device__ __forceinline__ int tile_index(int k, int r, int R) { return k * (R + 1) + r; }
-  static size_t bytes(int R, size_t csize) {
-    return ((size_t)R * XArea<M>::size + (size_t)M * (R + 1)) * csize;
-  }
-};
-
-// partner slots for bin k = l + m L and M - k: slot E-1-m of lane L-l, or
-// for lane 0 its own slot (E-m) mod E
-template <typename real, int E, int L>
-__device__ __forceinline__ void partner_bins(const cplx<real> (&v)[E], cplx<real> (&pn)[E], int lane) {
-  const int src = (L - lane) & (L - 1);
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const real px = __shfl(v[i].x, src, L), py = __shfl(v[i].y, src, L);
-    pn[E - 1 - i] = mk<cplx<real>>(px, py);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) pn[m] = v[(E - m) & (E - 1)];
-  }
-}
-
-template <typename real, int M, int E>
-__device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
-                                               const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
-                                               const cplx<real>* __restrict__ twx, double* __restrict__ part,
-                                               int ny, int ngr) {
-  using C = cplx<real>;
-  constexpr int L = M / E, nx = 2 * M;
-  extern __shared__ unsigned char smem_raw[];
-  __shared__ double red[(THREADS / 64) * NP_ROW];
-  int g, si;
-  row_coords(ngr, g, si);
-  const int s = list[si];
-  if (s < 0) return;
-  const SlotCtl& ctl = ctls[s];
-  const int phase = ctl.phase;
-  const int ncomp = phase_comps_row(phase);
-  if (phase != PH_AM_CHK && ncomp == 0) return;
-  const SlotParam& P = prms[s];
-  const SlotPtr<real> F = ptrs[s];
-  const int R = blockDim.x / L;
-  const int row = threadIdx.x / L, lane = threadIdx.x & (L - 1);
-  const int y0 = g * R;
-  const int n = nx * ny;
-  C* xa = reinterpret_cast<C*>(smem_raw) + row * XArea<M>::size;
-  C* tile = reinterpret_cast<C*>(smem_raw) + R * XArea<M>::size;
-  double acc[NP_ROW];
-#pragma unroll
-  for (int i = 0; i < NP_ROW; ++i) acc[i] = 0.0;
-  if (phase == PH_STATS) acc[3] = -1.0e300;
-  const RowCtx<real> X = row_ctx<real>(ctl, P, phase, ncomp, n);
-
-  C v[3][E];
-  {
-    real val[E][3][2];
-    row_prologue_n<real, E, 2 * L>(X, P, F.E, F.phi, F.phi_ref, F.eps, F.theta, F.rm, F.pm,
-                                   (y0 + row) * nx + 2 * lane, val, acc);
-#pragma unroll
-    for (int m = 0; m < E; ++m)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) v[c][m] = mk<C>(val[m][c][0], val[m][c][1]);
-  }
-  if (ncomp > 0) {
-    C* spec = reinterpret_cast<C*>(F.spec);
-    const int logR = ilog2(R);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (c < ncomp) {
-        reg_fft<real, false, M, E>(v[c], xa, lane, twx, 2);
-        // half spectrum of the real row: X[k] = e + w^k o (k > 0), bin 0
-        // packs X[0] + i X[M]
-        C pn[E];
-        partner_bins<real, E, L>(v[c], pn, lane);
-        __syncthreads();  // the tile is free
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-          const int k = lane + m * L;
-          C out;
-          if (k == 0) {
-            out = mk<C>(v[c][m].x + v[c][m].y, v[c][m].x - v[c][m].y);
-          } else {
-            const C zk = v[c][m], zm = cconj(pn[m]);
-            const C e = cscale(cadd(zk, zm), real(0.5));
-            const C od = cscale(cmulni(csub(zk, zm)), real(0.5));
-            out = cadd(e, cmul(twx[k], od));
-          }
-          tile[RowLds<M>::tile_index(k, row, R)] = out;
-        }
-        __syncthreads();
-        // transposed store: spec[c][kx][y0 + r], r fastest
-        for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
-          const int r = idx & (R - 1), k = idx >> logR;
-          spec[(size_t)(c * M + k) * ny + y0 + r] = tile[RowLds<M>::tile_index(k, r, R)];
-        }
-      }
-    }
-  }
-  block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, phase == PH_STATS ? 3 : -1);
-}
-
-template <typename real, int M, int E>
-__device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
-                                               const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
-                                               const cplx<real>* __restrict__ twx,
-                                               const double* __restrict__ part_row, double* __restrict__ part,
-                                               int ny, int ngr) {
-  using C = cplx<real>;
-  constexpr int L = M / E, nx = 2 * M;
-  extern __shared__ unsigned char smem_raw[];
-  __shared__ double red[(THREADS / 64) * NP_INV];
-  __shared__ double scal[1];
-  int g, si;
-  row_coords(ngr, g, si);
-  const int s = list[si];
-  if (s < 0) return;
-  const SlotCtl& ctl = ctls[s];
-  const int phase = ctl.phase;
-  int ncomp;
-  switch (phase) {
-    case PH_M_RES:
-    case PH_M_CG:
-    case PH_X_PROJ:
-      ncomp = 3;
-      break;
-    case PH_PF_ASM:
-    case PH_PF_R:
-    case PH_X_LAP:
-      ncomp = 1;
-      break;
-    default:
-      return;
-  }
-  const SlotParam& P = prms[s];
-  const SlotPtr<real> F = ptrs[s];
-  const int R = blockDim.x / L;
-  const int row = threadIdx.x / L, lane = threadIdx.x & (L - 1);
-  const int y0 = g * R;
-  const int n = nx * ny;
-  const RowCtx<real> X = row_ctx<real>(ctl, P, phase, ncomp, n);
-  C* xa = reinterpret_cast<C*>(smem_raw) + row * XArea<M>::size;
-  C* tile = reinterpret_cast<C*>(smem_raw) + R * XArea<M>::size;
-  const C* spec = reinterpret_cast<const C*>(F.spec);
-
-  // CG step length from this tick's row-forward partials (same fixed-order
-  // reduction as the controller)
-  real alpha = 0;
-  if (phase == PH_M_CG) {
-    if (threadIdx.x < 64) {
-      const double pcp = wave_reduce_partials(part_row + (size_t)s * NP_ROW * ngr, ngr);
-      if (threadIdx.x == 0) scal[0] = (pcp > 0.0 && isfinite(pcp)) ? ctl.rr / pcp : 0.0;
-    }
-    __syncthreads();
-    alpha = real(scal[0]);
-  }
-
-  const int logR = ilog2(R);
-  C v[3][E];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (c < ncomp) {
-      if (c > 0) __syncthreads();  // the previous component's tile reads are done
-      for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
-        const int r = idx & (R - 1), k = idx >> logR;
-        tile[RowLds<M>::tile_index(k, r, R)] = spec[(size_t)(c * M + k) * ny + y0 + r];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[c][m] = tile[RowLds<M>::tile_index(lane + m * L, row, R)];
-      // from the packed half spectrum to Z whose unnormalised inverse FFT
-      // gives nx (x[2h] + i x[2h+1])
-      C pn[E];
-      partner_bins<real, E, L>(v[c], pn, lane);
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const int k = lane + m * L;
-        if (k == 0) {
-          v[c][m] = mk<C>(v[c][m].x + v[c][m].y, v[c][m].x - v[c][m].y);
-        } else {
-          const C xk = v[c][m], xm = cconj(pn[m]);
-          const C a = cadd(xk, xm), b = csub(xk, xm);
-          v[c][m] = cadd(a, cmuli(cmul(cconj(twx[k]), b)));
-        }
-      }
-      reg_fft<real, true, M, E>(v[c], xa, lane, twx, 2);
-    }
-  }
-  double acc[NP_INV] = {0.0, 0.0, 0.0, 0.0};
-  {
-    C q[E][3];
-#pragma unroll
-    for (int m = 0; m < E; ++m)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) q[m][c] = c < ncomp ? v[c][m] : mk<C>(real(0), real(0));
-    row_epilogue_n<real, E, 2 * L>(X, P, F.phi, F.phi_ref, F.theta, F.rm, F.pm, (y0 + row) * nx + 2 * lane, q,
-                                   alpha, acc);
-  }
-  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr);
+  block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, nacc_rowfwd(phase),
+                             phase == PH_STATS ? 3 : -1);
 }
 
 // ===========================================================================
@@ -772,7 +589,7 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
       spec[(size_t)(c * M + kx0 + w) * ny + y] = buf[rest * stride + y];
     }
   }
-  block_reduce_store<NP_COL>(acc, red, part + (size_t)s * NP_COL * ngc + g, ngc);
+  block_reduce_store<NP_COL>(acc, red, part + (size_t)s * NP_COL * ngc + g, ngc, mode == 2 ? 1 : 0);
 }
 
 // Column kernel with register-resident transforms (ny = N in {128, 256,
@@ -939,7 +756,7 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
       }
     }
   }
-  block_reduce_store<NP_COL>(acc, red, part + (size_t)s * NP_COL * ngc + g, ngc);
+  block_reduce_store<NP_COL>(acc, red, part + (size_t)s * NP_COL * ngc + g, ngc, mode == 2 ? 1 : 0);
 }
 
 // Row-inverse epilogue for the pixel pair (o, o + 1): q[c] holds the
@@ -1039,6 +856,221 @@ __device__ __forceinline__ void row_epilogue_n(const RowCtx<real>& X, const Slot
 #undef SPFF_EPI_CASE
 }
 
+// ---------------------------------------------------------------------------
+// Row kernels with register-resident transforms (M = nx/2 in {64 .. 512},
+// FP32): a group of L = M/E lanes (E = 8 or 4 points per lane) owns one row
+// (R = blockDim/L rows per work-group); lane l holds z[h] = x[2h] + i x[2h+1]
+// for h = l + m L.  The
+// prologue / epilogue run per pixel pair on the registers; the real <->
+// half-spectrum step pairs bin k with M - k by a cross-lane shuffle (same
+// pattern as the packed column); the transposed spectrum store / load goes
+// through an LDS tile [kx][row] so that R consecutive y of one kx move as
+// one run.
+// ---------------------------------------------------------------------------
+template <int M>
+struct RowLds {
+  // exchange areas of the R row groups, then the [kx][row] tile
+  static __device__ __forceinline__ int tile_index(int k, int r, int R) { return k * (R + 1) + r; }
+  static size_t bytes(int R, size_t csize) {
+    return ((size_t)R * XArea<M>::size + (size_t)M * (R + 1)) * csize;
+  }
+};
+
+// partner slots for bin k = l + m L and M - k: slot E-1-m of lane L-l, or
+// for lane 0 its own slot (E-m) mod E
+template <typename real, int E, int L>
+__device__ __forceinline__ void partner_bins(const cplx<real> (&v)[E], cplx<real> (&pn)[E], int lane) {
+  const int src = (L - lane) & (L - 1);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const real px = __shfl(v[i].x, src, L), py = __shfl(v[i].y, src, L);
+    pn[E - 1 - i] = mk<cplx<real>>(px, py);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) pn[m] = v[(E - m) & (E - 1)];
+  }
+}
+
+template <typename real, int M, int E>
+__device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                               const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
+                                               const cplx<real>* __restrict__ twx, double* __restrict__ part,
+                                               int ny, int ngr) {
+  using C = cplx<real>;
+  constexpr int L = M / E, nx = 2 * M;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[(THREADS / 64) * NP_ROW];
+  int g, si;
+  row_coords(ngr, g, si);
+  const int s = list[si];
+  if (s < 0) return;
+  const SlotCtl& ctl = ctls[s];
+  const int phase = ctl.phase;
+  const int ncomp = phase_comps_row(phase);
+  if (phase != PH_AM_CHK && ncomp == 0) return;
+  const SlotParam& P = prms[s];
+  const SlotPtr<real> F = ptrs[s];
+  const int R = blockDim.x / L;
+  const int row = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+  const int y0 = g * R;
+  const int n = nx * ny;
+  C* xa = reinterpret_cast<C*>(smem_raw) + row * XArea<M>::size;
+  C* tile = reinterpret_cast<C*>(smem_raw) + R * XArea<M>::size;
+  double acc[NP_ROW];
+#pragma unroll
+  for (int i = 0; i < NP_ROW; ++i) acc[i] = 0.0;
+  if (phase == PH_STATS) acc[3] = -1.0e300;
+  const RowCtx<real> X = row_ctx<real>(ctl, P, phase, ncomp, n);
+
+  C v[3][E];
+  {
+    real val[E][3][2];
+    row_prologue_n<real, E, 2 * L>(X, P, F.E, F.phi, F.phi_ref, F.eps, F.theta, F.rm, F.pm,
+                                   (y0 + row) * nx + 2 * lane, val, acc);
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c][m] = mk<C>(val[m][c][0], val[m][c][1]);
+  }
+  if (ncomp > 0) {
+    C* spec = reinterpret_cast<C*>(F.spec);
+    const int logR = ilog2(R);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c < ncomp) {
+        reg_fft<real, false, M, E>(v[c], xa, lane, twx, 2);
+        // half spectrum of the real row: X[k] = e + w^k o (k > 0), bin 0
+        // packs X[0] + i X[M]
+        C pn[E];
+        partner_bins<real, E, L>(v[c], pn, lane);
+        __syncthreads();  // the tile is free
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int k = lane + m * L;
+          C out;
+          if (k == 0) {
+            out = mk<C>(v[c][m].x + v[c][m].y, v[c][m].x - v[c][m].y);
+          } else {
+            const C zk = v[c][m], zm = cconj(pn[m]);
+            const C e = cscale(cadd(zk, zm), real(0.5));
+            const C od = cscale(cmulni(csub(zk, zm)), real(0.5));
+            out = cadd(e, cmul(twx[k], od));
+          }
+          tile[RowLds<M>::tile_index(k, row, R)] = out;
+        }
+        __syncthreads();
+        // transposed store: spec[c][kx][y0 + r], r fastest
+        for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
+          const int r = idx & (R - 1), k = idx >> logR;
+          spec[(size_t)(c * M + k) * ny + y0 + r] = tile[RowLds<M>::tile_index(k, r, R)];
+        }
+      }
+    }
+  }
+  block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, nacc_rowfwd(phase),
+                             phase == PH_STATS ? 3 : -1);
+}
+
+template <typename real, int M, int E>
+__device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                               const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
+                                               const cplx<real>* __restrict__ twx,
+                                               const double* __restrict__ part_row, double* __restrict__ part,
+                                               int ny, int ngr) {
+  using C = cplx<real>;
+  constexpr int L = M / E, nx = 2 * M;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[(THREADS / 64) * NP_INV];
+  int g, si;
+  row_coords(ngr, g, si);
+  const int s = list[si];
+  if (s < 0) return;
+  const SlotCtl& ctl = ctls[s];
+  const int phase = ctl.phase;
+  int ncomp;
+  switch (phase) {
+    case PH_M_RES:
+    case PH_M_CG:
+    case PH_X_PROJ:
+      ncomp = 3;
+      break;
+    case PH_PF_ASM:
+    case PH_PF_R:
+    case PH_X_LAP:
+      ncomp = 1;
+      break;
+    default:
+      return;
+  }
+  const SlotParam& P = prms[s];
+  const SlotPtr<real> F = ptrs[s];
+  const int R = blockDim.x / L;
+  const int row = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+  const int y0 = g * R;
+  const int n = nx * ny;
+  const RowCtx<real> X = row_ctx<real>(ctl, P, phase, ncomp, n);
+  C* xa = reinterpret_cast<C*>(smem_raw) + row * XArea<M>::size;
+  C* tile = reinterpret_cast<C*>(smem_raw) + R * XArea<M>::size;
+  const C* spec = reinterpret_cast<const C*>(F.spec);
+
+  // CG step length from this tick's row-forward partials (same fixed-order
+  // reduction as the controller)
+  __shared__ double scal[1];
+  real alpha = 0;
+  if (phase == PH_M_CG) {
+    if (threadIdx.x < 64) {
+      const double pcp = wave_reduce_partials(part_row + (size_t)s * NP_ROW * ngr, ngr);
+      if (threadIdx.x == 0) scal[0] = (pcp > 0.0 && isfinite(pcp)) ? ctl.rr / pcp : 0.0;
+    }
+    __syncthreads();
+    alpha = real(scal[0]);
+  }
+
+  const int logR = ilog2(R);
+  C v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c < ncomp) {
+      if (c > 0) __syncthreads();  // the previous component's tile reads are done
+      for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
+        const int r = idx & (R - 1), k = idx >> logR;
+        tile[RowLds<M>::tile_index(k, r, R)] = spec[(size_t)(c * M + k) * ny + y0 + r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[c][m] = tile[RowLds<M>::tile_index(lane + m * L, row, R)];
+      // from the packed half spectrum to Z whose unnormalised inverse FFT
+      // gives nx (x[2h] + i x[2h+1])
+      C pn[E];
+      partner_bins<real, E, L>(v[c], pn, lane);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int k = lane + m * L;
+        if (k == 0) {
+          v[c][m] = mk<C>(v[c][m].x + v[c][m].y, v[c][m].x - v[c][m].y);
+        } else {
+          const C xk = v[c][m], xm = cconj(pn[m]);
+          const C a = cadd(xk, xm), b = csub(xk, xm);
+          v[c][m] = cadd(a, cmuli(cmul(cconj(twx[k]), b)));
+        }
+      }
+      reg_fft<real, true, M, E>(v[c], xa, lane, twx, 2);
+    }
+  }
+  double acc[NP_INV] = {0.0, 0.0, 0.0, 0.0};
+  {
+    C q[E][3];
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) q[m][c] = c < ncomp ? v[c][m] : mk<C>(real(0), real(0));
+    row_epilogue_n<real, E, 2 * L>(X, P, F.phi, F.phi_ref, F.theta, F.rm, F.pm, (y0 + row) * nx + 2 * lane, q,
+                                   alpha, acc);
+  }
+  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr, nacc_rowinv(phase));
+}
+
 // ===========================================================================
 // Row-inverse kernel: transposed load -> C2R row FFTs -> epilogue (per
 // phase); FP64 partial sums per work-group.
@@ -1054,7 +1086,6 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
   using C = cplx<real>;
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_INV];
-  __shared__ double scal[1];
   int g, si;
   row_coords(ngr, g, si);
   const int s = list[si];
@@ -1086,7 +1117,8 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
   const C* spec = reinterpret_cast<const C*>(F.spec);
 
   // CG step length from this tick's row-forward partials (same fixed-order
-  // reduction as the controller).
+  // reduction as the controller)
+  __shared__ double scal[1];
   real alpha = 0;
   if (phase == PH_M_CG) {
     if (threadIdx.x < 64) {
@@ -1119,7 +1151,7 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
     for (int c = 0; c < 3; ++c) q[c] = c < ncomp ? buf[c * R * stride + li] : mk<C>(real(0), real(0));
     row_epilogue<real>(X, P, F.phi, F.phi_ref, F.theta, F.rm, F.pm, o, q, alpha, acc);
   }
-  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr);
+  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr, nacc_rowinv(phase));
 }
 
 // Algorithmic HBM bytes per pixel moved by the row-forward, column and
@@ -1178,6 +1210,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
                                        const double* __restrict__ pinv, double* __restrict__ prof,
                                        SlotSeq* __restrict__ seqs, StepRec* __restrict__ recs, int nx, int ny,
                                        int ngr, int ngc) {
+  const double* pr = prow + (size_t)s * NP_ROW * ngr;
+  const double* pc = pcol + (size_t)s * NP_COL * ngc;
+  const double* pi = pinv + (size_t)s * NP_INV * ngr;
   SlotCtl& C = ctls[s];
   const int phase = C.phase;
   if (phase == PH_IDLE) return;
@@ -1191,9 +1226,6 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
     prof[3 * s + 1] += b[1] * npx;
     prof[3 * s + 2] += b[2] * npx;
   }
-  const double* pr = prow + (size_t)s * NP_ROW * ngr;
-  const double* pc = pcol + (size_t)s * NP_COL * ngc;
-  const double* pi = pinv + (size_t)s * NP_INV * ngr;
   const double inv_n = 1.0 / (double(nx) * double(ny));
   // all lanes compute the same values; lane 0 writes
   double v[8];
@@ -1295,9 +1327,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
       break;
     }
     case PH_PF_PQ: {
-      v[0] = wave_reduce_partials(pr, ngr);      // sum d p^2
+      v[0] = wave_reduce_partials(pr, ngr);            // sum d p^2
       v[1] = wave_reduce_partials(pr + 1 * ngr, ngr);  // sum r p
-      v[2] = wave_reduce_partials(pc, ngc);      // sum L |p^|^2
+      v[2] = wave_reduce_partials(pc, ngc);            // sum L |p^|^2
       bad = !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
       pq = v[0] + P.kappa * inv_n * v[2];
       rp = v[1];
