@@ -21,10 +21,14 @@ is measured on its own (reported under breakdown.steady_all_active).
 
 Also reported on the same line:
   roofline      dominant kernel's algorithmic HBM bytes per launch / its
-                average execution time per launch, both over the timed
-                steps (the library's device-clock kernel timers on the
-                solver stream: first work-group start to last work-group
-                end of every launch, also inside captured graphs)
+                average time per launch, both over the timed steps (the
+                library's device-clock kernel timers on the solver stream,
+                also inside captured graphs: a launch's work-group activity
+                plus half of the dead time to the next kernel's first start,
+                which brackets a kernel trace's duration);
+                traffic = measured HBM bytes per launch from the committed
+                rocprofv3 --pmc record when it was taken on these kernel
+                sources, else null
   plain_gpu     the plain single-instance path (256x256, one problem, host
                 check after every tick, no graph) over its full 200-step
                 ramp, for each of AT1/AT2 x no split/spectral split
@@ -124,11 +128,11 @@ def batched_leg(args):
         pr = p.profile_read()
         p.profile_enable(False)
         cg1, pf1 = iters(stats)
+        kt1 = {k: 0.5 * (pr["kernel_ms"][k] + pr["kernel_span_ms"][k]) for k in KERNELS}
         steady = {"steps": [args.steady_start, args.steady_start + args.steady_steps - 1], "seconds": dt1,
                   "value": (cg1 + pf1) * n * n / dt1, "unit": "grid-pt-iters/s", "cg_iters": cg1,
-                  "bccg_iters": pf1, "kernel_ms": pr["kernel_ms"], "kernel_alg_bytes": pr["alg_bytes"],
-                  "kernel_alg_GBs": {k: pr["alg_bytes"][k] / (pr["kernel_ms"][k] * 1e-3) / 1e9
-                                     for k in KERNELS if pr["kernel_ms"][k] > 0}}
+                  "bccg_iters": pf1, "kernel_ms": kt1, "kernel_alg_bytes": pr["alg_bytes"],
+                  "kernel_alg_GBs": {k: pr["alg_bytes"][k] / (kt1[k] * 1e-3) / 1e9 for k in KERNELS if kt1[k] > 0}}
         log(f"[bench] steady window {steady['steps']}: {steady['value']:.3e} grid-pt-iters/s, "
             f"kernel GB/s {steady['kernel_alg_GBs']}")
         if s0 > args.steady_start + args.steady_steps:
@@ -245,6 +249,43 @@ def serving_leg(args):
             "loads": loads}
 
 
+KERNEL_SOURCES = ("spff_kernels.hip", "spff_device.hpp", "spff_engine.hpp")
+PMC_RECORD = os.path.join(ROOT, "profiles", "pmc_traffic_row_kernels_batched_64x512.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2203_16467_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(role):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 --pmc record (FETCH_SIZE and WRITE_SIZE in KiB per dispatch,
+    each scaled by the factor the same counter reads for a copy kernel of
+    known size), or None if the record is missing, covers another kernel
+    role, or was taken on kernel sources other than the ones built here."""
+    if not os.path.exists(PMC_RECORD):
+        return None
+    rec = {}
+    with open(PMC_RECORD) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    try:
+        if rec.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        fetch = float(rec[f"{role}.fetch_kib_per_dispatch"]) * float(rec["fetch_scale"])
+        write = float(rec[f"{role}.write_kib_per_dispatch"]) * float(rec["write_scale"])
+    except (KeyError, ValueError):
+        return None
+    return (fetch + write) * 1024.0
+
+
 def cpu_leg(res, budget_s):
     """The FP64 oracle on one host core, realization 0 of the workload, for as
     many load steps as fit the budget (at least one)."""
@@ -321,10 +362,14 @@ def main():
     res = batched_leg(args)
     value = (res["cg"] + res["pf"]) * res["n"] ** 2 / res["dt"]
     prof = res["prof"]
-    dom = max(KERNELS, key=lambda k: prof["kernel_ms"][k])
-    ms = prof["kernel_ms"][dom]
+    # a launch's time: its work-group activity plus half of the dead time to
+    # the next kernel (drain and write-back belong to it, the next dispatch
+    # does not); a kernel trace's duration lies between the two figures
+    ktime = {k: 0.5 * (prof["kernel_ms"][k] + prof["kernel_span_ms"][k]) for k in KERNELS}
+    dom = max(KERNELS, key=lambda k: ktime[k])
+    ms = ktime[dom]
     achieved = prof["alg_bytes"][dom] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    all_ms = sum(prof["kernel_ms"][k] for k in KERNELS)
+    all_ms = sum(ktime[k] for k in KERNELS)
     all_b = sum(prof["alg_bytes"][k] for k in KERNELS)
     out = {
         "metric": METRIC,
@@ -348,13 +393,16 @@ def main():
         },
         "breakdown": {"cg_iters": res["cg"], "bccg_iters": res["pf"], "seconds": res["dt"],
                       "realizations_cracked": res["ncrack"], "status": res["status"],
-                      "kernel_ms": prof["kernel_ms"], "kernel_launches": prof["launches"],
+                      "kernel_ms": ktime, "kernel_activity_ms": prof["kernel_ms"],
+                      "kernel_span_ms": prof["kernel_span_ms"], "kernel_launches": prof["launches"],
                       "kernel_alg_bytes": prof["alg_bytes"],
                       "alg_GBs_all_fft_kernels": all_b / (all_ms * 1e-3) / 1e9 if all_ms > 0 else None,
                       "steady_all_active": res["steady"]},
         "autotune": res["tuned"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "alg_bytes_per_launch": prof["alg_bytes"][dom] / max(prof["launches"][dom], 1),
+                     "avg_launch_us": ms * 1e3 / max(prof["launches"][dom], 1)},
     }
     if args.plain:
         pl = plain_leg(args)

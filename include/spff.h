@@ -211,19 +211,24 @@ spff_status spff_apply_operator(spff_problem* p, int32_t op, const void* in_dev,
 
 /* Kernel profiling.  A tick is four kernels: row-forward FFT, column FFT,
  * row-inverse FFT and the controller.  While enabled, every work-group of
- * the three FFT kernels brackets its work with the device wall clock, and
- * the controller of the same tick folds (last end - first start) of each
- * into a per-kernel total: kernel execution times, also inside captured
- * graphs, without host events (the controller itself is not timed: its
- * kernel_ms stays zero).  The controller also accumulates each kernel's
- * algorithmic HBM bytes for the phase every problem executed (inputs read
- * once, outputs written once, half spectra round-tripped).  Enabling resets
- * the totals. */
+ * the three FFT kernels stamps its first and last device wall-clock reading,
+ * and the controller of the same tick accumulates per FFT kernel
+ *   kernel_ms       its activity: first work-group start to last end;
+ *   kernel_span_ms  its span: first start to the first start of the next
+ *                   kernel of the tick (activity plus the dead time of its
+ *                   drain, end-of-kernel write-back and the next dispatch);
+ * a profiler's kernel trace, which also counts dispatch and write-back,
+ * falls between the two.  Works inside captured graphs, without host
+ * events; the controller itself is not timed (index 3 stays zero).  The
+ * controller also accumulates each kernel's algorithmic HBM bytes for the
+ * phase every problem executed (inputs read once, outputs written once, half
+ * spectra round-tripped).  Enabling resets the totals. */
 typedef struct spff_profile {
-  double kernel_ms[4];     /* summed execution time per kernel */
-  int64_t launches[4];     /* launches per kernel */
-  double alg_bytes[4];     /* summed algorithmic bytes per kernel */
+  double kernel_ms[4];       /* summed activity per kernel */
+  int64_t launches[4];       /* launches per kernel */
+  double alg_bytes[4];       /* summed algorithmic bytes per kernel */
   int64_t ticks;
+  double kernel_span_ms[4];  /* summed span per kernel */
 } spff_profile;
 spff_status spff_profile_enable(spff_problem* p, int32_t enable);
 spff_status spff_profile_read(spff_problem* p, spff_profile* out);

@@ -92,7 +92,9 @@ def _time_plan(prob, bidx, plan, state, eps):
     pr = prob.profile_read()
     prob.profile_enable(False)
     t = max(pr["ticks"], 1)
-    km = pr["kernel_ms"]
+    # activity plus half the dead time to the next kernel (write-back heavy
+    # plans pay for it there)
+    km = {k: 0.5 * (pr["kernel_ms"][k] + pr["kernel_span_ms"][k]) for k in pr["kernel_ms"]}
     return (km["rowfwd"] + km["rowinv"]) / t, km["col"] / t
 
 

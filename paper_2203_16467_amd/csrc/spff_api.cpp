@@ -274,7 +274,7 @@ Layout layout(const spff_config* c, int S, size_t rsize, bool scratch_only = fal
   L.prof = take(sizeof(double) * 3 * S);
   L.seq = take(sizeof(SlotSeq) * S);
   L.kt = take(sizeof(KTime) * 3);
-  L.ktsum = take(sizeof(unsigned long long) * 4);
+  L.ktsum = take(sizeof(unsigned long long) * 8);
   L.rec = take(sizeof(StepRec) * SEQ_MAX * S);
   L.slot0 = off;
   size_t so = 0;
@@ -1031,7 +1031,7 @@ spff_status spff_profile_enable(spff_problem* p, int32_t enable) {
     std::fill(std::begin(k.end), std::end(k.end), 0ull);
   }
   HIP_TRY(hipMemcpyAsync(p->d_kt(), init.data(), sizeof(KTime) * 3, hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(hipMemsetAsync(p->d_ktsum(), 0, sizeof(unsigned long long) * 4, p->stream));
+  HIP_TRY(hipMemsetAsync(p->d_ktsum(), 0, sizeof(unsigned long long) * 8, p->stream));
   HIP_TRY(hipMemsetAsync(p->d_prof(), 0, sizeof(double) * 3 * p->S, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   // the profiling buffers are compiled into the captured blocks: recapture lazily
@@ -1042,7 +1042,7 @@ spff_status spff_profile_enable(spff_problem* p, int32_t enable) {
 spff_status spff_profile_read(spff_problem* p, spff_profile* out) {
   if (!p || !out) return fail(SPFF_E_INVALID, "NULL argument");
   std::vector<double> b(3 * (size_t)p->S);
-  unsigned long long ks[4] = {0, 0, 0, 0};
+  unsigned long long ks[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(b.data(), p->d_prof(), sizeof(double) * b.size(), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipMemcpyAsync(ks, p->d_ktsum(), sizeof(ks), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -1051,6 +1051,7 @@ spff_status spff_profile_read(spff_problem* p, spff_profile* out) {
     for (int j = 0; j < 3; ++j) out->alg_bytes[j] += b[3 * s + j];
   for (int j = 0; j < 4; ++j) {
     out->kernel_ms[j] = p->clock_khz > 0.0 ? (double)ks[j] / p->clock_khz : 0.0;
+    out->kernel_span_ms[j] = p->clock_khz > 0.0 ? (double)ks[4 + j] / p->clock_khz : 0.0;
     out->launches[j] = p->launches[j];
   }
   out->ticks = p->prof_ticks;

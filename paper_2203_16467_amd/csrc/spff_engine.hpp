@@ -129,9 +129,11 @@ struct StepRec {
 // Device-side kernel timing (profiling) of one kernel: every work-group
 // lowers one of KT_LINES `start` words to its first clock reading and raises
 // one of KT_LINES `end` words to its last (hashed by work-group, one word per
-// 128-byte line, so that thousands of groups do not contend on one address);
-// the controller of the same tick folds max(end) - min(start) into a
-// per-kernel total and resets the words.
+// 128-byte line, so that thousands of groups do not contend on one address).
+// The controller of the same tick folds, per FFT kernel, its activity
+// (last end - first start) and its span (first start to the next kernel's
+// first start: activity plus the dead time of its drain, write-back and the
+// next dispatch), and resets the words.
 constexpr int KT_LINES = 64;
 constexpr int KT_STRIDE = 16;  // 64-bit words per line
 struct KTime {

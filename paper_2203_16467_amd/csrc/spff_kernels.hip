@@ -1499,7 +1499,7 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
 }
 
 // ===========================================================================
-// Kernel entry points: the bodies above, bracketed by the device clock when
+// Kernel entry points: the bodies above, stamped with the device clock when
 // profiling (kt != nullptr).
 // ===========================================================================
 __device__ __forceinline__ int kt_line() {
@@ -1599,9 +1599,14 @@ __global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const
                                              StepRec* __restrict__ recs, int nx, int ny, int ngr, int ngc,
                                              KTime* kt, unsigned long long* __restrict__ ktsum) {
   // fold this tick's kernel times (first work-group, before any early
-  // return): lane l takes line l of every kernel
+  // return): lane l takes line l of every kernel.  ktsum[j]: activity of
+  // kernel j (first start to last end); ktsum[4 + j]: its span (first start
+  // to the first start of kernel j + 1, this kernel's own start for the
+  // row-inverse kernel)
   if (kt && blockIdx.x == 0) {
     const int l = threadIdx.x;
+    const unsigned long long t_ctrl = wall_clock64();
+    unsigned long long st[3], en[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       unsigned long long a = kt[j].start[l * KT_STRIDE], b = kt[j].end[l * KT_STRIDE];
@@ -1613,7 +1618,16 @@ __global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const
         a = a2 < a ? a2 : a;
         b = b2 > b ? b2 : b;
       }
-      if (l == 0 && b > a) ktsum[j] += b - a;
+      st[j] = a;
+      en[j] = b;
+    }
+    if (l == 0) {
+      const unsigned long long nxt[3] = {st[1], st[2], t_ctrl};
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (en[j] > st[j]) ktsum[j] += en[j] - st[j];
+        if (nxt[j] > st[j] && st[j] != ~0ull) ktsum[4 + j] += nxt[j] - st[j];
+      }
     }
   }
   const int s = list[blockIdx.x];

@@ -74,14 +74,16 @@ class StepStats(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4),
-                ("alg_bytes", ctypes.c_double * 4), ("ticks", ctypes.c_int64)]
+                ("alg_bytes", ctypes.c_double * 4), ("ticks", ctypes.c_int64),
+                ("kernel_span_ms", ctypes.c_double * 4)]
 
     KERNELS = ("rowfwd", "col", "rowinv", "ctrl")
 
     def to_dict(self):
         return {"kernel_ms": dict(zip(self.KERNELS, self.kernel_ms)),
                 "launches": dict(zip(self.KERNELS, self.launches)),
-                "alg_bytes": dict(zip(self.KERNELS, self.alg_bytes)), "ticks": self.ticks}
+                "alg_bytes": dict(zip(self.KERNELS, self.alg_bytes)), "ticks": self.ticks,
+                "kernel_span_ms": dict(zip(self.KERNELS, self.kernel_span_ms))}
 
 
 FFT_LDS, FFT_REG, FFT_REG4 = 1, 2, 3
