@@ -144,7 +144,7 @@ def batched_leg(args):
     if args.warmup > 0:
         p.run_sequence(ramp[s0:args.start])
     log(f"[bench] warmup steps {s0}..{args.start - 1} done")
-    p.profile_enable(True)  # reset the kernel totals for the timed region
+    p.profile_enable(args.profile)  # reset the kernel totals for the timed region
     torch.cuda.synchronize()
     ROCTX.push("bench_timed")
     t0 = time.perf_counter()
@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--steady-start", type=int, default=40)
     ap.add_argument("--steady-steps", type=int, default=10)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--no-profile", dest="profile", action="store_false",
+                    help="time the window without the kernel timers (diagnostic: no roofline)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs one process on one MI355X "

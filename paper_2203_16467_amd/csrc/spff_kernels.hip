@@ -1592,19 +1592,21 @@ __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list
 // the XCDs from every group would need a device-scope release per group (an
 // L2 write-back each), which costs far more than the kernel boundary.
 template <typename real>
-__global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const SlotParam* __restrict__ prms,
+__global__ __launch_bounds__(128) void k_ctrl(const int* __restrict__ list, const SlotParam* __restrict__ prms,
                                              SlotCtl* __restrict__ ctls, const double* __restrict__ prow,
                                              const double* __restrict__ pcol, const double* __restrict__ pinv,
                                              double* __restrict__ prof, SlotSeq* __restrict__ seqs,
                                              StepRec* __restrict__ recs, int nx, int ny, int ngr, int ngc,
                                              KTime* kt, unsigned long long* __restrict__ ktsum) {
-  // fold this tick's kernel times (first work-group, before any early
-  // return): lane l takes line l of every kernel.  ktsum[j]: activity of
+  // Wavefront 0 of each work-group runs the controller of one slot; the
+  // second wavefront of the first work-group folds this tick's kernel times
+  // meanwhile (lane l takes line l of every kernel).  ktsum[j]: activity of
   // kernel j (first start to last end); ktsum[4 + j]: its span (first start
   // to the first start of kernel j + 1, this kernel's own start for the
   // row-inverse kernel)
-  if (kt && blockIdx.x == 0) {
-    const int l = threadIdx.x;
+  if (threadIdx.x >= 64) {
+    if (!kt || blockIdx.x != 0) return;
+    const int l = threadIdx.x - 64;
     const unsigned long long t_ctrl = wall_clock64();
     unsigned long long st[3], en[3];
 #pragma unroll
@@ -1629,6 +1631,7 @@ __global__ __launch_bounds__(64) void k_ctrl(const int* __restrict__ list, const
         if (nxt[j] > st[j] && st[j] != ~0ull) ktsum[4 + j] += nxt[j] - st[j];
       }
     }
+    return;
   }
   const int s = list[blockIdx.x];
   if (s < 0) return;
@@ -1773,7 +1776,7 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
     hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow,
                        pinv, G.nx, G.ny, G.R, G.ngr, kti);
   }
-  hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(64), 0, st, list, prms, ctls, prow, pcol, pinv, prof, seqs,
+  hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(128), 0, st, list, prms, ctls, prow, pcol, pinv, prof, seqs,
                      recs, G.nx, G.ny, G.ngr, G.ngc, kt, ktsum);
   return hipGetLastError();
 }
