@@ -17,11 +17,26 @@ Readings of the paper:
   * An optional residual stiffness k_res is added to h(phi) in the elastic
     energy and the stress, psi = (h + k_res) psi0+ + psi0-; the paper has
     k_res = 0, which is the default everywhere.
+  * Volumetric-deviatoric split (Sec. 2.1): K = lambda + 2 mu / 3 and the
+    deviator with the 1/3 trace are three-dimensional; in plane strain the
+    out-of-plane strain is zero, so the deviatoric energy sums the in-plane
+    components and the zz component -tr/3:  mu (eps:eps - tr^2 / 3).  This
+    makes psi0+ + psi0- the isotropic energy and sigma0+ + sigma0- the
+    isotropic stress, as Sec. 4.2.1 states for all models at phi = 0; the
+    printed psi0+ = 2 mu (a^2 + ab + 5 b^2/18) of Sec. 4.2.1 instead sums the
+    in-plane components only (giving b^2/3 in place of 5 b^2/18 here) and
+    would break that statement.  The stresses are the derivatives:
+    sigma0+ = K <tr>+ I + 2 mu (eps - tr/3 I), sigma0- = K <tr>- I (the
+    worked contact example of Sec. 4.2.1 gives K tr I for the negative part).
+  * Non-variational models (Sec. 2.1, 4.2.1) pair the crack driving force of
+    one split with the stress ("contact model") of another; the functions
+    here take one model each, the caller chooses which one feeds the stress
+    and which the driving force psi0+.
 """
 
 import numpy as np
 
-SPLITS = ("none", "spectral")
+SPLITS = ("none", "spectral", "voldev")
 
 I2 = np.eye(2)
 
@@ -88,6 +103,10 @@ def psi0(eps, lam, mu, split):
             out.append(0.5 * lam * ramp(tr, s) ** 2
                        + mu * np.sum(ramp(w, s) ** 2, axis=-1))
         return out[0], out[1]
+    if split == "voldev":
+        K = lam + 2.0 * mu / 3.0
+        dev2 = ddot(eps, eps) - tr ** 2 / 3.0
+        return 0.5 * K * ramp(tr, +1) ** 2 + mu * dev2, 0.5 * K * ramp(tr, -1) ** 2
     raise ValueError(split)
 
 
@@ -114,6 +133,12 @@ def sigma0(eps, lam, mu, split):
                 acc = acc + coef[..., None, None] * _outer(n, n)
             out.append(acc)
         return out[0], out[1]
+    if split == "voldev":
+        lam0, mu0 = lam[..., 0, 0], mu[..., 0, 0]
+        K = lam0 + 2.0 * mu0 / 3.0
+        plus = (K * ramp(tr, +1) - 2.0 * mu0 * tr / 3.0)[..., None, None] * I2 + 2.0 * mu * eps
+        minus = (K * ramp(tr, -1))[..., None, None] * I2
+        return plus, minus
     raise ValueError(split)
 
 
@@ -149,6 +174,14 @@ def dsigma0(eps, d, lam, mu, split, sign):
         if sign < 0:
             return np.zeros(np.broadcast_shapes(eps.shape, d.shape))
         return lam_[..., None, None] * trd[..., None, None] * I2 + 2.0 * mu_[..., None, None] * d
+    if split == "voldev":
+        # d sigma0+ = K H+(tr) tr(d) I + 2 mu (d - tr(d)/3 I),
+        # d sigma0- = K H-(tr) tr(d) I
+        K = lam_ + 2.0 * mu_ / 3.0
+        vol = (K * step(trace(eps), sign) * trd)[..., None, None] * I2
+        if sign < 0:
+            return vol + np.zeros(np.broadcast_shapes(eps.shape, d.shape))
+        return vol + 2.0 * mu_[..., None, None] * (d - (trd / 3.0)[..., None, None] * I2)
     w, v = eig(eps)
     n1, n2 = v[..., :, 0], v[..., :, 1]
     e1, e2 = w[..., 0], w[..., 1]

@@ -18,6 +18,11 @@ Readings of the paper:
     zero strain with phi_con(phi_init) (Algorithm 2, first two lines).
   * C = sigma_bar_ij / eps_bar_ij at the component with the largest
     |eps_bar_ij| (Sec. 3.2.1).
+  * Non-variational models (Sec. 2.1, 4.2.1): ``split`` is the crack driving
+    force model (psi0+ of the phase-field problem), ``contact`` the model of
+    the stress (mechanics problem); contact=None means the same model
+    (variational).  The elastic energy reported is the one of the contact
+    model, whose derivative the stress is.
 """
 
 import numpy as np
@@ -33,11 +38,12 @@ class Problem:
 
     Parameters mirror the library's problem configuration: Young's modulus
     field E (ny, nx), Poisson ratio nu, length scale ell (pixels), G_c, AT
-    model (1 or 2), split ('none' | 'spectral'), irreversibility
-    ('crack_set' | 'damage').
+    model (1 or 2), split ('none' | 'spectral' | 'voldev': the crack
+    driving force model), contact (the stress model; None: same as split),
+    irreversibility ('crack_set' | 'damage').
     """
 
-    def __init__(self, E, nu=0.2, ell=2.0, gc=1.0, at=1, split="spectral",
+    def __init__(self, E, nu=0.2, ell=2.0, gc=1.0, at=1, split="spectral", contact=None,
                  irreversibility="crack_set", threshold=0.9, k_res=0.0,
                  eta_over_dt=0.0, tol_mech=1e-8, tol_pf=1e-8, tol_am=None,
                  tol_abs_mech=0.0, tol_abs_pf=0.0, max_cg=10000,
@@ -46,6 +52,7 @@ class Problem:
         self.ny, self.nx = self.E.shape
         self.nu, self.ell, self.gc, self.at = float(nu), float(ell), float(gc), int(at)
         self.split, self.irr, self.threshold = split, irreversibility, float(threshold)
+        self.contact = split if contact is None else contact
         self.k_res, self.eta_dt = float(k_res), float(eta_over_dt)
         self.tol_mech, self.tol_pf = float(tol_mech), float(tol_pf)
         self.tol_abs_mech, self.tol_abs_pf = float(tol_abs_mech), float(tol_abs_pf)
@@ -70,7 +77,7 @@ class Problem:
         return self.eps_bar + self.eps_star
 
     def stress(self):
-        return cm.stress(self.strain(), self.phi, self.lam, self.mu, self.split, self.k_res)
+        return cm.stress(self.strain(), self.phi, self.lam, self.mu, self.contact, self.k_res)
 
     def psi_plus(self):
         return cm.psi0(self.strain(), self.lam, self.mu, self.split)[0]
@@ -83,7 +90,7 @@ class Problem:
     def elastic_energy(self, phi=None, eps_star=None):
         phi = self.phi if phi is None else phi
         eps = self.eps_bar + (self.eps_star if eps_star is None else eps_star)
-        return float(np.sum(cm.energy_density(eps, phi, self.lam, self.mu, self.split, self.k_res)))
+        return float(np.sum(cm.energy_density(eps, phi, self.lam, self.mu, self.contact, self.k_res)))
 
     def fracture_energy(self, phi=None):
         return pf.fracture_energy(self.phi if phi is None else phi, self.at, self.gc, self.ell)
@@ -91,7 +98,7 @@ class Problem:
     # -- sub-problems ----------------------------------------------------
     def solve_mechanics(self):
         self.eps_star, info = mech.solve(self.eps_star, self.eps_bar, self.phi, self.lam,
-                                         self.mu, self.split, self.k_res, self.tol_mech,
+                                         self.mu, self.contact, self.k_res, self.tol_mech,
                                          self.tol_abs_mech, self.max_newton, self.max_cg)
         return info
 

@@ -60,6 +60,37 @@ def test_worked_example_contact_mixed(b):
     np.testing.assert_allclose(cm.stress(eps, 1.0, lam, mu, "none"), 0.0, atol=1e-15)
 
 
+@pytest.mark.parametrize("b", [0.1, 1.0, 3.0])
+def test_worked_example_voldev_contact(b):
+    """Sec. 4.2.1, volumetric-deviatoric split at phi = 1: eps = diag(0, -b)
+    gives sigma = (lam + 2 mu/3) diag(-b, -b); eps = [[0, b], [b, 2b]]
+    (tension along y) gives sigma = 0."""
+    lam, mu = cm.lame(2.3, 0.3)
+    np.testing.assert_allclose(cm.stress(np.diag([0.0, -b]), 1.0, lam, mu, "voldev"),
+                               (lam + 2 * mu / 3) * np.diag([-b, -b]), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(cm.stress(np.array([[0.0, b], [b, 2 * b]]), 1.0, lam, mu, "voldev"), 0.0,
+                               atol=1e-14)
+
+
+@pytest.mark.parametrize("a,b,theta", [(0.3, 0.0, 0.0), (0.3, 0.2, 0.7), (1.0, 2.5, -1.1),
+                                       (0.01, 0.05, 2.0)])
+def test_worked_example_voldev_driving_force(a, b, theta):
+    """Sec. 4.2.1, principal strains (a, -a-b): the volumetric-deviatoric
+    driving force equals the isotropic one for pure shear (b = 0) and lies
+    between the isotropic and the strain-spectral ones,
+    iso >= vol.-dev. > spectral.  With the plane-strain deviator (out-of-plane
+    strain zero) its value is 2 mu (a^2 + ab + b^2/3)."""
+    lam, mu = cm.lame(1.7, 0.23)
+    eps = principal(a, -a - b, theta)
+    iso = cm.psi0(eps, lam, mu, "none")[0]
+    vd = cm.psi0(eps, lam, mu, "voldev")[0]
+    spec = cm.psi0(eps, lam, mu, "spectral")[0]
+    if b == 0.0:
+        assert vd == pytest.approx(iso, rel=1e-12)
+    assert iso >= vd - 1e-15 and vd > spec
+    assert vd == pytest.approx(2 * mu * (a * a + a * b + b * b / 3), rel=1e-12)
+
+
 def test_degradation_properties():
     """Sec. 2.1: h(0) = 1, h(1) = 0, h'(1) = 0."""
     assert cm.degradation(0.0) == 1.0 and cm.degradation(1.0) == 0.0
@@ -83,9 +114,15 @@ def test_split_sums_to_isotropic():
     pi, _ = cm.psi0(eps, lam, mu, "none")
     np.testing.assert_allclose(pp + pm, pi, atol=1e-13)
     assert np.all(pp >= 0) and np.all(pm >= 0)
+    # Sec. 4.2.1: at phi = 0 every model gives the isotropic response
+    sp_, sm = cm.sigma0(eps, lam, mu, "voldev")
+    np.testing.assert_allclose(sp_ + sm, si, atol=1e-13)
+    pp, pm = cm.psi0(eps, lam, mu, "voldev")
+    np.testing.assert_allclose(pp + pm, pi, atol=1e-13)
+    assert np.all(pp >= 0) and np.all(pm >= 0)
 
 
-@pytest.mark.parametrize("split", ["none", "spectral"])
+@pytest.mark.parametrize("split", ["none", "spectral", "voldev"])
 def test_homogeneity(split):
     """Sec. 3.2.3: psi0+ is degree-2 and the stress degree-1 homogeneous."""
     rng = np.random.default_rng(6)
@@ -99,7 +136,7 @@ def test_homogeneity(split):
                                    g * cm.stress(eps, phi, lam, mu, split), rtol=1e-11, atol=1e-14)
 
 
-@pytest.mark.parametrize("split", ["none", "spectral"])
+@pytest.mark.parametrize("split", ["none", "spectral", "voldev"])
 def test_stress_is_energy_gradient(split):
     """sigma = d psi / d eps (Sec. 2.1), by central differences."""
     rng = np.random.default_rng(7)
@@ -115,7 +152,7 @@ def test_stress_is_energy_gradient(split):
         np.testing.assert_allclose((fp - fm) / (2 * h), cm.ddot(sig, d), rtol=1e-6, atol=1e-8)
 
 
-@pytest.mark.parametrize("split", ["none", "spectral"])
+@pytest.mark.parametrize("split", ["none", "spectral", "voldev"])
 def test_tangent_is_stress_derivative(split):
     """C : d equals the central difference of sigma (Sec. 3.1.1), away from
     the kinks of the ramps."""

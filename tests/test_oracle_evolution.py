@@ -63,6 +63,50 @@ def test_at2_homogeneous_fixed_point(e):
     np.testing.assert_allclose(p.phi, 2 * psi / (2 * psi + 1.0 / 2.0), atol=1e-9)
 
 
+@pytest.mark.parametrize("split,contact", [("spectral", "none"), ("spectral", "voldev"), ("voldev", "voldev"),
+                                           ("none", "spectral")])
+@pytest.mark.parametrize("strain", [(0.0, 0.3, 0.0), (0.2, -0.25, 0.15)])
+def test_non_variational_homogeneous_step(split, contact, strain):
+    """Sec. 2.1 / 4.2.1: a model pairs the driving force of one energy with
+    the stress of another.  Homogeneous AT2 material: eps* stays 0, phi is
+    the fixed point 2 psi0+ / (2 psi0+ + G_c/l) of the driving-force model,
+    and the mean stress is h(phi) sigma0+ + sigma0- of the contact model."""
+    E = np.full((6, 6), 1.0)
+    p = oracle.Problem(E, nu=0.2, ell=2.0, gc=1.0, at=2, split=split, contact=contact)
+    st = p.load_step(strain)
+    lam, mu = cm.lame(1.0, 0.2)
+    eb = cm.sym_tensor(*strain)
+    psi = cm.psi0(eb, lam, mu, split)[0]
+    phi = 2 * psi / (2 * psi + 1.0 / 2.0)
+    np.testing.assert_allclose(p.phi, phi, atol=1e-9)
+    np.testing.assert_allclose(p.eps_star, 0.0, atol=1e-12)
+    sp_, sm = cm.sigma0(eb, lam, mu, contact)
+    want = cm.degradation(phi) * sp_ + sm
+    np.testing.assert_allclose(st["sigma_bar"], [want[0, 0], want[1, 1], want[0, 1]], rtol=1e-8, atol=1e-12)
+
+
+def test_stress_free_contact_keeps_crack_stress_free():
+    """Sec. 4.2.1: with the isotropic (stress-free) contact model a fully
+    damaged pixel carries no stress, also in compression, while the
+    strain-spectral contact model transmits it."""
+    n = 16
+    E = np.full((n, n), 1.0)
+    phi0 = np.zeros((n, n))
+    phi0[:, n // 2] = 1.0
+    for contact, zero in (("none", True), ("spectral", False)):
+        p = oracle.Problem(E, nu=0.2, ell=2.0, gc=1.0, at=1, split="spectral", contact=contact,
+                           irreversibility="damage")
+        p.set_state({"eps_star": np.zeros((n, n, 2, 2)), "phi": phi0, "phi_ref": phi0,
+                     "eps_bar": cm.sym_tensor(-0.01, 0.0, 0.0)})
+        p.eps_bar = cm.sym_tensor(-0.01, 0.0, 0.0)
+        p.solve_mechanics()
+        sxx = p.stress()[:, n // 2, 0, 0]
+        if zero:
+            np.testing.assert_allclose(sxx, 0.0, atol=1e-12)
+        else:
+            assert np.all(sxx < -1e-4)
+
+
 def _hetero(n=24, seed=3, amp=0.3):
     rng = np.random.default_rng(seed)
     z = rng.standard_normal((n, n))
@@ -73,7 +117,7 @@ def _hetero(n=24, seed=3, amp=0.3):
     return np.maximum(1 + amp * z, 0.5)
 
 
-@pytest.mark.parametrize("split", ["none", "spectral"])
+@pytest.mark.parametrize("split", ["none", "spectral", "voldev"])
 @pytest.mark.parametrize("at", [1, 2])
 def test_am_energy_non_increasing(split, at):
     """Each AM half-step minimises F in one variable with fixed bounds, so
