@@ -59,7 +59,15 @@ typedef enum {
 } spff_status;
 
 enum { SPFF_AT1 = 1, SPFF_AT2 = 2 };
-enum { SPFF_SPLIT_NONE = 0, SPFF_SPLIT_SPECTRAL = 1 };
+/* Energy models (Sec. 2.1): isotropic, strain-spectral split, volumetric-
+ * deviatoric split (plane strain: K = lambda + 2 mu/3, three-dimensional
+ * deviator with zero out-of-plane strain, so every model is isotropic at
+ * phi = 0).  `split` selects the crack driving force psi0+, `contact` the
+ * stress; equal (or contact = SPFF_CONTACT_SAME) gives the variational
+ * model, different values the non-variational pairings of Sec. 4.2.1 (e.g.
+ * strain-spectral driving force with the stress-free isotropic contact). */
+enum { SPFF_SPLIT_NONE = 0, SPFF_SPLIT_SPECTRAL = 1, SPFF_SPLIT_VOLDEV = 2 };
+enum { SPFF_CONTACT_SAME = -1 };
 enum { SPFF_IRR_CRACK_SET = 0, SPFF_IRR_DAMAGE = 1 };
 enum { SPFF_FP32 = 0, SPFF_FP64 = 1 };
 
@@ -79,7 +87,7 @@ enum {
 typedef struct spff_config {
   int32_t nx, ny;          /* grid, powers of two in [8, 4096] */
   int32_t at;              /* SPFF_AT1 (w = phi, c_w = 8/3) or SPFF_AT2 (w = phi^2, c_w = 2) */
-  int32_t split;           /* SPFF_SPLIT_NONE (isotropic) or SPFF_SPLIT_SPECTRAL */
+  int32_t split;           /* crack driving force model: SPFF_SPLIT_NONE (isotropic), _SPECTRAL, _VOLDEV */
   int32_t irreversibility; /* SPFF_IRR_CRACK_SET or SPFF_IRR_DAMAGE */
   int32_t precision;       /* SPFF_FP32 or SPFF_FP64 */
   double nu;               /* Poisson ratio, -1 < nu < 0.5 (plane strain) */
@@ -109,6 +117,7 @@ typedef struct spff_config {
    * columns per column-FFT work-group (powers of two), threads per
    * work-group (64, 128 or 256; threads * 8 >= max(nx/2, ny)). */
   int32_t plan_rows, plan_cols, plan_threads;
+  int32_t contact;         /* stress (contact) model: SPFF_SPLIT_* or SPFF_CONTACT_SAME (default: = split) */
 } spff_config;
 
 /* Per-problem result of one load step (Sec. 3.2.1 quantities). */

@@ -67,7 +67,11 @@ spff_status check_config(const spff_config* c) {
   if (!(c->ell > 0.0) || !std::isfinite(c->ell)) return fail(SPFF_E_INVALID, "ell must be > 0");
   if (!(c->gc > 0.0) || !std::isfinite(c->gc)) return fail(SPFF_E_INVALID, "gc must be > 0");
   if (c->at != SPFF_AT1 && c->at != SPFF_AT2) return fail(SPFF_E_INVALID, "at must be 1 or 2");
-  if (c->split != SPFF_SPLIT_NONE && c->split != SPFF_SPLIT_SPECTRAL) return fail(SPFF_E_INVALID, "bad split");
+  if (c->split != SPFF_SPLIT_NONE && c->split != SPFF_SPLIT_SPECTRAL && c->split != SPFF_SPLIT_VOLDEV)
+    return fail(SPFF_E_INVALID, "bad split");
+  if (c->contact != SPFF_CONTACT_SAME && c->contact != SPFF_SPLIT_NONE && c->contact != SPFF_SPLIT_SPECTRAL &&
+      c->contact != SPFF_SPLIT_VOLDEV)
+    return fail(SPFF_E_INVALID, "bad contact model");
   if (c->irreversibility != SPFF_IRR_CRACK_SET && c->irreversibility != SPFF_IRR_DAMAGE)
     return fail(SPFF_E_INVALID, "bad irreversibility");
   if (c->precision != SPFF_FP32 && c->precision != SPFF_FP64) return fail(SPFF_E_INVALID, "bad precision");
@@ -505,6 +509,7 @@ SlotParam make_param(const spff_config* c) {
   P.stall_iters = c->stall_iters;
   P.at = c->at;
   P.split = c->split;
+  P.contact = c->contact == SPFF_CONTACT_SAME ? c->split : c->contact;
   P.irr = c->irreversibility;
   P.max_cg = c->max_cg;
   P.max_newton = c->max_newton;
@@ -645,6 +650,7 @@ void spff_default_config(spff_config* c) {
   c->nx = c->ny = 64;
   c->at = SPFF_AT1;
   c->split = SPFF_SPLIT_SPECTRAL;
+  c->contact = SPFF_CONTACT_SAME;
   c->irreversibility = SPFF_IRR_CRACK_SET;
   c->precision = SPFF_FP32;
   c->nu = 0.2;

@@ -539,10 +539,42 @@ __device__ __forceinline__ void spectral_part(const Sym<real>& e, real lam, real
   }
 }
 
+// Volumetric-deviatoric split (plane strain, zero out-of-plane strain):
+//   psi0+ = K <tr>+^2 / 2 + mu (eps:eps - tr^2 / 3),  psi0- = K <tr>-^2 / 2,
+//   sigma0+ = (K <tr>+ - 2 mu tr / 3) I + 2 mu eps,   sigma0- = K <tr>- I,
+// K = lam + 2 mu / 3; the tangent differentiates the ramps with [tr > 0],
+// [tr < 0].
+template <typename real>
+__device__ __forceinline__ Sym<real> voldev_stress(const Sym<real>& e, real lam, real mu, real hk) {
+  const real K = lam + real(2) * mu / real(3);
+  const real tr = e.xx + e.yy;
+  const real tp = tr > real(0) ? tr : real(0), tm = tr < real(0) ? tr : real(0);
+  const real iso = hk * (K * tp - real(2) * mu * tr / real(3)) + K * tm;
+  Sym<real> o;
+  o.xx = iso + hk * real(2) * mu * e.xx;
+  o.yy = iso + hk * real(2) * mu * e.yy;
+  o.xy = hk * real(2) * mu * e.xy;
+  return o;
+}
+template <typename real>
+__device__ __forceinline__ Sym<real> voldev_tangent(const Sym<real>& e, const Sym<real>& p, real lam, real mu,
+                                                    real hk) {
+  const real K = lam + real(2) * mu / real(3);
+  const real tr = e.xx + e.yy, dtr = p.xx + p.yy;
+  const real vol = (tr > real(0) ? hk * K : real(0)) + (tr < real(0) ? K : real(0));
+  const real iso = vol * dtr - hk * real(2) * mu * dtr / real(3);
+  Sym<real> o;
+  o.xx = iso + hk * real(2) * mu * p.xx;
+  o.yy = iso + hk * real(2) * mu * p.yy;
+  o.xy = hk * real(2) * mu * p.xy;
+  return o;
+}
+
 // Full stress sigma = hk sigma0+ + sigma0-, hk = h(phi) + k_res.
 template <typename real>
 __device__ __forceinline__ Sym<real> stress(const Sym<real>& e, real lam, real mu, real hk, int split) {
   Sym<real> o;
+  if (split == 2) return voldev_stress(e, lam, mu, hk);
   if (split == 0) {
     const real tr = e.xx + e.yy;
     o.xx = hk * (lam * tr + real(2) * mu * e.xx);
@@ -564,6 +596,7 @@ template <typename real>
 __device__ __forceinline__ Sym<real> tangent(const Sym<real>& e, const Sym<real>& p, real lam, real mu, real hk,
                                              int split) {
   Sym<real> o;
+  if (split == 2) return voldev_tangent(e, p, lam, mu, hk);
   if (split == 0) {
     const real tr = p.xx + p.yy;
     o.xx = hk * (lam * tr + real(2) * mu * p.xx);
@@ -583,6 +616,14 @@ __device__ __forceinline__ Sym<real> tangent(const Sym<real>& e, const Sym<real>
 // psi0+ and psi0- (isotropic model: psi0+ = full energy, psi0- = 0).
 template <typename real>
 __device__ __forceinline__ void energies(const Sym<real>& e, real lam, real mu, int split, real* pp, real* pm) {
+  if (split == 2) {
+    const real K = lam + real(2) * mu / real(3);
+    const real tr = e.xx + e.yy;
+    const real tp = tr > real(0) ? tr : real(0), tm = tr < real(0) ? tr : real(0);
+    *pp = real(0.5) * K * tp * tp + mu * (e.xx * e.xx + e.yy * e.yy + real(2) * e.xy * e.xy - tr * tr / real(3));
+    *pm = real(0.5) * K * tm * tm;
+    return;
+  }
   if (split == 0) {
     const real tr = e.xx + e.yy;
     *pp = real(0.5) * lam * tr * tr + mu * (e.xx * e.xx + e.yy * e.yy + real(2) * e.xy * e.xy);

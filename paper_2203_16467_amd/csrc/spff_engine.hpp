@@ -65,7 +65,8 @@ struct SlotParam {
   // computed from); floor_coef = floor_factor * u * sqrt(log2(nx ny))
   double floor_coef;
   double lap_rms;          // mean |2 pi q|^2 over the grid's modes (2 pi^2 / 3)
-  int32_t at, split, irr, stall_iters;
+  int32_t at, split, irr, stall_iters;  // split: driving-force model
+  int32_t contact, pad_c;                 // stress model
   int32_t max_cg, max_newton, max_bccg, max_am;
 };
 

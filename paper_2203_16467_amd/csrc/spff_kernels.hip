@@ -114,7 +114,7 @@ __device__ __forceinline__ real lower_bound(real pref, const SlotParam& P) {
 // Per-slot scalars of a tick shared by the row prologue and epilogue.
 template <typename real>
 struct RowCtx {
-  int phase, flags, split, n, ncomp;
+  int phase, flags, split, contact, n, ncomp;  // split: driving-force model, contact: stress model
   real lt, mt, kres, eb0, eb1, eb2, beta_m, beta_pf, alpha_pf;
 };
 
@@ -124,6 +124,7 @@ __device__ __forceinline__ RowCtx<real> row_ctx(const SlotCtl& ctl, const SlotPa
   X.phase = phase;
   X.flags = ctl.flags;
   X.split = P.split;
+  X.contact = P.contact;
   X.n = n;
   X.ncomp = ncomp;
   X.lt = real(P.lam_t);
@@ -149,7 +150,7 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
                                              real (&val)[3][2], double (&acc)[NP_ROW]) {
   // PH >= 0: the phase is known at compile time (the other cases fold away)
   const int phase = PH >= 0 ? PH : X.phase;
-  const int flags = X.flags, split = X.split, n = X.n, ncomp = X.ncomp;
+  const int flags = X.flags, split = X.split, contact = X.contact, n = X.n, ncomp = X.ncomp;
   const real lt = X.lt, mt = X.mt, kres = X.kres, eb0 = X.eb0, eb1 = X.eb1, eb2 = X.eb2;
 #pragma unroll
   for (int q = 0; q < 2; ++q) val[0][q] = val[1][q] = val[2][q] = real(0);
@@ -174,9 +175,9 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
         const real lam = lt * Ev[q], mu = mt * Ev[q];
         const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
         const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
-        const Sym<real> sg = stress(e, lam, mu, hk, split);
+        const Sym<real> sg = stress(e, lam, mu, hk, contact);
         const Sym<real> eh = {eb0, eb1, eb2};
-        const Sym<real> sh = stress(eh, lam, mu, hk, split);
+        const Sym<real> sh = stress(eh, lam, mu, hk, contact);
         acc[0] += double(ddot(sh, sh));
         acc[1] += double(ddot(sg, sg));
         val[0][q] = sg.xx;
@@ -199,7 +200,7 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       st2(pmp + n + o, py.a, py.b);
       st2(pmp + 2 * n + o, pxy.a, pxy.b);
       V2<real> ex = {0, 0}, ey = {0, 0}, exy = {0, 0};
-      if (split != 0) {
+      if (contact != 0) {
         ex = ld2(epsp + o);
         ey = ld2(epsp + n + o);
         exy = ld2(epsp + 2 * n + o);
@@ -213,7 +214,7 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
         const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
         const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
         const Sym<real> p = {pxv[q], pyv[q], psv[q]};
-        const Sym<real> cp = tangent(e, p, lam, mu, hk, split);
+        const Sym<real> cp = tangent(e, p, lam, mu, hk, contact);
         acc[0] += double(ddot(p, cp));
         val[0][q] = cp.xx;
         val[1][q] = cp.yy;
@@ -292,8 +293,8 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
         const real hk = (real(1) - pv[q]) * (real(1) - pv[q]) + kres;
         const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
         real pp, pm;
-        energies(e, lam, mu, split, &pp, &pm);
-        const Sym<real> sg = stress(e, lam, mu, hk, split);
+        energies(e, lam, mu, contact, &pp, &pm);  // elastic energy of the stress model
+        const Sym<real> sg = stress(e, lam, mu, hk, contact);
         acc[0] += double(hk) * double(pp) + double(pm);
         acc[1] += P.at == 1 ? double(pv[q]) : double(pv[q]) * double(pv[q]);
         acc[2] += double(pv[q]);
@@ -1220,7 +1221,7 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
   const SlotParam& P = prms[s];
   if (prof && threadIdx.x == 0) {
     double b[3];
-    phase_bytes(phase, C.flags, P.split, double(sizeof(real)), b);
+    phase_bytes(phase, C.flags, P.contact, double(sizeof(real)), b);
     const double npx = double(nx) * double(ny);
     prof[3 * s + 0] += b[0] * npx;
     prof[3 * s + 1] += b[1] * npx;
@@ -1274,7 +1275,7 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
         nphase = PH_PF_ASM;
       } else {
         rr = r2;
-        inner_tol = (P.split == 0) ? fmax(mech_target, mech_floor)
+        inner_tol = (P.contact == 0) ? fmax(mech_target, mech_floor)
                                    : fmax(0.1 * mech_res, fmax(mech_target, mech_floor));
         cg_newton = 0;
         flags |= FL_CG_FIRST;
@@ -1674,7 +1675,7 @@ __global__ void k_fields(const SlotPtr<real>* __restrict__ ptrs, const SlotParam
       strain[2 * n + i] = e.xy;
     }
     if (stress_out) {
-      const Sym<real> sg = stress(e, lam, mu, hk, P.split);
+      const Sym<real> sg = stress(e, lam, mu, hk, P.contact);
       stress_out[i] = sg.xx;
       stress_out[n + i] = sg.yy;
       stress_out[2 * n + i] = sg.xy;

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libspff.so")
 
 OK, WARN_NOT_CONVERGED, E_INVALID, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY = 0, 1, -1, -2, -3, -4, -5
 AT1, AT2 = 1, 2
-SPLIT_NONE, SPLIT_SPECTRAL = 0, 1
+SPLIT_NONE, SPLIT_SPECTRAL, SPLIT_VOLDEV = 0, 1, 2
+CONTACT_SAME = -1
 IRR_CRACK_SET, IRR_DAMAGE = 0, 1
 FP32, FP64 = 0, 1
 OP_PROJECT, OP_NEG_LAPLACIAN = 0, 1
@@ -53,6 +54,7 @@ class Config(ctypes.Structure):
         ("max_am", ctypes.c_int32), ("ticks_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32),
         ("floor_factor", ctypes.c_double), ("stall_iters", ctypes.c_int32),
         ("plan_rows", ctypes.c_int32), ("plan_cols", ctypes.c_int32), ("plan_threads", ctypes.c_int32),
+        ("contact", ctypes.c_int32),
     ]
 
 

@@ -9,7 +9,7 @@ import oracle
 from oracle import constitutive as ocm
 from paper_2203_16467_amd import spff
 
-SPLITS = {"none": spff.SPLIT_NONE, "spectral": spff.SPLIT_SPECTRAL}
+SPLITS = {"none": spff.SPLIT_NONE, "spectral": spff.SPLIT_SPECTRAL, "voldev": spff.SPLIT_VOLDEV}
 IRRS = {"crack_set": spff.IRR_CRACK_SET, "damage": spff.IRR_DAMAGE}
 
 
@@ -19,12 +19,13 @@ def device():
 
 
 def cfg_for(nx, ny=None, precision="fp32", at=1, split="spectral", irr="crack_set", ell=2.0, gc=1.0, nu=0.2,
-            tol=None, **kw):
+            tol=None, contact=None, **kw):
     ny = nx if ny is None else ny
     tol = (1e-10 if precision == "fp64" else 1e-6) if tol is None else tol
     cfg = spff.default_config(nx=nx, ny=ny, at=at, split=SPLITS[split], irreversibility=IRRS[irr], ell=ell, gc=gc,
                               nu=nu, precision=spff.FP64 if precision == "fp64" else spff.FP32, tol_mech=tol,
-                              tol_pf=tol)
+                              tol_pf=tol,
+                              contact=spff.CONTACT_SAME if contact is None else SPLITS[contact])
     # caps keep a runaway case short; the cases here converge well inside them
     cfg.max_cg = kw.pop("max_cg", 4000)
     cfg.max_bccg = kw.pop("max_bccg", 4000)
@@ -35,9 +36,11 @@ def cfg_for(nx, ny=None, precision="fp32", at=1, split="spectral", irr="crack_se
 
 
 def oracle_for(E, cfg, tol=1e-10, **kw):
-    split = "none" if cfg.split == spff.SPLIT_NONE else "spectral"
+    names = {v: k for k, v in SPLITS.items()}
+    split = names[cfg.split]
+    contact = None if cfg.contact == spff.CONTACT_SAME else names[cfg.contact]
     irr = "crack_set" if cfg.irreversibility == spff.IRR_CRACK_SET else "damage"
-    args = dict(nu=cfg.nu, ell=cfg.ell, gc=cfg.gc, at=cfg.at, split=split, irreversibility=irr,
+    args = dict(nu=cfg.nu, ell=cfg.ell, gc=cfg.gc, at=cfg.at, split=split, contact=contact, irreversibility=irr,
                 threshold=cfg.crack_set_threshold, k_res=cfg.k_res, tol_mech=tol, tol_pf=tol,
                 max_am=cfg.max_am)
     args.update(kw)

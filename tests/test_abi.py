@@ -54,7 +54,8 @@ def test_workspace_bytes_scales_with_batch():
 
 
 @pytest.mark.parametrize("field,value", [("nx", 100), ("ny", 4), ("nx", 4096), ("nu", 0.5), ("nu", -1.0),
-                                         ("ell", 0.0), ("gc", -1.0), ("at", 3), ("split", 2),
+                                         ("ell", 0.0), ("gc", -1.0), ("at", 3), ("split", 3), ("split", -1),
+                                         ("contact", 3), ("contact", -2),
                                          ("irreversibility", 5), ("precision", 2), ("max_cg", 0),
                                          ("ticks_per_sync", 0), ("tol_pf", -1.0), ("k_res", -0.1)])
 def test_invalid_config_rejected(field, value):
@@ -64,6 +65,14 @@ def test_invalid_config_rejected(field, value):
     st = spff.lib().spff_workspace_bytes(ctypes.byref(cfg), 1, ctypes.byref(out))
     assert st == spff.E_INVALID
     assert spff.last_error()
+
+
+@pytest.mark.parametrize("split,contact", [(0, -1), (1, -1), (2, -1), (1, 0), (1, 2), (0, 1), (2, 2)])
+def test_model_matrix_accepted(split, contact):
+    """Every driving-force / contact pairing of the three energy models is a
+    valid configuration (variational when equal or SPFF_CONTACT_SAME)."""
+    cfg = spff.default_config(split=split, contact=contact)
+    assert spff.workspace_bytes(cfg, 1) > 0
 
 
 def test_create_rejects_null_arguments_without_device():

@@ -185,6 +185,64 @@ def test_initial_crack_solve(precision):
     p.close()
 
 
+MODELS = [("voldev", None), ("spectral", "none"), ("spectral", "voldev"), ("none", "spectral")]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("split,contact", MODELS)
+def test_model_matrix_step_parity(precision, split, contact):
+    """Sec. 2.1 / 4.2.1 energy models beyond the variational spectral one:
+    the volumetric-deviatoric split and non-variational pairings of a
+    crack driving force with another model's stress.  Step-wise parity on
+    the CPU-sized input: an elastic step (mechanics only), then AT1 through
+    the first nucleating step (alternating minimisation capped at 3) from
+    the same state on both sides."""
+    E, ramp = _c1_inputs()
+    cfg = cfg_for(64, precision=precision, split=split, contact=contact, max_am=3)
+    p = spff.Problem(torch_E(E, precision), cfg)
+    o = oracle_for(E, cfg, max_am=3)
+    st, stats = p.load_step(ramp[5])
+    ost = o.load_step(ramp[5])
+    compare(gpu_fields(p), oracle_fields(o), precision)
+    assert stats[0]["F_e"] == pytest.approx(ost["F_e"], rel=tol_fields(precision))
+    k = None
+    for s in range(6, 20):
+        _, stt = p.load_step(ramp[s])
+        if stt[0]["phi_max"] > 0.0:
+            k = s
+            break
+    assert k is not None
+    # redo step k from the state before it on both sides
+    q = spff.Problem(torch_E(E, precision), cfg)
+    q.run_sequence(ramp[:k])
+    set_oracle_from_gpu(o, q)
+    _, stats = q.load_step(ramp[k])
+    ost = o.load_step(ramp[k])
+    cmp = compare(gpu_fields(q), oracle_fields(o), precision, phi_tol=1e-6 if precision == "fp64" else 1e-3)
+    print(split, contact, k, cmp, stats[0]["am_iters"], ost["am"])
+    assert stats[0]["am_iters"] == ost["am"]
+    tot = ost["F_e"] + ost["F_f"]
+    assert abs(stats[0]["F_e"] - ost["F_e"]) <= 10 * tol_fields(precision) * tot
+    assert abs(stats[0]["F_f"] - ost["F_f"]) <= 10 * tol_fields(precision) * tot
+    p.close()
+    q.close()
+
+
+@pytest.mark.parametrize("split,contact", MODELS)
+def test_model_matrix_at2_step(split, contact):
+    """AT2 (phi evolves from the first load) with each model, FP32."""
+    E, ramp = _c1_inputs()
+    cfg = cfg_for(64, split=split, contact=contact, at=2)
+    p = spff.Problem(torch_E(E, "fp32"), cfg)
+    o = oracle_for(E, cfg)
+    p.load_step(ramp[6])
+    set_oracle_from_gpu(o, p)
+    _, stats = p.load_step(ramp[10])
+    o.load_step(ramp[10])
+    compare(gpu_fields(p), oracle_fields(o), "fp32")
+    p.close()
+
+
 def test_batch_equals_single_bitwise():
     """Problems in a batch do not interact: each result is bitwise the one
     of the same problem run alone."""
