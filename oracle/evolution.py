@@ -18,6 +18,9 @@ Readings of the paper:
     zero strain with phi_con(phi_init) (Algorithm 2, first two lines).
   * C = sigma_bar_ij / eps_bar_ij at the component with the largest
     |eps_bar_ij| (Sec. 3.2.1).
+  * ``time_step`` is one iteration of the time-discretized evolution
+    (Algorithm 3, Sec. 3.2.2); the caller increments eps_bar when the
+    returned ``advance`` is set.
   * Non-variational models (Sec. 2.1, 4.2.1): ``split`` is the crack driving
     force model (psi0+ of the phase-field problem), ``contact`` the model of
     the stress (mechanics problem); contact=None means the same model
@@ -144,6 +147,50 @@ class Problem:
         self.step_count += 1
         return self.stats(am=am, newton=newton, cg=cg, bccg=bccg, dphi=dphi,
                           converged=converged)
+
+    # -- Algorithm 3, one iteration n of the time-discretized evolution ----
+    def time_step(self, eps_bar, eta, dt_max, dt_min, dphi_max, dphi_min):
+        """One outer iteration of Algorithm 3 (Sec. 3.2.2) at macroscopic
+        strain ``eps_bar``: the elasticity sub-problem at phi_n, then the
+        phase-field sub-problem with the viscous term eta/dt and phi_con(phi_n)
+        (phi_old = phi_n), halving dt until ||phi_n+1 - phi_n||_1 < dphi_max
+        or dt <= dt_min; dt doubles (up to dt_max) when the accepted change is
+        below dphi_max / 2.  dt persists between calls (initially dt_max).
+        Returns the stats dict with dt (the next step's), the halvings and
+        ``advance``: the condition under which Algorithm 3 increments the
+        macroscopic strain (dphi < dphi_min and dt >= dt_max).
+
+        Readings: the doubling is capped at dt_max (the text bounds dt by
+        (dt)_max); each retry restarts the phase-field solve from phi_n."""
+        eps_bar = np.asarray(eps_bar, dtype=np.float64)
+        if eps_bar.shape == (3,):
+            eps_bar = cm.sym_tensor(*eps_bar)
+        if not hasattr(self, "dt"):
+            self.dt = float(dt_max)
+        self.eps_bar = eps_bar
+        phi_n = self.phi.copy()
+        self.phi_ref = phi_n
+        lo = pf.constraint_field(phi_n, self.irr, self.threshold)
+        mi = self.solve_mechanics()
+        halvings = bccg = 0
+        converged = bool(mi["converged"])
+        while True:
+            op = pf.Operator(self.psi_plus(), self.at, self.gc, self.ell, eta / self.dt, phi_n)
+            phi_new, pi = pf.bccg(phi_n, lo, np.ones_like(lo), op, self.tol_pf, self.tol_abs_pf, self.max_bccg)
+            bccg += pi["iterations"]
+            dphi = float(np.sum(np.abs(phi_new - phi_n)))
+            if dphi < dphi_max or self.dt <= dt_min:
+                if dphi < 0.5 * dphi_max:
+                    self.dt = min(2.0 * self.dt, float(dt_max))
+                break
+            self.dt *= 0.5
+            halvings += 1
+        converged &= pi["stopped"] == "converged"
+        self.phi = phi_new
+        self.step_count += 1
+        advance = dphi < dphi_min and self.dt >= dt_max
+        return self.stats(am=1, newton=mi["newton"], cg=mi["cg"], bccg=bccg, dphi=dphi, converged=converged,
+                          dt=self.dt, halvings=halvings, advance=bool(advance))
 
     def stats(self, **extra):
         sig = self.stress()

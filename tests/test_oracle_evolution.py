@@ -107,6 +107,71 @@ def test_stress_free_contact_keeps_crack_stress_free():
             assert np.all(sxx < -1e-4)
 
 
+def _td_closed_form_phi(psi, eta, dt, gc, ell, phi_n):
+    """Homogeneous AT2 phase-field sub-problem with the viscous term
+    (Sec. 3.2.2): (2 psi + G_c/l + eta/dt) phi = 2 psi + (eta/dt) phi_n."""
+    return (2 * psi + eta / dt * phi_n) / (2 * psi + gc / ell + eta / dt)
+
+
+@pytest.mark.parametrize("eta,e", [(0.5, 0.3), (4.0, 0.5)])
+def test_time_step_homogeneous_closed_form(eta, e):
+    """Algorithm 3 on a homogeneous AT2 material: each accepted phase field
+    is the viscous closed form at the accepted dt; dt stays at dt_max when
+    the change is small and doubles back after a halving."""
+    n = 6
+    p = oracle.Problem(np.full((n, n), 1.0), nu=0.2, ell=2.0, gc=1.0, at=2, split="spectral")
+    lam, mu = cm.lame(1.0, 0.2)
+    psi = 0.5 * (lam + 2 * mu) * e * e
+    st = p.time_step((0.0, e, 0.0), eta, dt_max=1.0, dt_min=1e-3, dphi_max=1e9, dphi_min=0.0)
+    np.testing.assert_allclose(p.phi, _td_closed_form_phi(psi, eta, 1.0, 1.0, 2.0, 0.0), atol=1e-9)
+    assert st["dt"] == 1.0 and st["halvings"] == 0
+    phi1 = p.phi.copy()
+    p.time_step((0.0, e, 0.0), eta, dt_max=1.0, dt_min=1e-3, dphi_max=1e9, dphi_min=0.0)
+    np.testing.assert_allclose(p.phi, _td_closed_form_phi(psi, eta, 1.0, 1.0, 2.0, phi1), atol=1e-9)
+
+
+def test_time_step_halving_and_advance():
+    """Algorithm 3's inner loop: dt is halved until the change of phi is
+    below dphi_max; the number of halvings follows from the closed-form
+    change N^2 |phi(dt) - phi_n| of a homogeneous AT2 material."""
+    n, eta, e = 6, 2.0, 0.5
+    lam, mu = cm.lame(1.0, 0.2)
+    psi = 0.5 * (lam + 2 * mu) * e * e
+    dphi = lambda dt: n * n * _td_closed_form_phi(psi, eta, dt, 1.0, 2.0, 0.0)  # noqa: E731
+    dphi_max = 0.5 * dphi(1.0 / 8)  # accepted at dt = 1/32 at the latest
+    k, dt = 0, 1.0
+    while not dphi(dt) < dphi_max:
+        dt, k = dt / 2, k + 1
+    p = oracle.Problem(np.full((n, n), 1.0), nu=0.2, ell=2.0, gc=1.0, at=2, split="spectral")
+    st = p.time_step((0.0, e, 0.0), eta, dt_max=1.0, dt_min=1e-4, dphi_max=dphi_max, dphi_min=0.0)
+    assert st["halvings"] == k and k >= 3
+    np.testing.assert_allclose(p.phi, _td_closed_form_phi(psi, eta, dt, 1.0, 2.0, 0.0), atol=1e-9)
+    want_next = min(2 * dt, 1.0) if dphi(dt) < 0.5 * dphi_max else dt
+    assert st["dt"] == pytest.approx(want_next)
+    assert st["advance"] is False
+    # dt_min stops the halving
+    q = oracle.Problem(np.full((n, n), 1.0), nu=0.2, ell=2.0, gc=1.0, at=2, split="spectral")
+    st = q.time_step((0.0, e, 0.0), eta, dt_max=1.0, dt_min=0.25, dphi_max=dphi_max, dphi_min=0.0)
+    assert st["halvings"] == 2 and st["dphi"] >= dphi_max
+    # a converged state with dt at dt_max advances the load
+    r = oracle.Problem(np.full((n, n), 1.0), nu=0.2, ell=2.0, gc=1.0, at=1, split="spectral")
+    st = r.time_step((0.0, 0.1, 0.0), eta, dt_max=1.0, dt_min=1e-3, dphi_max=1.0, dphi_min=1e-6)
+    assert st["advance"] is True and st["dphi"] == 0.0
+
+
+def test_time_step_without_viscosity_is_one_am_iteration():
+    """With eta -> 0 the phase-field sub-problem of Algorithm 3 is the one of
+    alternating minimisation: a time step equals one AM iteration."""
+    E = _hetero(16, seed=4)
+    a = oracle.Problem(E, at=1, split="spectral", max_am=1)
+    b = oracle.Problem(E, at=1, split="spectral")
+    for eb in ((0.0, 0.3, 0.0), (0.0, 0.36, 0.0)):
+        a.load_step(eb)
+        b.time_step(eb, 0.0, dt_max=1.0, dt_min=1e-3, dphi_max=1e9, dphi_min=0.0)
+        np.testing.assert_allclose(b.phi, a.phi, atol=1e-10)
+        np.testing.assert_allclose(b.eps_star, a.eps_star, atol=1e-12)
+
+
 def _hetero(n=24, seed=3, amp=0.3):
     rng = np.random.default_rng(seed)
     z = rng.standard_normal((n, n))
