@@ -68,6 +68,10 @@ enum { SPFF_AT1 = 1, SPFF_AT2 = 2 };
  * strain-spectral driving force with the stress-free isotropic contact). */
 enum { SPFF_SPLIT_NONE = 0, SPFF_SPLIT_SPECTRAL = 1, SPFF_SPLIT_VOLDEV = 2 };
 enum { SPFF_CONTACT_SAME = -1 };
+/* Evolution method of a load step (Sec. 3.2): alternating minimisation
+ * (Algorithm 2) or one iteration of the time-discretized evolution
+ * (Algorithm 3). */
+enum { SPFF_EVOL_AM = 0, SPFF_EVOL_TIME = 1 };
 enum { SPFF_IRR_CRACK_SET = 0, SPFF_IRR_DAMAGE = 1 };
 enum { SPFF_FP32 = 0, SPFF_FP64 = 1 };
 
@@ -118,6 +122,19 @@ typedef struct spff_config {
    * work-group (64, 128 or 256; threads * 8 >= max(nx/2, ny)). */
   int32_t plan_rows, plan_cols, plan_threads;
   int32_t contact;         /* stress (contact) model: SPFF_SPLIT_* or SPFF_CONTACT_SAME (default: = split) */
+  /* Evolution (Sec. 3.2).  SPFF_EVOL_AM: a load step is Algorithm 2 at
+   * eta_over_dt.  SPFF_EVOL_TIME: a load step is one iteration n of
+   * Algorithm 3 at the given eps_bar: elasticity at phi_n, then the phase
+   * field with the viscous term eta/dt and phi_con(phi_n), dt halved until
+   * ||phi_n+1 - phi_n||_1 < dphi_max or dt <= dt_min and doubled (up to
+   * dt_max) after a change below dphi_max/2; dt persists between steps
+   * (initially dt_max).  The step's stats report dt and whether Algorithm 3
+   * increments the load (dphi < dphi_min and dt >= dt_max); the caller adds
+   * the strain increment then. */
+  int32_t evolution;       /* SPFF_EVOL_AM or SPFF_EVOL_TIME */
+  double eta;              /* viscosity eta >= 0 (SPFF_EVOL_TIME) */
+  double dt_max, dt_min;   /* 0 < dt_min <= dt_max */
+  double dphi_max, dphi_min; /* bounds on ||phi_n+1 - phi_n||_1 (pixel units) */
 } spff_config;
 
 /* Per-problem result of one load step (Sec. 3.2.1 quantities). */
@@ -137,6 +154,9 @@ typedef struct spff_step_stats {
   double phi_max, phi_mean;
   int64_t crack_px;        /* pixels with phi > 0.9 */
   double wall_ms;          /* host wall time from enqueueing the step to observing its end */
+  double dt;               /* SPFF_EVOL_TIME: dt for the next step */
+  int32_t halvings;        /* SPFF_EVOL_TIME: dt halvings in this step */
+  int32_t advance;         /* SPFF_EVOL_TIME: 1 if Algorithm 3 increments the load now */
 } spff_step_stats;
 
 typedef struct spff_problem spff_problem; /* opaque: a batch of 1..B problems */

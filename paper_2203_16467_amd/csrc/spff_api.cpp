@@ -72,6 +72,12 @@ spff_status check_config(const spff_config* c) {
   if (c->contact != SPFF_CONTACT_SAME && c->contact != SPFF_SPLIT_NONE && c->contact != SPFF_SPLIT_SPECTRAL &&
       c->contact != SPFF_SPLIT_VOLDEV)
     return fail(SPFF_E_INVALID, "bad contact model");
+  if (c->evolution != SPFF_EVOL_AM && c->evolution != SPFF_EVOL_TIME) return fail(SPFF_E_INVALID, "bad evolution");
+  if (c->evolution == SPFF_EVOL_TIME &&
+      (!(c->eta >= 0.0) || !(c->dt_min > 0.0) || !(c->dt_max >= c->dt_min) || !std::isfinite(c->dt_max) ||
+       !(c->dphi_max > 0.0) || !(c->dphi_min >= 0.0)))
+    return fail(SPFF_E_INVALID, "time-discretized evolution needs eta >= 0, 0 < dt_min <= dt_max, dphi_max > 0, "
+                                "dphi_min >= 0");
   if (c->irreversibility != SPFF_IRR_CRACK_SET && c->irreversibility != SPFF_IRR_DAMAGE)
     return fail(SPFF_E_INVALID, "bad irreversibility");
   if (c->precision != SPFF_FP32 && c->precision != SPFF_FP64) return fail(SPFF_E_INVALID, "bad precision");
@@ -510,6 +516,12 @@ SlotParam make_param(const spff_config* c) {
   P.at = c->at;
   P.split = c->split;
   P.contact = c->contact == SPFF_CONTACT_SAME ? c->split : c->contact;
+  P.evolution = c->evolution;
+  P.eta = c->eta;
+  P.dt_max = c->dt_max;
+  P.dt_min = c->dt_min;
+  P.dphi_max = c->dphi_max;
+  P.dphi_min = c->dphi_min;
   P.irr = c->irreversibility;
   P.max_cg = c->max_cg;
   P.max_newton = c->max_newton;
@@ -616,6 +628,9 @@ void fill_stats(const spff_problem* p, const SlotCtl& c, spff_step_stats& o, dou
   o.pf_residual = c.pf_res;
   o.F_e = c.F_e;
   o.F_f = c.F_f;
+  o.dt = c.dt;
+  o.halvings = c.halvings;
+  o.advance = c.advance;
   for (int k = 0; k < 3; ++k) o.sigma_bar[k] = c.sbar[k];
   int kmax = 0;
   for (int k = 1; k < 3; ++k)
@@ -628,11 +643,15 @@ void fill_stats(const spff_problem* p, const SlotCtl& c, spff_step_stats& o, dou
 }
 
 void start_step(spff_problem* p, int s, const double* eb) {
+  // the time step of the time-discretized evolution carries over
+  const double dt = p->host_ctl[s].dt > 0.0 ? p->host_ctl[s].dt : p->cfg.dt_max;
   reset_ctl(p, s);
   SlotCtl& c = p->host_ctl[s];
   for (int k = 0; k < 3; ++k) c.eps_bar[k] = eb[k];
   c.phase = PH_M_RES;
   c.flags = FL_FIRST_OF_STEP;
+  c.dt = dt;
+  c.eta_dt = p->cfg.evolution == SPFF_EVOL_TIME ? p->cfg.eta / dt : p->cfg.eta_over_dt;
 }
 
 double now_ms() {
@@ -651,6 +670,12 @@ void spff_default_config(spff_config* c) {
   c->at = SPFF_AT1;
   c->split = SPFF_SPLIT_SPECTRAL;
   c->contact = SPFF_CONTACT_SAME;
+  c->evolution = SPFF_EVOL_AM;
+  c->eta = 0.0;
+  c->dt_max = 1.0;
+  c->dt_min = 1e-3;
+  c->dphi_max = 1.0;
+  c->dphi_min = 0.0;
   c->irreversibility = SPFF_IRR_CRACK_SET;
   c->precision = SPFF_FP32;
   c->nu = 0.2;
@@ -849,6 +874,9 @@ spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps
         c.bccg = r.bccg;
         c.ticks = r.ticks;
         c.status = r.status;
+        c.dt = r.dt;
+        c.halvings = r.halvings;
+        c.advance = r.advance;
         c.flags = r.flags;
         c.dphi = r.dphi;
         c.mech_res = r.mech_res;

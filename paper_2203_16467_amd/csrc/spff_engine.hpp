@@ -35,6 +35,7 @@ enum Phase : int32_t {
   PH_STATS = 7,
   PH_X_PROJ = 8,  // diagnostic: rm = G[theta] (3 planes)
   PH_X_LAP = 9,   // diagnostic: rm[0] = -lap theta[0]
+  PH_TD_RESTORE = 10,  // time-discretized evolution: phi <- phi_n before a retry with dt/2
 };
 
 // ctl.flags bits
@@ -66,7 +67,8 @@ struct SlotParam {
   double floor_coef;
   double lap_rms;          // mean |2 pi q|^2 over the grid's modes (2 pi^2 / 3)
   int32_t at, split, irr, stall_iters;  // split: driving-force model
-  int32_t contact, pad_c;                 // stress model
+  int32_t contact, evolution;             // stress model; SPFF_EVOL_AM / _TIME
+  double eta, dt_max, dt_min, dphi_max, dphi_min;  // time-discretized evolution
   int32_t max_cg, max_newton, max_bccg, max_am;
 };
 
@@ -88,6 +90,10 @@ struct SlotCtl {
   int32_t pf_best_it, pad1;
   // alternating minimisation
   double dphi;
+  // viscous term of the running phase-field solve; time-discretized
+  // evolution: time step (kept between load steps), halvings, load advance
+  double eta_dt, dt;
+  int32_t halvings, advance;
   // statistics of the finished step
   double F_e, F_f, sbar[3], phi_sum, phi_max, crack_px;
 };
@@ -121,7 +127,9 @@ struct SlotSeq {
 };
 
 struct StepRec {
-  int32_t status, flags, am, newton, cg, bccg, ticks, pad;
+  int32_t status, flags, am, newton, cg, bccg, ticks, halvings;
+  int32_t advance, pad;
+  double dt;
   uint64_t t_start, t_end;  // device wall clock
   double dphi, mech_res, pf_res, F_e, F_f, sbar[3], phi_sum, phi_max, crack_px;
   double eps_bar[3];

@@ -116,6 +116,7 @@ template <typename real>
 struct RowCtx {
   int phase, flags, split, contact, n, ncomp;  // split: driving-force model, contact: stress model
   real lt, mt, kres, eb0, eb1, eb2, beta_m, beta_pf, alpha_pf;
+  double eta_dt;
 };
 
 template <typename real>
@@ -136,6 +137,7 @@ __device__ __forceinline__ RowCtx<real> row_ctx(const SlotCtl& ctl, const SlotPa
   X.beta_m = real(ctl.beta_m);
   X.beta_pf = real(ctl.beta_pf);
   X.alpha_pf = real(ctl.alpha_pf);
+  X.eta_dt = ctl.eta_dt;
   return X;
 }
 
@@ -234,8 +236,8 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
         const Sym<real> e = {eb0 + xv[q], eb1 + yv[q], eb2 + sv[q]};
         real pp, pm;
         energies(e, lam, mu, split, &pp, &pm);
-        dv[q] = real(2) * pp + real(P.cwl * P.wpp + P.eta_dt);
-        bv[q] = real(2) * pp - real(P.cwl * P.dw0) + real(P.eta_dt) * rv[q];
+        dv[q] = real(2) * pp + real(P.cwl * P.wpp + X.eta_dt);
+        bv[q] = real(2) * pp - real(P.cwl * P.dw0) + real(X.eta_dt) * rv[q];
         const real lo = lower_bound(rv[q], P);
         cv[q] = fmin(fmax(pv[q], lo), real(1));
         acc[0] += double(bv[q]) * double(bv[q]);
@@ -275,6 +277,11 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       st2(phip + o, a0, a1);
       val[0][0] = a0;
       val[0][1] = a1;
+      break;
+    }
+    case PH_TD_RESTORE: {
+      const V2<real> pr = ld2(prefp + o);
+      st2(phip + o, pr.a, pr.b);
       break;
     }
     case PH_AM_CHK: {
@@ -345,6 +352,7 @@ __device__ __forceinline__ void row_prologue_n(const RowCtx<real>& X, const Slot
     SPFF_PRO_CASE(PH_PF_PQ)
     SPFF_PRO_CASE(PH_PF_R)
     SPFF_PRO_CASE(PH_AM_CHK)
+    SPFF_PRO_CASE(PH_TD_RESTORE)
     SPFF_PRO_CASE(PH_STATS)
     SPFF_PRO_CASE(PH_X_PROJ)
     SPFF_PRO_CASE(PH_X_LAP)
@@ -378,7 +386,7 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
   const SlotCtl& ctl = ctls[s];
   const int phase = ctl.phase;
   const int ncomp = phase_comps_row(phase);
-  if (phase != PH_AM_CHK && ncomp == 0) return;
+  if (phase != PH_AM_CHK && phase != PH_TD_RESTORE && ncomp == 0) return;
   const SlotParam& P = prms[s];
   const SlotPtr<real> F = ptrs[s];
   const int flags = ctl.flags;
@@ -909,7 +917,7 @@ __device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, con
   const SlotCtl& ctl = ctls[s];
   const int phase = ctl.phase;
   const int ncomp = phase_comps_row(phase);
-  if (phase != PH_AM_CHK && ncomp == 0) return;
+  if (phase != PH_AM_CHK && phase != PH_TD_RESTORE && ncomp == 0) return;
   const SlotParam& P = prms[s];
   const SlotPtr<real> F = ptrs[s];
   const int R = blockDim.x / L;
@@ -1190,6 +1198,7 @@ __device__ inline void phase_bytes(int phase, int flags, int split, double r, do
       b[2] = sp + r * (5 + 1) + 1;
       break;
     case PH_AM_CHK:
+    case PH_TD_RESTORE:
       b[0] = 2 * r;
       break;
     case PH_STATS:
@@ -1241,6 +1250,8 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
   double alpha_pf = C.alpha_pf, beta_pf = C.beta_pf, pq = C.pq, rp = C.rp, dphi = C.dphi;
   double pf_bnorm = C.pf_bnorm, pf_best = C.pf_best, mech_floor = C.mech_floor, pf_floor = C.pf_floor;
   int pf_best_it = C.pf_best_it;
+  double eta_dt = C.eta_dt, dt = C.dt;
+  int halvings = C.halvings, advance = C.advance;
   bool bad = false;
   auto pf_done = [&]() {
     if (flags & FL_INIT_SOLVE) {
@@ -1377,6 +1388,21 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
       dphi = wave_reduce_partials(pr, ngr);
       bad = !isfinite(dphi);
       ++am;
+      if (P.evolution == 1) {
+        // Algorithm 3: accept the phase field if its change is small enough
+        // or dt has reached its floor, else retry from phi_n with dt / 2
+        if (dphi < P.dphi_max || dt <= P.dt_min) {
+          if (dphi < 0.5 * P.dphi_max) dt = fmin(2.0 * dt, P.dt_max);
+          advance = (dphi < P.dphi_min && dt >= P.dt_max) ? 1 : 0;
+          nphase = PH_STATS;
+        } else {
+          dt *= 0.5;
+          ++halvings;
+          eta_dt = P.eta / dt;
+          nphase = PH_TD_RESTORE;
+        }
+        break;
+      }
       if (dphi <= P.tol_am) {
         nphase = PH_STATS;
       } else if (am >= P.max_am) {
@@ -1387,6 +1413,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
       }
       break;
     }
+    case PH_TD_RESTORE:
+      nphase = PH_PF_ASM;
+      break;
     case PH_X_PROJ:
     case PH_X_LAP:
       nphase = PH_IDLE;
@@ -1430,6 +1459,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
       r.cg = cg;
       r.bccg = bccg;
       r.ticks = C.ticks + 1;
+      r.dt = dt;
+      r.halvings = halvings;
+      r.advance = advance;
       r.t_start = C.t_start;
       r.t_end = wall_clock64();
       r.dphi = dphi;
@@ -1460,6 +1492,10 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
     C.ticks = 0;
     C.status = 0;
     C.dphi = 0.0;
+    C.dt = dt;
+    C.halvings = 0;
+    C.advance = 0;
+    C.eta_dt = P.evolution == 1 ? P.eta / dt : P.eta_dt;
     C.t_start = wall_clock64();
     return;
   }
@@ -1495,6 +1531,10 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
     C.pf_best_it = pf_best_it;
     C.mech_floor = mech_floor;
     C.pf_floor = pf_floor;
+    C.eta_dt = eta_dt;
+    C.dt = dt;
+    C.halvings = halvings;
+    C.advance = advance;
     C.ticks = C.ticks + 1;
   }
 }

@@ -22,6 +22,7 @@ OK, WARN_NOT_CONVERGED, E_INVALID, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY = 0, 1
 AT1, AT2 = 1, 2
 SPLIT_NONE, SPLIT_SPECTRAL, SPLIT_VOLDEV = 0, 1, 2
 CONTACT_SAME = -1
+EVOL_AM, EVOL_TIME = 0, 1
 IRR_CRACK_SET, IRR_DAMAGE = 0, 1
 FP32, FP64 = 0, 1
 OP_PROJECT, OP_NEG_LAPLACIAN = 0, 1
@@ -54,7 +55,9 @@ class Config(ctypes.Structure):
         ("max_am", ctypes.c_int32), ("ticks_per_sync", ctypes.c_int32), ("use_graph", ctypes.c_int32),
         ("floor_factor", ctypes.c_double), ("stall_iters", ctypes.c_int32),
         ("plan_rows", ctypes.c_int32), ("plan_cols", ctypes.c_int32), ("plan_threads", ctypes.c_int32),
-        ("contact", ctypes.c_int32),
+        ("contact", ctypes.c_int32), ("evolution", ctypes.c_int32),
+        ("eta", ctypes.c_double), ("dt_max", ctypes.c_double), ("dt_min", ctypes.c_double),
+        ("dphi_max", ctypes.c_double), ("dphi_min", ctypes.c_double),
     ]
 
 
@@ -66,6 +69,7 @@ class StepStats(ctypes.Structure):
         ("F_e", ctypes.c_double), ("F_f", ctypes.c_double), ("sigma_bar", ctypes.c_double * 3),
         ("C_bar", ctypes.c_double), ("phi_max", ctypes.c_double), ("phi_mean", ctypes.c_double),
         ("crack_px", ctypes.c_int64), ("wall_ms", ctypes.c_double),
+        ("dt", ctypes.c_double), ("halvings", ctypes.c_int32), ("advance", ctypes.c_int32),
     ]
 
     def to_dict(self):

@@ -67,6 +67,26 @@ def test_invalid_config_rejected(field, value):
     assert spff.last_error()
 
 
+@pytest.mark.parametrize("field,value", [("evolution", 2), ("evolution", -1), ("eta", -1.0), ("dt_min", 0.0),
+                                         ("dt_max", 1e-4), ("dphi_max", 0.0), ("dphi_min", -1.0)])
+def test_invalid_time_discretized_config_rejected(field, value):
+    """Algorithm 3's parameters are checked only when it is selected."""
+    cfg = spff.default_config(evolution=spff.EVOL_TIME, eta=1.0)
+    assert spff.workspace_bytes(cfg, 1) > 0
+    setattr(cfg, field, value)
+    out = ctypes.c_size_t(0)
+    assert spff.lib().spff_workspace_bytes(ctypes.byref(cfg), 1, ctypes.byref(out)) == spff.E_INVALID
+    if field not in ("evolution",):
+        cfg.evolution = spff.EVOL_AM
+        assert spff.workspace_bytes(cfg, 1) > 0
+
+
+def test_time_discretized_defaults():
+    cfg = spff.default_config()
+    assert cfg.evolution == spff.EVOL_AM and cfg.eta == 0.0
+    assert 0.0 < cfg.dt_min <= cfg.dt_max and cfg.dphi_max > 0.0 and cfg.dphi_min >= 0.0
+
+
 @pytest.mark.parametrize("split,contact", [(0, -1), (1, -1), (2, -1), (1, 0), (1, 2), (0, 1), (2, 2)])
 def test_model_matrix_accepted(split, contact):
     """Every driving-force / contact pairing of the three energy models is a

@@ -363,3 +363,101 @@ def test_profile_counters():
     assert prof["kernel_ms"]["ctrl"] == 0
     # per launch, a 64x64 tick kernel runs for well under a millisecond
     assert prof["kernel_ms"]["col"] / prof["launches"]["col"] < 1.0
+
+
+def _td_phi(psi, eta, dt, gc, ell, phi_n):
+    """Homogeneous AT2 phase field of one time step of Algorithm 3 (Sec.
+    3.2.2): (2 psi + G_c/l + eta/dt) phi = 2 psi + (eta/dt) phi_n."""
+    return (2 * psi + eta / dt * phi_n) / (2 * psi + gc / ell + eta / dt)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_time_step_homogeneous_closed_form(precision):
+    """Algorithm 3 on a homogeneous AT2 material, against the closed form:
+    dt is halved until the change of phi, N^2 |phi(dt) - phi_n|, drops
+    below dphi_max; the accepted phi is the closed form at that dt; dt then
+    doubles back (capped at dt_max) over the following steps."""
+    n, eta, e, nu, ell = 64, 2.0, 0.5, 0.2, 2.0
+    lam = nu / ((1 + nu) * (1 - 2 * nu))
+    mu = 1.0 / (2 * (1 + nu))
+    psi = 0.5 * (lam + 2 * mu) * e * e
+    dphi = lambda dt, phi_n=0.0: n * n * abs(_td_phi(psi, eta, dt, 1.0, ell, phi_n) - phi_n)  # noqa: E731
+    dphi_max = 0.5 * dphi(1.0 / 8)
+    k, dt = 0, 1.0
+    while not dphi(dt) < dphi_max:
+        dt, k = dt / 2, k + 1
+    # every decision is far from its threshold (relative margins >= 2%)
+    for x in (dphi(dt) / dphi_max, dphi(2 * dt) / dphi_max, 2 * dphi(dt) / dphi_max):
+        assert abs(x - 1) > 1e-2
+    cfg = cfg_for(n, precision=precision, at=2, ell=ell, evolution=spff.EVOL_TIME, eta=eta, dt_max=1.0,
+                  dt_min=1e-4, dphi_max=dphi_max, dphi_min=0.0)
+    p = spff.Problem(torch_E(np.ones((n, n)), precision), cfg)
+    _, stats = p.load_step((0.0, e, 0.0))
+    s = stats[0]
+    assert s["halvings"] == k and k >= 3 and s["advance"] == 0
+    phi = p.get_fields(spff.FIELD_PHI)["phi"].double().cpu().numpy()
+    atol = 1e-10 if precision == "fp64" else 2e-6
+    assert np.abs(phi - _td_phi(psi, eta, dt, 1.0, ell, 0.0)).max() <= atol
+    want = min(2 * dt, 1.0) if dphi(dt) < 0.5 * dphi_max else dt
+    assert s["dt"] == pytest.approx(want, rel=1e-12)
+    # the next steps start from the carried-over dt
+    phi_n = float(phi.mean())
+    _, stats = p.load_step((0.0, e, 0.0))
+    dt2 = want
+    while not dphi(dt2, phi_n) < dphi_max:
+        dt2 /= 2
+    phi2 = p.get_fields(spff.FIELD_PHI)["phi"].double().cpu().numpy()
+    assert np.abs(phi2 - _td_phi(psi, eta, dt2, 1.0, ell, phi_n)).max() <= atol
+    p.close()
+
+
+def test_time_step_without_viscosity_is_one_am_iteration():
+    """With eta = 0 and no bound on the change of phi, a time step of
+    Algorithm 3 runs the same sub-solves as one alternating-minimisation
+    iteration: the fields agree bit for bit."""
+    E, ramp = _c1_inputs()
+    a = spff.Problem(torch_E(E, "fp32"), cfg_for(64, max_am=1))
+    b = spff.Problem(torch_E(E, "fp32"), cfg_for(64, evolution=spff.EVOL_TIME, eta=0.0, dphi_max=1e30))
+    for s in (8, 12, 13):
+        _, sa = a.load_step(ramp[s])
+        _, sb = b.load_step(ramp[s])
+        assert sb[0]["halvings"] == 0 and sb[0]["dt"] == 1.0
+        fa, fb = gpu_fields(a), gpu_fields(b)
+        for k in ("phi", "eps_star", "stress"):
+            assert np.array_equal(fa[k], fb[k]), (s, k)
+    assert sa[0]["phi_max"] > 0.0
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_time_steps_parity_through_halvings(precision):
+    """Algorithm 3 (Sec. 3.2.2) on the heterogeneous CPU-sized input, AT1,
+    eta = 0.5, dphi_max = 20 px: the elastic steps run on the device queue
+    (dt stays at dt_max, every step advances); from the nucleation on, each
+    time step is compared with the oracle's from the GPU state and dt (the
+    steps after nucleation halve dt two and three times)."""
+    E, ramp = _c1_inputs()
+    td = dict(evolution=spff.EVOL_TIME, eta=0.5, dt_max=1.0, dt_min=1e-3, dphi_max=20.0, dphi_min=1e-3)
+    cfg = cfg_for(64, precision=precision, **td)
+    p = spff.Problem(torch_E(E, precision), cfg)
+    st, seq = p.run_sequence(ramp[:12])
+    assert st == spff.OK
+    for s in seq[0]:
+        assert s["dt"] == 1.0 and s["halvings"] == 0 and s["advance"] == 1 and s["phi_max"] == 0.0
+    o = oracle_for(E, cfg)
+    dt, seen = 1.0, 0
+    for k in (12, 13, 14):
+        set_oracle_from_gpu(o, p)
+        o.dt = dt
+        _, stats = p.load_step(ramp[k])
+        ost = o.time_step(ramp[k], 0.5, 1.0, 1e-3, 20.0, 1e-3)
+        g = stats[0]
+        print(k, g["dt"], g["halvings"], g["dphi_l1"], ost["dt"], ost["halvings"], ost["dphi"])
+        assert (g["halvings"], g["advance"]) == (ost["halvings"], int(ost["advance"]))
+        assert g["dt"] == ost["dt"]
+        assert g["dphi_l1"] == pytest.approx(ost["dphi"], rel=1e-6 if precision == "fp64" else 2e-3)
+        compare(gpu_fields(p), oracle_fields(o), precision, phi_tol=1e-6 if precision == "fp64" else 1e-3)
+        dt, seen = g["dt"], seen + g["halvings"]
+    assert seen >= 3
+    p.close()
