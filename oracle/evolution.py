@@ -26,6 +26,19 @@ Readings of the paper:
     the stress (mechanics problem); contact=None means the same model
     (variational).  The elastic energy reported is the one of the contact
     model, whose derivative the stress is.
+  * ``near_equilibrium_step`` is one iteration of the near-equilibrium
+    evolution (Algorithm 4, Sec. 3.2.2), with these readings of its printed
+    formulas: the crack driving force that gates the rescaling is
+    -h'(phi) psi0+ = 2 (1 - phi) psi0+ (the printed -h psi0+ is never
+    positive); psi0+ is degree-two homogeneous, psi0+(g eps) = g^2 psi0+(eps)
+    (the printed right-hand side lost psi0+); so g solves
+    g^2 (-h' psi0+)(x*) + [-F_phi - (-h' psi0+)](x*) = (-F_phi)_max, i.e. the
+    denominator is -h' psi0+ > 0 (printed with the opposite sign); a
+    negative g^2 (the part of -F_phi that does not scale already exceeds the
+    bound) gives g = 0, and a vanishing driving force at x* leaves the strain
+    unscaled; F_phi carries no viscous term (at phi = phi_n it is zero
+    anyway); x* is the first maximiser in row-major order; the trigger flag
+    persists once set.
 """
 
 import numpy as np
@@ -191,6 +204,60 @@ class Problem:
         advance = dphi < dphi_min and self.dt >= dt_max
         return self.stats(am=1, newton=mi["newton"], cg=mi["cg"], bccg=bccg, dphi=dphi, converged=converged,
                           dt=self.dt, halvings=halvings, advance=bool(advance))
+
+    # -- Algorithm 4, one iteration n of the near-equilibrium evolution ----
+    def near_equilibrium_step(self, eps_bar, deps, fphi_max, drive_threshold, eta=0.0, dt_max=1.0,
+                              dphi_min=0.0):
+        """One outer iteration of Algorithm 4 (Sec. 3.2.2) at macroscopic
+        strain ``eps_bar``: the elasticity sub-problem at phi_n; if the
+        largest -F_phi(phi_n, eps_n) exceeds ``fphi_max`` (and the trigger
+        flag is set: the largest crack driving force -h'(phi_n) psi0+ has
+        once exceeded ``drive_threshold``), the whole strain (eps_bar and
+        eps*) is scaled by g so that -F_phi = fphi_max at the maximiser x*,
+        with g capped at 1 + max|deps| / max|eps_bar|; then the phase-field
+        sub-problem with phi_con(phi_n) and the viscous term eta/dt_max.
+        ``deps`` is the load increment (xx, yy, xy).  Returns the stats dict
+        with ``gamma``, ``fphi_max`` (the largest -F_phi before scaling),
+        ``eps_bar`` (the scaled macroscopic strain), ``ne_flag`` and
+        ``advance`` (||phi_n+1 - phi_n||_1 < dphi_min: the caller then adds
+        deps to the returned eps_bar)."""
+        eps_bar = np.asarray(eps_bar, dtype=np.float64)
+        if eps_bar.shape == (3,):
+            eps_bar = cm.sym_tensor(*eps_bar)
+        if not hasattr(self, "ne_flag"):
+            self.ne_flag = False
+        self.eps_bar = eps_bar
+        phi_n = self.phi.copy()
+        self.phi_ref = phi_n
+        lo = pf.constraint_field(phi_n, self.irr, self.threshold)
+        mi = self.solve_mechanics()
+        psi = self.psi_plus()
+        neg_f = -pf.f_phi(phi_n, psi, self.at, self.gc, self.ell)
+        drive = 2.0 * (1.0 - phi_n) * psi
+        fmax = float(neg_f.max())
+        if fmax > fphi_max and float(drive.max()) > drive_threshold:
+            self.ne_flag = True
+        gamma = 1.0
+        if fmax > fphi_max and self.ne_flag:
+            i = int(np.argmax(neg_f))
+            dx, fx = float(drive.flat[i]), float(neg_f.flat[i])
+            if dx > 0.0:
+                gamma = float(np.sqrt(max((fphi_max - (fx - dx)) / dx, 0.0)))
+            eb = max(abs(eps_bar[0, 0]), abs(eps_bar[1, 1]), abs(eps_bar[0, 1]))
+            if eb > 0.0:
+                gamma = min(gamma, 1.0 + float(np.max(np.abs(deps))) / eb)
+            self.eps_star = gamma * self.eps_star
+            self.eps_bar = gamma * self.eps_bar
+        op = pf.Operator(self.psi_plus(), self.at, self.gc, self.ell, eta / dt_max, phi_n)
+        phi_new, pi = pf.bccg(phi_n, lo, np.ones_like(lo), op, self.tol_pf, self.tol_abs_pf, self.max_bccg)
+        dphi = float(np.sum(np.abs(phi_new - phi_n)))
+        self.phi = phi_new
+        self.step_count += 1
+        converged = bool(mi["converged"]) and pi["stopped"] == "converged"
+        ebar = [float(self.eps_bar[0, 0]), float(self.eps_bar[1, 1]), float(self.eps_bar[0, 1])]
+        return self.stats(am=1, newton=mi["newton"], cg=mi["cg"], bccg=pi["iterations"], dphi=dphi,
+                          converged=converged, gamma=gamma, fphi_max=fmax, eps_bar=ebar,
+                          ne_flag=bool(self.ne_flag), advance=bool(dphi < dphi_min))
 
     def stats(self, **extra):
         sig = self.stress()

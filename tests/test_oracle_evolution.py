@@ -11,7 +11,9 @@ import pytest
 
 import oracle
 from oracle import constitutive as cm
+from oracle import mechanics as mech
 from oracle import phasefield as pf
+from oracle import spectral as sp
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "strength_closed_forms.json")))
 
@@ -268,3 +270,92 @@ def test_displacement_matches_strain():
     u = p.displacement()
     from oracle import spectral as sp
     np.testing.assert_allclose(sp.symmetric_gradient(u), p.eps_star, atol=1e-10)
+
+
+@pytest.mark.parametrize("at", [1, 2])
+def test_near_equilibrium_homogeneous_closed_form(at):
+    """Algorithm 4 on a homogeneous material from phi = 0 under uniaxial
+    strain e: -F_phi = 2 psi - c w'(0) everywhere (c = G_c/(c_w l), psi =
+    (lam + 2 mu) e^2 / 2), so the rescaling factor is
+    g^2 = (fphi_max + c w'(0)) / (2 psi), the macroscopic strain becomes g e,
+    and (eta = 0) the phase field is the homogeneous minimiser at the scaled
+    strain: AT1 fphi_max / (fphi_max + c), AT2 fphi_max / (fphi_max + 2 c)."""
+    n, e, ell, fmax = 6, 0.5, 2.0, 0.05
+    lam, mu = cm.lame(1.0, 0.2)
+    psi = 0.5 * (lam + 2 * mu) * e * e
+    c = 1.0 / ((8.0 / 3.0 if at == 1 else 2.0) * ell)
+    dw0 = 1.0 if at == 1 else 0.0
+    p = oracle.Problem(np.full((n, n), 1.0), nu=0.2, ell=ell, gc=1.0, at=at, split="spectral", tol_pf=1e-12)
+    st = p.near_equilibrium_step((0.0, e, 0.0), (0.0, 1e-3, 0.0), fmax, 0.0)
+    g = np.sqrt((fmax + c * dw0) / (2 * psi))
+    assert g < 1.0 and st["gamma"] == pytest.approx(g, rel=1e-12) and st["ne_flag"]
+    assert st["fphi_max"] == pytest.approx(2 * psi - c * dw0, rel=1e-12)
+    np.testing.assert_allclose(st["eps_bar"], [0.0, g * e, 0.0], rtol=1e-12, atol=1e-15)
+    want = fmax / (fmax + c) if at == 1 else fmax / (fmax + 2 * c)
+    np.testing.assert_allclose(p.phi, want, rtol=1e-9)
+    np.testing.assert_allclose(p.strain()[..., 1, 1], g * e, rtol=1e-12)
+    assert st["sigma_bar"][1] == pytest.approx((1 - want) ** 2 * (lam + 2 * mu) * g * e, rel=1e-9)
+
+
+@pytest.mark.parametrize("split", ["none", "spectral", "voldev"])
+def test_near_equilibrium_bound_by_energy_variation(split):
+    """After the rescaling of Algorithm 4, minus the derivative of the total
+    energy F_e + F_f with respect to phi at x* (central differences of the
+    energies, exact for their quadratic dependence on one pixel) equals
+    (-F_phi)_max; the scaled strain still solves the mechanics problem
+    (the stress is degree-one homogeneous in the strain), and the scaled
+    macroscopic strain is g eps_bar."""
+    E = _hetero(12, seed=5)
+    n = E.shape[0]
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    phi0 = 0.5 * np.exp(-((xx - 5.0) ** 2 + (yy - 6.0) ** 2) / 4.0)
+    p = oracle.Problem(E, nu=0.2, ell=1.5, gc=1.0, at=1, split=split, irreversibility="damage",
+                       tol_mech=1e-12, tol_pf=1e-12)
+    p.set_state({"eps_star": np.zeros((n, n, 2, 2)), "phi": phi0, "phi_ref": phi0,
+                 "eps_bar": cm.sym_tensor(0.0, 0.0, 0.0)})
+    eb = (0.05, 0.6, 0.02)
+    fmax = 0.1
+    st = p.near_equilibrium_step(eb, (0.0, 1e-3, 0.0), fmax, 0.0)
+    g = st["gamma"]
+    assert 0.0 < g < 1.0 and st["fphi_max"] > fmax
+    np.testing.assert_allclose(st["eps_bar"], np.multiply(g, eb), rtol=1e-13)
+    # -dF/dphi at x*, from the energies at the scaled strain and phi_n
+    eps_star = p.eps_star.copy()
+    q = oracle.Problem(E, nu=0.2, ell=1.5, gc=1.0, at=1, split=split, irreversibility="damage")
+    q.set_state({"eps_star": eps_star, "phi": phi0, "phi_ref": phi0, "eps_bar": cm.sym_tensor(*st["eps_bar"])})
+
+    def total(ph):
+        return q.elastic_energy(phi=ph) + q.fracture_energy(phi=ph)
+
+    psi = q.psi_plus()
+    negf = -pf.f_phi(phi0, psi, 1, 1.0, 1.5)
+    i = np.unravel_index(int(np.argmax(negf)), negf.shape)
+    h = 1e-4
+    a, b = phi0.copy(), phi0.copy()
+    a[i] += h
+    b[i] -= h
+    deriv = (total(a) - total(b)) / (2 * h)
+    assert -deriv == pytest.approx(fmax, rel=1e-6)
+    # equilibrium survives the scaling
+    sig = q.stress()
+    g_sig = sp.project(sig)
+    assert np.sqrt(mech.inner(g_sig, g_sig)) <= 1e-9 * np.sqrt(mech.inner(sig, sig))
+
+
+def test_near_equilibrium_trigger_flag_persists_and_advance():
+    """The rescaling waits for the crack driving force to pass its threshold
+    once (Algorithm 4's flag) and keeps working after that; below the bound
+    on -F_phi the strain is not touched and a quiet step advances the load."""
+    n, e, fmax = 6, 0.5, 0.05
+    p = oracle.Problem(np.full((n, n), 1.0), nu=0.2, ell=2.0, gc=1.0, at=2, split="spectral")
+    st = p.near_equilibrium_step((0.0, e, 0.0), (0.0, 1e-3, 0.0), fmax, 1e9)
+    assert st["gamma"] == 1.0 and not st["ne_flag"] and st["eps_bar"][1] == e
+    # phi_n now minimises F at e (-F_phi = 0): load further
+    st = p.near_equilibrium_step((0.0, 2 * e, 0.0), (0.0, 1e-3, 0.0), fmax, 0.0)
+    assert st["gamma"] < 1.0 and st["ne_flag"]
+    st = p.near_equilibrium_step((0.0, 4 * e, 0.0), (0.0, 1e-3, 0.0), fmax, 1e9)
+    assert st["gamma"] < 1.0 and st["ne_flag"]
+    # AT1 below its elastic limit: -F_phi < 0, nothing moves, the load advances
+    r = oracle.Problem(np.full((n, n), 1.0), nu=0.2, ell=2.0, gc=1.0, at=1, split="spectral")
+    st = r.near_equilibrium_step((0.0, 0.1, 0.0), (0.0, 1e-3, 0.0), fmax, 0.0, dphi_min=1e-6)
+    assert st["gamma"] == 1.0 and st["dphi"] == 0.0 and st["advance"] and not st["ne_flag"]
