@@ -69,9 +69,10 @@ enum { SPFF_AT1 = 1, SPFF_AT2 = 2 };
 enum { SPFF_SPLIT_NONE = 0, SPFF_SPLIT_SPECTRAL = 1, SPFF_SPLIT_VOLDEV = 2 };
 enum { SPFF_CONTACT_SAME = -1 };
 /* Evolution method of a load step (Sec. 3.2): alternating minimisation
- * (Algorithm 2) or one iteration of the time-discretized evolution
- * (Algorithm 3). */
-enum { SPFF_EVOL_AM = 0, SPFF_EVOL_TIME = 1 };
+ * (Algorithm 2), one iteration of the time-discretized evolution
+ * (Algorithm 3) or one iteration of the near-equilibrium evolution
+ * (Algorithm 4). */
+enum { SPFF_EVOL_AM = 0, SPFF_EVOL_TIME = 1, SPFF_EVOL_NEAR_EQ = 2 };
 enum { SPFF_IRR_CRACK_SET = 0, SPFF_IRR_DAMAGE = 1 };
 enum { SPFF_FP32 = 0, SPFF_FP64 = 1 };
 
@@ -131,10 +132,25 @@ typedef struct spff_config {
    * (initially dt_max).  The step's stats report dt and whether Algorithm 3
    * increments the load (dphi < dphi_min and dt >= dt_max); the caller adds
    * the strain increment then. */
-  int32_t evolution;       /* SPFF_EVOL_AM or SPFF_EVOL_TIME */
+  int32_t evolution;       /* SPFF_EVOL_AM, SPFF_EVOL_TIME or SPFF_EVOL_NEAR_EQ */
   double eta;              /* viscosity eta >= 0 (SPFF_EVOL_TIME) */
   double dt_max, dt_min;   /* 0 < dt_min <= dt_max */
   double dphi_max, dphi_min; /* bounds on ||phi_n+1 - phi_n||_1 (pixel units) */
+  /* SPFF_EVOL_NEAR_EQ (Sec. 3.2.2, Algorithm 4): a load step is one
+   * iteration n at the given eps_bar: elasticity at phi_n; if
+   * max(-F_phi(phi_n, eps_n)) > fphi_max and the trigger flag is set (set
+   * once max(-h'(phi_n) psi0+) > drive_threshold together with the first
+   * condition, kept afterwards), eps* and eps_bar are scaled by
+   * g = sqrt((fphi_max - [-F_phi + h' psi0+](x*)) / (-h' psi0+)(x*)) at the
+   * first maximiser x* of -F_phi (row-major), g <= 1 + deps_max /
+   * max|eps_bar|; then the phase field with phi_con(phi_n) and the viscous
+   * term eta/dt_max.  Stats report g, the largest -F_phi before scaling, the
+   * scaled eps_bar, the flag and advance = ||phi_n+1 - phi_n||_1 <
+   * dphi_min (the caller then adds its increment to the returned eps_bar).
+   * Uses eta, dt_max and dphi_min above. */
+  double fphi_max;         /* bound on -F_phi, > 0 */
+  double drive_threshold;  /* trigger threshold on -h'(phi) psi0+, >= 0 */
+  double deps_max;         /* max |component| of the load increment, >= 0 */
 } spff_config;
 
 /* Per-problem result of one load step (Sec. 3.2.1 quantities). */
@@ -156,7 +172,12 @@ typedef struct spff_step_stats {
   double wall_ms;          /* host wall time from enqueueing the step to observing its end */
   double dt;               /* SPFF_EVOL_TIME: dt for the next step */
   int32_t halvings;        /* SPFF_EVOL_TIME: dt halvings in this step */
-  int32_t advance;         /* SPFF_EVOL_TIME: 1 if Algorithm 3 increments the load now */
+  int32_t advance;         /* SPFF_EVOL_TIME / _NEAR_EQ: 1 if the algorithm increments the load now */
+  double gamma;            /* SPFF_EVOL_NEAR_EQ: strain scaling factor of the step (1: none) */
+  double fphi_max;         /* SPFF_EVOL_NEAR_EQ: largest -F_phi(phi_n, eps_n) before scaling */
+  double eps_bar[3];       /* macroscopic strain at the end of the step (xx, yy, xy) */
+  int32_t ne_flag;         /* SPFF_EVOL_NEAR_EQ: trigger flag after the step */
+  int32_t reserved;
 } spff_step_stats;
 
 typedef struct spff_problem spff_problem; /* opaque: a batch of 1..B problems */

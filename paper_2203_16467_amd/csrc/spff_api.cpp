@@ -72,7 +72,14 @@ spff_status check_config(const spff_config* c) {
   if (c->contact != SPFF_CONTACT_SAME && c->contact != SPFF_SPLIT_NONE && c->contact != SPFF_SPLIT_SPECTRAL &&
       c->contact != SPFF_SPLIT_VOLDEV)
     return fail(SPFF_E_INVALID, "bad contact model");
-  if (c->evolution != SPFF_EVOL_AM && c->evolution != SPFF_EVOL_TIME) return fail(SPFF_E_INVALID, "bad evolution");
+  if (c->evolution != SPFF_EVOL_AM && c->evolution != SPFF_EVOL_TIME && c->evolution != SPFF_EVOL_NEAR_EQ)
+    return fail(SPFF_E_INVALID, "bad evolution");
+  if (c->evolution == SPFF_EVOL_NEAR_EQ &&
+      (!(c->eta >= 0.0) || !(c->dt_max > 0.0) || !std::isfinite(c->dt_max) || !(c->dphi_min >= 0.0) ||
+       !(c->fphi_max > 0.0) || !std::isfinite(c->fphi_max) || !(c->drive_threshold >= 0.0) ||
+       !(c->deps_max >= 0.0)))
+    return fail(SPFF_E_INVALID, "near-equilibrium evolution needs eta >= 0, dt_max > 0, dphi_min >= 0, "
+                                "fphi_max > 0, drive_threshold >= 0, deps_max >= 0");
   if (c->evolution == SPFF_EVOL_TIME &&
       (!(c->eta >= 0.0) || !(c->dt_min > 0.0) || !(c->dt_max >= c->dt_min) || !std::isfinite(c->dt_max) ||
        !(c->dphi_max > 0.0) || !(c->dphi_min >= 0.0)))
@@ -522,6 +529,9 @@ SlotParam make_param(const spff_config* c) {
   P.dt_min = c->dt_min;
   P.dphi_max = c->dphi_max;
   P.dphi_min = c->dphi_min;
+  P.fphi_max = c->fphi_max;
+  P.drive_thr = c->drive_threshold;
+  P.deps_max = c->deps_max;
   P.irr = c->irreversibility;
   P.max_cg = c->max_cg;
   P.max_newton = c->max_newton;
@@ -631,6 +641,10 @@ void fill_stats(const spff_problem* p, const SlotCtl& c, spff_step_stats& o, dou
   o.dt = c.dt;
   o.halvings = c.halvings;
   o.advance = c.advance;
+  o.gamma = c.gamma;
+  o.fphi_max = c.fmax_ne;
+  for (int k = 0; k < 3; ++k) o.eps_bar[k] = c.eps_bar[k];
+  o.ne_flag = c.ne_flag;
   for (int k = 0; k < 3; ++k) o.sigma_bar[k] = c.sbar[k];
   int kmax = 0;
   for (int k = 1; k < 3; ++k)
@@ -643,15 +657,22 @@ void fill_stats(const spff_problem* p, const SlotCtl& c, spff_step_stats& o, dou
 }
 
 void start_step(spff_problem* p, int s, const double* eb) {
-  // the time step of the time-discretized evolution carries over
+  // the time step of the time-discretized evolution and the trigger flag
+  // of the near-equilibrium evolution carry over
   const double dt = p->host_ctl[s].dt > 0.0 ? p->host_ctl[s].dt : p->cfg.dt_max;
+  const int ne_flag = p->host_ctl[s].ne_flag;
   reset_ctl(p, s);
   SlotCtl& c = p->host_ctl[s];
   for (int k = 0; k < 3; ++k) c.eps_bar[k] = eb[k];
+  const int evol = p->cfg.evolution;
   c.phase = PH_M_RES;
-  c.flags = FL_FIRST_OF_STEP;
+  c.flags = FL_FIRST_OF_STEP | (evol == SPFF_EVOL_NEAR_EQ ? FL_NE_CHECK : 0);
   c.dt = dt;
-  c.eta_dt = p->cfg.evolution == SPFF_EVOL_TIME ? p->cfg.eta / dt : p->cfg.eta_over_dt;
+  c.eta_dt = evol == SPFF_EVOL_TIME      ? p->cfg.eta / dt
+             : evol == SPFF_EVOL_NEAR_EQ ? p->cfg.eta / p->cfg.dt_max
+                                         : p->cfg.eta_over_dt;
+  c.gamma = 1.0;
+  c.ne_flag = ne_flag;
 }
 
 double now_ms() {
@@ -676,6 +697,9 @@ void spff_default_config(spff_config* c) {
   c->dt_min = 1e-3;
   c->dphi_max = 1.0;
   c->dphi_min = 0.0;
+  c->fphi_max = 0.35;        // 0.7 G_c / l at the default G_c = 1, l = 2
+  c->drive_threshold = 0.5;  // 1 G_c / l
+  c->deps_max = 0.0;
   c->irreversibility = SPFF_IRR_CRACK_SET;
   c->precision = SPFF_FP32;
   c->nu = 0.2;
@@ -877,6 +901,9 @@ spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps
         c.dt = r.dt;
         c.halvings = r.halvings;
         c.advance = r.advance;
+        c.gamma = r.gamma;
+        c.fmax_ne = r.fmax_ne;
+        c.ne_flag = r.ne_flag;
         c.flags = r.flags;
         c.dphi = r.dphi;
         c.mech_res = r.mech_res;

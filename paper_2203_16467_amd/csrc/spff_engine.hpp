@@ -49,6 +49,8 @@ enum : int32_t {
   FL_NONFINITE = 64,      // a reduction was NaN/Inf
   FL_PF_FIRST = 128,      // next PF_PQ is the first BCCG iteration (beta = 0)
   FL_STALLED = 256,       // BCCG residual stopped improving (stall guard)
+  FL_NE_CHECK = 512,      // near-equilibrium: this PF_ASM evaluates -F_phi(phi_n, eps_n)
+  FL_NE_SCALE = 1024,     // near-equilibrium: this PF_ASM first scales eps* by gamma
 };
 
 // Per-slot physical and solver parameters (read-only during a step).
@@ -67,8 +69,9 @@ struct SlotParam {
   double floor_coef;
   double lap_rms;          // mean |2 pi q|^2 over the grid's modes (2 pi^2 / 3)
   int32_t at, split, irr, stall_iters;  // split: driving-force model
-  int32_t contact, evolution;             // stress model; SPFF_EVOL_AM / _TIME
+  int32_t contact, evolution;             // stress model; SPFF_EVOL_*
   double eta, dt_max, dt_min, dphi_max, dphi_min;  // time-discretized evolution
+  double fphi_max, drive_thr, deps_max;            // near-equilibrium evolution
   int32_t max_cg, max_newton, max_bccg, max_am;
 };
 
@@ -94,6 +97,10 @@ struct SlotCtl {
   // evolution: time step (kept between load steps), halvings, load advance
   double eta_dt, dt;
   int32_t halvings, advance;
+  // near-equilibrium evolution: strain scaling of the step, largest -F_phi
+  // before it, trigger flag (kept between load steps)
+  double gamma, fmax_ne;
+  int32_t ne_flag, pad2;
   // statistics of the finished step
   double F_e, F_f, sbar[3], phi_sum, phi_max, crack_px;
 };
@@ -128,8 +135,8 @@ struct SlotSeq {
 
 struct StepRec {
   int32_t status, flags, am, newton, cg, bccg, ticks, halvings;
-  int32_t advance, pad;
-  double dt;
+  int32_t advance, ne_flag;
+  double dt, gamma, fmax_ne;
   uint64_t t_start, t_end;  // device wall clock
   double dphi, mech_res, pf_res, F_e, F_f, sbar[3], phi_sum, phi_max, crack_px;
   double eps_bar[3];

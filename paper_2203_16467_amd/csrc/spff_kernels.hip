@@ -50,9 +50,9 @@ __device__ __forceinline__ int nacc_rowfwd(int phase) {
   switch (phase) {
     case PH_M_RES:
     case PH_PF_PQ:
+    case PH_PF_ASM:
       return 2;
     case PH_M_CG:
-    case PH_PF_ASM:
     case PH_AM_CHK:
       return 1;
     case PH_STATS:
@@ -116,6 +116,7 @@ template <typename real>
 struct RowCtx {
   int phase, flags, split, contact, n, ncomp;  // split: driving-force model, contact: stress model
   real lt, mt, kres, eb0, eb1, eb2, beta_m, beta_pf, alpha_pf;
+  real ne_gamma;  // near-equilibrium strain scaling (FL_NE_SCALE)
   double eta_dt;
 };
 
@@ -138,6 +139,7 @@ __device__ __forceinline__ RowCtx<real> row_ctx(const SlotCtl& ctl, const SlotPa
   X.beta_pf = real(ctl.beta_pf);
   X.alpha_pf = real(ctl.alpha_pf);
   X.eta_dt = ctl.eta_dt;
+  X.ne_gamma = real(ctl.gamma);
   return X;
 }
 
@@ -226,7 +228,18 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
     }
     case PH_PF_ASM: {
       const V2<real> E = ld2(Ep + o), ph = ld2(phip + o), pr = ld2(prefp + o);
-      const V2<real> ex = ld2(epsp + o), ey = ld2(epsp + n + o), exy = ld2(epsp + 2 * n + o);
+      V2<real> ex = ld2(epsp + o), ey = ld2(epsp + n + o), exy = ld2(epsp + 2 * n + o);
+      if (flags & FL_NE_SCALE) {
+        // near-equilibrium evolution: eps* <- gamma eps* (eps_bar was scaled
+        // by the controller)
+        const real g = X.ne_gamma;
+        ex = {g * ex.a, g * ex.b};
+        ey = {g * ey.a, g * ey.b};
+        exy = {g * exy.a, g * exy.b};
+        st2(epsp + o, ex.a, ex.b);
+        st2(epsp + n + o, ey.a, ey.b);
+        st2(epsp + 2 * n + o, exy.a, exy.b);
+      }
       const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b}, rv[2] = {pr.a, pr.b};
       const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
       real dv[2], bv[2], cv[2];
@@ -237,6 +250,8 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
         real pp, pm;
         energies(e, lam, mu, split, &pp, &pm);
         dv[q] = real(2) * pp + real(P.cwl * P.wpp + X.eta_dt);
+        // crack driving force -h'(phi_n) psi0+ (near-equilibrium trigger)
+        if (flags & FL_NE_CHECK) acc[1] = fmax(acc[1], double(real(2) * (real(1) - rv[q]) * pp));
         bv[q] = real(2) * pp - real(P.cwl * P.dw0) + real(X.eta_dt) * rv[q];
         const real lo = lower_bound(rv[q], P);
         cv[q] = fmin(fmax(pv[q], lo), real(1));
@@ -429,7 +444,7 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
     }
   }
   block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, nacc_rowfwd(phase),
-                             phase == PH_STATS ? 3 : -1);
+                             phase == PH_STATS ? 3 : (phase == PH_PF_ASM ? 1 : -1));
 }
 
 // ===========================================================================
@@ -815,6 +830,12 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
       const bool a0 = (ph.a <= lo0 && rr0 > real(0)) || (ph.a >= real(1) && rr0 < real(0));
       const bool a1 = (ph.b <= lo1 && rr1 > real(0)) || (ph.b >= real(1) && rr1 < real(0));
       const real r0 = a0 ? real(0) : rr0, r1 = a1 ? real(0) : rr1;
+      if (phase == PH_PF_ASM && (X.flags & FL_NE_CHECK)) {
+        // near-equilibrium evolution: phi = phi_n here, so the unmasked
+        // residual is F_phi(phi_n, eps_n); keep it for the search of x*
+        st2(rmp + n + o, rr0, rr1);
+        acc[1] = fmax(acc[1], fmax(-double(rr0), -double(rr1)));
+      }
       if (phase == PH_PF_R) {
         const V2<real> ro = ld2(rmp + o);
         acc[1] += double(r0) * ro.a + double(r1) * ro.b;
@@ -978,7 +999,7 @@ __device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, con
     }
   }
   block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, nacc_rowfwd(phase),
-                             phase == PH_STATS ? 3 : -1);
+                             phase == PH_STATS ? 3 : (phase == PH_PF_ASM ? 1 : -1));
 }
 
 template <typename real, int M, int E>
@@ -1068,6 +1089,7 @@ __device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, con
     }
   }
   double acc[NP_INV] = {0.0, 0.0, 0.0, 0.0};
+  if (phase == PH_PF_ASM) acc[1] = -1.0e300;  // max of -F_phi (near-equilibrium)
   {
     C q[E][3];
 #pragma unroll
@@ -1077,7 +1099,8 @@ __device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, con
     row_epilogue_n<real, E, 2 * L>(X, P, F.phi, F.phi_ref, F.theta, F.rm, F.pm, (y0 + row) * nx + 2 * lane, q,
                                    alpha, acc);
   }
-  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr, nacc_rowinv(phase));
+  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr, nacc_rowinv(phase),
+                             phase == PH_PF_ASM ? 1 : -1);
 }
 
 // ===========================================================================
@@ -1151,6 +1174,7 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
   fft_lds<real, true, MAXE>(buf, M, ncomp * R, stride, twx, 2);
 
   double acc[NP_INV] = {0.0, 0.0, 0.0, 0.0};
+  if (phase == PH_PF_ASM) acc[1] = -1.0e300;  // max of -F_phi (near-equilibrium)
   for (int idx = threadIdx.x; idx < R * M; idx += blockDim.x) {
     const int r = idx >> logM, h = idx & (M - 1);
     const int o = (y0 + r) * nx + 2 * h;
@@ -1160,7 +1184,8 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
     for (int c = 0; c < 3; ++c) q[c] = c < ncomp ? buf[c * R * stride + li] : mk<C>(real(0), real(0));
     row_epilogue<real>(X, P, F.phi, F.phi_ref, F.theta, F.rm, F.pm, o, q, alpha, acc);
   }
-  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr, nacc_rowinv(phase));
+  block_reduce_store<NP_INV>(acc, red, part + (size_t)s * NP_INV * ngr + g, ngr, nacc_rowinv(phase),
+                             phase == PH_PF_ASM ? 1 : -1);
 }
 
 // Algorithmic HBM bytes per pixel moved by the row-forward, column and
@@ -1184,9 +1209,9 @@ __device__ inline void phase_bytes(int phase, int flags, int split, double r, do
       b[2] = 3 * sp + r * (3 + 3 + ((flags & FL_CG_FIRST) ? 0 : 3) + 6);
       break;
     case PH_PF_ASM:
-      b[0] = r * (6 + 4) + sp;
+      b[0] = r * (6 + 4) + sp + ((flags & FL_NE_SCALE) ? 3 * r : 0);
       b[1] = 2 * sp;
-      b[2] = sp + r * (4 + 1) + 1;
+      b[2] = sp + r * (4 + 1) + 1 + ((flags & FL_NE_CHECK) ? r : 0);
       break;
     case PH_PF_PQ:
       b[0] = r * (2 + ((flags & FL_PF_FIRST) ? 0 : 1) + 1) + 1 + sp;
@@ -1214,8 +1239,62 @@ __device__ inline void phase_bytes(int phase, int flags, int split, double r, do
 // Controller of one slot, run by one wavefront.  Reduces the tick's partials
 // in a fixed order, updates FP64 scalars and moves the slot's state machine.
 // ===========================================================================
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Near-equilibrium strain scaling (Sec. 3.2.2, Algorithm 4).  fm is the
+// largest -F_phi(phi_n, eps_n); the row-inverse kernel of the assembly kept
+// the unmasked residual F_phi in rm[1] and its per-row-group maxima in
+// gmax[0 .. ngr).  x* is the first pixel (row-major) where -F_phi equals fm:
+// the first row group holding the maximum, then the first pixel of that
+// group's rows.  With d = -h'(phi_n) psi0+ at x*, gamma^2 =
+// (fphi_max - (fm - d)) / d (psi0+ is degree-two homogeneous in the strain),
+// clamped at 0 and capped at 1 + deps_max / max|eps_bar|.  Returns false
+// (no scaling) when x* is not found or d is not positive.  One wavefront.
 template <typename real>
-__device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ prms, SlotCtl* __restrict__ ctls,
+__device__ bool ne_gamma(const SlotPtr<real>& F, const SlotParam& P, const SlotCtl& C, double fm,
+                         const double* __restrict__ gmax, int nx, int ny, int ngr, double* gamma) {
+  const int lane = threadIdx.x & 63;
+  int gs = ngr;
+  for (int i = lane; i < ngr; i += 64)
+    if (gmax[i] == fm) {
+      gs = i;
+      break;
+    }
+  gs = wave_min_int(gs);
+  if (gs >= ngr) return false;
+  const int n = nx * ny, rows = ny / ngr;
+  const int base = gs * rows * nx, cnt = rows * nx;
+  const real* fr = F.rm + n;
+  int xi = n;
+  for (int i = lane; i < cnt; i += 64)
+    if (-double(fr[base + i]) == fm) {
+      xi = base + i;
+      break;
+    }
+  xi = wave_min_int(xi);
+  if (xi >= n) return false;
+  const real E = F.E[xi], ph = F.phi_ref[xi];
+  const real lam = real(P.lam_t) * E, mu = real(P.mu_t) * E;
+  const Sym<real> e = {real(C.eps_bar[0]) + F.eps[xi], real(C.eps_bar[1]) + F.eps[n + xi],
+                       real(C.eps_bar[2]) + F.eps[2 * n + xi]};
+  real pp, pm;
+  energies(e, lam, mu, P.split, &pp, &pm);
+  const double d = double(real(2) * (real(1) - ph) * pp);
+  if (!(d > 0.0)) return false;
+  double g = sqrt(fmax((P.fphi_max - (fm - d)) / d, 0.0));
+  const double eb = fmax(fabs(C.eps_bar[0]), fmax(fabs(C.eps_bar[1]), fabs(C.eps_bar[2])));
+  if (eb > 0.0) g = fmin(g, 1.0 + P.deps_max / eb);
+  *gamma = g;
+  return true;
+}
+
+template <typename real>
+__device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict__ ptrs,
+                                          const SlotParam* __restrict__ prms, SlotCtl* __restrict__ ctls,
                                        const double* __restrict__ prow, const double* __restrict__ pcol,
                                        const double* __restrict__ pinv, double* __restrict__ prof,
                                        SlotSeq* __restrict__ seqs, StepRec* __restrict__ recs, int nx, int ny,
@@ -1252,6 +1331,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
   int pf_best_it = C.pf_best_it;
   double eta_dt = C.eta_dt, dt = C.dt;
   int halvings = C.halvings, advance = C.advance;
+  double gamma = C.gamma, fmax_ne = C.fmax_ne;
+  int ne_flag = C.ne_flag;
+  bool scaled = false;
   bool bad = false;
   auto pf_done = [&]() {
     if (flags & FL_INIT_SOLVE) {
@@ -1315,6 +1397,22 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
       break;
     }
     case PH_PF_ASM: {
+      flags &= ~FL_NE_SCALE;
+      if (flags & FL_NE_CHECK) {
+        // Algorithm 4: -F_phi(phi_n, eps_n) and the crack driving force
+        // -h'(phi_n) psi0+ were evaluated by this assembly
+        flags &= ~FL_NE_CHECK;
+        fmax_ne = wave_reduce_partials(pi + 1 * ngr, ngr, true);
+        const double dmax = wave_reduce_partials(pr + 1 * ngr, ngr, true);
+        if (fmax_ne > P.fphi_max && dmax > P.drive_thr) ne_flag = 1;
+        if (fmax_ne > P.fphi_max && ne_flag &&
+            ne_gamma<real>(ptrs[s], P, C, fmax_ne, pi + 1 * ngr, nx, ny, ngr, &gamma)) {
+          scaled = true;
+          flags |= FL_NE_SCALE;
+          nphase = PH_PF_ASM;  // assemble again at the scaled strain
+          break;
+        }
+      }
       const double b2 = wave_reduce_partials(pr, ngr);
       const double r2 = wave_reduce_partials(pi, ngr);
       const double x2 = wave_reduce_partials(pi + 2 * ngr, ngr);
@@ -1388,6 +1486,11 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
       dphi = wave_reduce_partials(pr, ngr);
       bad = !isfinite(dphi);
       ++am;
+      if (P.evolution == 2) {
+        advance = dphi < P.dphi_min ? 1 : 0;
+        nphase = PH_STATS;
+        break;
+      }
       if (P.evolution == 1) {
         // Algorithm 3: accept the phase field if its change is small enough
         // or dt has reached its floor, else retry from phi_n with dt / 2
@@ -1462,6 +1565,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
       r.dt = dt;
       r.halvings = halvings;
       r.advance = advance;
+      r.gamma = gamma;
+      r.fmax_ne = fmax_ne;
+      r.ne_flag = ne_flag;
       r.t_start = C.t_start;
       r.t_end = wall_clock64();
       r.dphi = dphi;
@@ -1487,7 +1593,7 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
     C.eps_bar[1] = q.eps_bar[q.pos][1];
     C.eps_bar[2] = q.eps_bar[q.pos][2];
     C.phase = PH_M_RES;
-    C.flags = FL_FIRST_OF_STEP;
+    C.flags = FL_FIRST_OF_STEP | (P.evolution == 2 ? FL_NE_CHECK : 0);
     C.am = C.newton = C.cg = C.bccg = C.cg_newton = C.pf_it = C.newton_solve = 0;
     C.ticks = 0;
     C.status = 0;
@@ -1495,7 +1601,10 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
     C.dt = dt;
     C.halvings = 0;
     C.advance = 0;
-    C.eta_dt = P.evolution == 1 ? P.eta / dt : P.eta_dt;
+    C.eta_dt = P.evolution == 1 ? P.eta / dt : (P.evolution == 2 ? P.eta / P.dt_max : P.eta_dt);
+    C.gamma = 1.0;
+    C.fmax_ne = 0.0;
+    C.ne_flag = ne_flag;
     C.t_start = wall_clock64();
     return;
   }
@@ -1535,6 +1644,14 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotParam* __restrict__ p
     C.dt = dt;
     C.halvings = halvings;
     C.advance = advance;
+    C.gamma = gamma;
+    C.fmax_ne = fmax_ne;
+    C.ne_flag = ne_flag;
+    if (scaled) {
+      C.eps_bar[0] *= gamma;
+      C.eps_bar[1] *= gamma;
+      C.eps_bar[2] *= gamma;
+    }
     C.ticks = C.ticks + 1;
   }
 }
@@ -1633,7 +1750,8 @@ __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list
 // the XCDs from every group would need a device-scope release per group (an
 // L2 write-back each), which costs far more than the kernel boundary.
 template <typename real>
-__global__ __launch_bounds__(128) void k_ctrl(const int* __restrict__ list, const SlotParam* __restrict__ prms,
+__global__ __launch_bounds__(128) void k_ctrl(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                             const SlotParam* __restrict__ prms,
                                              SlotCtl* __restrict__ ctls, const double* __restrict__ prow,
                                              const double* __restrict__ pcol, const double* __restrict__ pinv,
                                              double* __restrict__ prof, SlotSeq* __restrict__ seqs,
@@ -1676,7 +1794,7 @@ __global__ __launch_bounds__(128) void k_ctrl(const int* __restrict__ list, cons
   }
   const int s = list[blockIdx.x];
   if (s < 0) return;
-  ctrl_slot<real>(s, prms, ctls, prow, pcol, pinv, prof, seqs, recs, nx, ny, ngr, ngc);
+  ctrl_slot<real>(s, ptrs, prms, ctls, prow, pcol, pinv, prof, seqs, recs, nx, ny, ngr, ngc);
 }
 
 // ===========================================================================
@@ -1817,8 +1935,8 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
     hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow,
                        pinv, G.nx, G.ny, G.R, G.ngr, kti);
   }
-  hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(128), 0, st, list, prms, ctls, prow, pcol, pinv, prof, seqs,
-                     recs, G.nx, G.ny, G.ngr, G.ngc, kt, ktsum);
+  hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(128), 0, st, list, ptrs, prms, ctls, prow, pcol, pinv, prof,
+                     seqs, recs, G.nx, G.ny, G.ngr, G.ngc, kt, ktsum);
   return hipGetLastError();
 }
 

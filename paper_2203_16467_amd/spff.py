@@ -22,7 +22,7 @@ OK, WARN_NOT_CONVERGED, E_INVALID, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY = 0, 1
 AT1, AT2 = 1, 2
 SPLIT_NONE, SPLIT_SPECTRAL, SPLIT_VOLDEV = 0, 1, 2
 CONTACT_SAME = -1
-EVOL_AM, EVOL_TIME = 0, 1
+EVOL_AM, EVOL_TIME, EVOL_NEAR_EQ = 0, 1, 2
 IRR_CRACK_SET, IRR_DAMAGE = 0, 1
 FP32, FP64 = 0, 1
 OP_PROJECT, OP_NEG_LAPLACIAN = 0, 1
@@ -58,6 +58,7 @@ class Config(ctypes.Structure):
         ("contact", ctypes.c_int32), ("evolution", ctypes.c_int32),
         ("eta", ctypes.c_double), ("dt_max", ctypes.c_double), ("dt_min", ctypes.c_double),
         ("dphi_max", ctypes.c_double), ("dphi_min", ctypes.c_double),
+        ("fphi_max", ctypes.c_double), ("drive_threshold", ctypes.c_double), ("deps_max", ctypes.c_double),
     ]
 
 
@@ -70,11 +71,14 @@ class StepStats(ctypes.Structure):
         ("C_bar", ctypes.c_double), ("phi_max", ctypes.c_double), ("phi_mean", ctypes.c_double),
         ("crack_px", ctypes.c_int64), ("wall_ms", ctypes.c_double),
         ("dt", ctypes.c_double), ("halvings", ctypes.c_int32), ("advance", ctypes.c_int32),
+        ("gamma", ctypes.c_double), ("fphi_max", ctypes.c_double), ("eps_bar", ctypes.c_double * 3),
+        ("ne_flag", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def to_dict(self):
         out = {name: getattr(self, name) for name, _ in self._fields_}
         out["sigma_bar"] = list(self.sigma_bar)
+        out["eps_bar"] = list(self.eps_bar)
         return out
 
 

@@ -67,7 +67,7 @@ def test_invalid_config_rejected(field, value):
     assert spff.last_error()
 
 
-@pytest.mark.parametrize("field,value", [("evolution", 2), ("evolution", -1), ("eta", -1.0), ("dt_min", 0.0),
+@pytest.mark.parametrize("field,value", [("evolution", 3), ("evolution", -1), ("eta", -1.0), ("dt_min", 0.0),
                                          ("dt_max", 1e-4), ("dphi_max", 0.0), ("dphi_min", -1.0)])
 def test_invalid_time_discretized_config_rejected(field, value):
     """Algorithm 3's parameters are checked only when it is selected."""
@@ -77,6 +77,20 @@ def test_invalid_time_discretized_config_rejected(field, value):
     out = ctypes.c_size_t(0)
     assert spff.lib().spff_workspace_bytes(ctypes.byref(cfg), 1, ctypes.byref(out)) == spff.E_INVALID
     if field not in ("evolution",):
+        cfg.evolution = spff.EVOL_AM
+        assert spff.workspace_bytes(cfg, 1) > 0
+
+
+@pytest.mark.parametrize("field,value", [("fphi_max", 0.0), ("fphi_max", float("inf")), ("drive_threshold", -1.0),
+                                         ("deps_max", -1e-3), ("dt_max", 0.0), ("eta", -1.0), ("dphi_min", -1.0)])
+def test_invalid_near_equilibrium_config_rejected(field, value):
+    """Algorithm 4's parameters are checked only when it is selected."""
+    cfg = spff.default_config(evolution=spff.EVOL_NEAR_EQ)
+    assert spff.workspace_bytes(cfg, 1) > 0
+    setattr(cfg, field, value)
+    out = ctypes.c_size_t(0)
+    assert spff.lib().spff_workspace_bytes(ctypes.byref(cfg), 1, ctypes.byref(out)) == spff.E_INVALID
+    if field not in ("dt_max", "eta", "dphi_min"):
         cfg.evolution = spff.EVOL_AM
         assert spff.workspace_bytes(cfg, 1) > 0
 

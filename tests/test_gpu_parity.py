@@ -461,3 +461,76 @@ def test_time_steps_parity_through_halvings(precision):
         dt, seen = g["dt"], seen + g["halvings"]
     assert seen >= 3
     p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("at", [1, 2])
+def test_near_equilibrium_homogeneous_closed_form(precision, at):
+    """Algorithm 4 on a homogeneous material from phi = 0 (Sec. 3.2.2):
+    -F_phi = 2 psi - c w'(0) everywhere, so g^2 = (fphi_max + c w'(0)) /
+    (2 psi) with c = G_c/(c_w l), psi = (lam + 2 mu) e^2 / 2; the returned
+    eps_bar is g e and (eta = 0) phi the homogeneous minimiser at the scaled
+    strain, fphi_max / (fphi_max + c) for AT1 and fphi_max / (fphi_max + 2 c)
+    for AT2."""
+    n, e, ell, fmax, nu = 64, 0.5, 2.0, 0.05, 0.2
+    lam = nu / ((1 + nu) * (1 - 2 * nu))
+    mu = 1.0 / (2 * (1 + nu))
+    psi = 0.5 * (lam + 2 * mu) * e * e
+    c = 1.0 / ((8.0 / 3.0 if at == 1 else 2.0) * ell)
+    dw0 = 1.0 if at == 1 else 0.0
+    cfg = cfg_for(n, precision=precision, at=at, ell=ell, evolution=spff.EVOL_NEAR_EQ, fphi_max=fmax,
+                  drive_threshold=0.0, deps_max=1e-3, eta=0.0)
+    p = spff.Problem(torch_E(np.ones((n, n)), precision), cfg)
+    _, stats = p.load_step((0.0, e, 0.0))
+    s = stats[0]
+    g = np.sqrt((fmax + c * dw0) / (2 * psi))
+    rel = 1e-12 if precision == "fp64" else 1e-5
+    assert s["gamma"] == pytest.approx(g, rel=rel) and s["ne_flag"] == 1 and s["advance"] == 0
+    assert s["fphi_max"] == pytest.approx(2 * psi - c * dw0, rel=rel)
+    assert s["eps_bar"][1] == pytest.approx(g * e, rel=rel) and s["eps_bar"][0] == 0.0
+    f = gpu_fields(p)
+    want = fmax / (fmax + c) if at == 1 else fmax / (fmax + 2 * c)
+    assert np.abs(f["phi"] - want).max() <= (1e-9 if precision == "fp64" else 2e-5)
+    assert np.abs(f["strain"][1] - g * e).max() <= (1e-12 if precision == "fp64" else 1e-6)
+    p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_near_equilibrium_steps_parity(precision):
+    """Algorithm 4 on the heterogeneous CPU-sized input (AT1, spectral,
+    crack set, (-F_phi)_max = 0.7 G_c/l, trigger threshold 1 G_c/l as in the
+    paper's runs): the load advances by its increment while phi does not
+    move; the steps from nucleation on are compared with the oracle from the
+    GPU state and trigger flag, through the first two strain scalings."""
+    E, ramp = _c1_inputs()
+    deps = np.asarray(ramp[1]) - np.asarray(ramp[0])
+    ne = dict(evolution=spff.EVOL_NEAR_EQ, fphi_max=0.35, drive_threshold=0.5, deps_max=float(np.abs(deps).max()),
+              eta=0.0, dt_max=1.0, dphi_min=1e-3)
+    cfg = cfg_for(64, precision=precision, **ne)
+    p = spff.Problem(torch_E(E, precision), cfg)
+    o = oracle_for(E, cfg)
+    eb = np.asarray(ramp[0], dtype=np.float64)
+    flag, scaled = False, 0
+    for k in range(19):
+        check = k == 12 or k >= 16
+        if check:
+            set_oracle_from_gpu(o, p)
+            o.ne_flag = flag
+        _, stats = p.load_step(eb)
+        g = stats[0]
+        if check:
+            ost = o.near_equilibrium_step(eb, deps, 0.35, 0.5, eta=0.0, dt_max=1.0, dphi_min=1e-3)
+            print(k, g["gamma"], ost["gamma"], g["fphi_max"], ost["fphi_max"], g["dphi_l1"], ost["dphi"])
+            assert (g["ne_flag"], g["advance"]) == (int(ost["ne_flag"]), int(ost["advance"]))
+            rel = 1e-7 if precision == "fp64" else 1e-4
+            assert g["gamma"] == pytest.approx(ost["gamma"], rel=rel)
+            assert g["fphi_max"] == pytest.approx(ost["fphi_max"], rel=10 * rel, abs=1e-6)
+            np.testing.assert_allclose(g["eps_bar"], ost["eps_bar"], rtol=rel, atol=1e-12)
+            compare(gpu_fields(p), oracle_fields(o), precision, phi_tol=1e-6 if precision == "fp64" else 1e-3)
+            scaled += g["gamma"] < 1.0
+        else:
+            assert g["gamma"] == 1.0
+        flag = bool(g["ne_flag"])
+        eb = np.asarray(g["eps_bar"]) + (deps if g["advance"] else 0.0)
+    assert flag and scaled >= 2
+    p.close()
