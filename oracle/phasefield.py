@@ -142,6 +142,16 @@ def bccg(phi0, lo, hi, op, tol_rel=1e-8, tol_abs=0.0, max_iter=10000):
                  "target": float(target), "stopped": stopped}
 
 
+def optimal_profile(d, at, ell):
+    """Optimal 1-D phase-field profile across a straight crack at distance
+    d from its centre line (Sec. 2.1): AT1 (1 - |d| / (2 l))^2 for
+    |d| <= 2 l, else 0; AT2 exp(-|d| / l)."""
+    d = np.abs(np.asarray(d, dtype=np.float64))
+    if at == 1:
+        return np.where(d <= 2.0 * ell, (1.0 - d / (2.0 * ell)) ** 2, 0.0)
+    return np.exp(-d / ell)
+
+
 def fracture_energy(phi, at, gc, ell):
     """F_f = G_c/(c_w l) [ sum w(phi) + l^2 sum |grad_N phi|^2 ] with unit
     pixel area (Sec. 2.1; the gradient term is the Laplacian quadratic form,

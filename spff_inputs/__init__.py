@@ -11,6 +11,9 @@ Sec. 3.4, whose realisations are not available):
     z  <- (z - mean z) / std z
     E  = max(1 + a z, floor)            rounded to float32
 Realisation i of workload configuration j uses seed = 1000 j + i.
+
+Also: the paper's two-phase ("slit island") microstructure (Sec. 3.4) and
+its initial phase fields for a crack and a small void (Sec. 4.1.1).
 """
 
 import numpy as np
@@ -75,3 +78,38 @@ WORKLOADS = {
     "c3_512x64": dict(n=512, corr_len=16.0, amp=0.2, ell=2.0, steps=200, seed=3000, batch=64),
     "c5_2048": dict(n=2048, corr_len=32.0, amp=0.3, ell=1.0, steps=500, seed=5000),
 }
+
+
+def two_phase(n, l_cut, a, seed, iters=21, ny=None):
+    """Two-phase Young's modulus field of Sec. 3.4, E0 = 1: white noise
+    N(0, 1) (numpy PCG64, ``seed``), low-pass filtered, thresholded to
+    sgn(xi) in {-1, 0, 1}, smoothed by ``iters`` explicit Allen-Cahn steps
+    xi <- xi - 0.1 [(xi^3 - xi) + (4 xi_k - sum of the four periodic
+    neighbours)], and mapped to E = a xi + 1 (bulk phases 1 - a and 1 + a,
+    ratio (1 + a) / (1 - a)).  Readings: the filter keeps the modes with
+    |q| <= 2 pi / l_cut (the text removes wavelengths shorter than l_cut;
+    the printed inequality is reversed); the iteration index runs over
+    n = 0 .. 20, i.e. 21 steps.  Returns float32, shape (ny or n, n)."""
+    ny = n if ny is None else ny
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((ny, n))
+    qy = np.fft.fftfreq(ny)[:, None] * 2.0 * np.pi
+    qx = np.fft.fftfreq(n)[None, :] * 2.0 * np.pi
+    keep = np.sqrt(qx ** 2 + qy ** 2) <= 2.0 * np.pi / l_cut
+    xi = np.sign(np.fft.ifft2(np.fft.fft2(w) * keep).real)
+    for _ in range(iters):
+        nb = np.roll(xi, 1, 0) + np.roll(xi, -1, 0) + np.roll(xi, 1, 1) + np.roll(xi, -1, 1)
+        xi = xi - 0.1 * ((xi ** 3 - xi) + (4.0 * xi - nb))
+    return (a * xi + 1.0).astype(np.float32)
+
+
+def round_void(ny, nx, ell, dx=1.0):
+    """Initial phase field of a small void (Sec. 4.1.1): the crack profile
+    with r = (x, y) on a grid centred at the origin, phi = (1 - |r| / (2 l))^2
+    where |r| <= 2 l, 0 elsewhere.  Returns float32."""
+    y = (np.arange(ny) - ny // 2)[:, None] * dx
+    x = (np.arange(nx) - nx // 2)[None, :] * dx
+    r = np.sqrt(x ** 2 + y ** 2)
+    phi = np.where(r <= 2.0 * ell, (1.0 - r / (2.0 * ell)) ** 2, 0.0)
+    return phi.astype(np.float32)
+

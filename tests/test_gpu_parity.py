@@ -188,17 +188,10 @@ def test_initial_crack_solve(precision):
 MODELS = [("voldev", None), ("spectral", "none"), ("spectral", "voldev"), ("none", "spectral")]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("split,contact", MODELS)
-def test_model_matrix_step_parity(precision, split, contact):
-    """Sec. 2.1 / 4.2.1 energy models beyond the variational spectral one:
-    the volumetric-deviatoric split and non-variational pairings of a
-    crack driving force with another model's stress.  Step-wise parity on
-    the CPU-sized input: an elastic step (mechanics only), then AT1 through
-    the first nucleating step (alternating minimisation capped at 3) from
-    the same state on both sides."""
-    E, ramp = _c1_inputs()
-    cfg = cfg_for(64, precision=precision, split=split, contact=contact, max_am=3)
+def _elastic_and_nucleation_parity(E, ramp, cfg, precision):
+    """Step-wise parity on one input: an elastic step (mechanics only), then
+    the first nucleating step redone from the GPU state before it on both
+    sides (alternating minimisation capped at 3)."""
     p = spff.Problem(torch_E(E, precision), cfg)
     o = oracle_for(E, cfg, max_am=3)
     st, stats = p.load_step(ramp[5])
@@ -206,26 +199,50 @@ def test_model_matrix_step_parity(precision, split, contact):
     compare(gpu_fields(p), oracle_fields(o), precision)
     assert stats[0]["F_e"] == pytest.approx(ost["F_e"], rel=tol_fields(precision))
     k = None
-    for s in range(6, 20):
+    for s in range(6, len(ramp)):
         _, stt = p.load_step(ramp[s])
         if stt[0]["phi_max"] > 0.0:
             k = s
             break
     assert k is not None
-    # redo step k from the state before it on both sides
     q = spff.Problem(torch_E(E, precision), cfg)
     q.run_sequence(ramp[:k])
     set_oracle_from_gpu(o, q)
     _, stats = q.load_step(ramp[k])
     ost = o.load_step(ramp[k])
     cmp = compare(gpu_fields(q), oracle_fields(o), precision, phi_tol=1e-6 if precision == "fp64" else 1e-3)
-    print(split, contact, k, cmp, stats[0]["am_iters"], ost["am"])
+    print(k, cmp, stats[0]["am_iters"], ost["am"])
     assert stats[0]["am_iters"] == ost["am"]
     tot = ost["F_e"] + ost["F_f"]
     assert abs(stats[0]["F_e"] - ost["F_e"]) <= 10 * tol_fields(precision) * tot
     assert abs(stats[0]["F_f"] - ost["F_f"]) <= 10 * tol_fields(precision) * tot
     p.close()
     q.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("split,contact", MODELS)
+def test_model_matrix_step_parity(precision, split, contact):
+    """Sec. 2.1 / 4.2.1 energy models beyond the variational spectral one:
+    the volumetric-deviatoric split and non-variational pairings of a
+    crack driving force with another model's stress.  Step-wise parity on
+    the CPU-sized input, AT1: an elastic step, then the first nucleating
+    step from the same state on both sides."""
+    E, ramp = _c1_inputs()
+    cfg = cfg_for(64, precision=precision, split=split, contact=contact, max_am=3)
+    _elastic_and_nucleation_parity(E, ramp, cfg, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_two_phase_production_model_parity(precision):
+    """The paper's two-phase microstructure (Sec. 3.4: modulus ratio 15,
+    a = 0.875, L_cut = 6 l) with its production model (Sec. 4.1: AT1,
+    damage irreversibility, spectral driving force, stress-free isotropic
+    contact): step-wise parity at an elastic and the first nucleating step."""
+    E = si.two_phase(64, 12.0, 0.875, seed=4000)
+    ramp = si.uniaxial_ramp(30, 0.2, 2.0)
+    cfg = cfg_for(64, precision=precision, split="spectral", contact="none", irr="damage", max_am=3)
+    _elastic_and_nucleation_parity(E, ramp, cfg, precision)
 
 
 @pytest.mark.parametrize("split,contact", MODELS)

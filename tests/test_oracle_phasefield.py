@@ -39,8 +39,7 @@ def line_crack(at, nx, ell, ny=4):
     lo = pf.constraint_field(phi_ref, "crack_set")
     op = pf.Operator(np.zeros((ny, nx)), at, 1.0, ell)
     phi, info = pf.bccg(phi_ref, lo, np.ones_like(lo), op, 1e-11, max_iter=20000)
-    x = np.abs(np.arange(nx) - nx // 2)
-    ana = np.where(x <= 2 * ell, (1 - x / (2 * ell)) ** 2, 0.0) if at == 1 else np.exp(-x / ell)
+    ana = pf.optimal_profile(np.arange(nx) - nx // 2, at, ell)
     err = np.abs(phi[0] - ana).sum() / ana.sum()
     return phi, err, pf.fracture_energy(phi, at, 1.0, ell) / ny
 
