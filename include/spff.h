@@ -227,6 +227,19 @@ spff_status spff_load_step_batch(spff_problem* p, const double* eps_bar, spff_st
  * worst status over all steps; blocks until every sequence is done. */
 spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps_bar, spff_step_stats* stats);
 
+/* Time-discretized or near-equilibrium evolution (Sec. 3.2.2, Algorithms 3
+ * and 4) driven on the device: problem b runs nsteps iterations; iteration
+ * j runs at eps_bar_j = eps_bar_{j-1} + advance_{j-1} deps[b][j], where
+ * eps_bar_{j-1} is the previous iteration's final macroscopic strain (scaled
+ * by the near-equilibrium rescaling) and advance_{j-1} its advance flag
+ * (the problem's last step before this call; 0 strain and advance = 1 for a
+ * fresh or reset problem).  deps: host, double[nbatch][nsteps][3], the load
+ * increment of each iteration (constant Delta eps_bar in the paper).
+ * stats: host spff_step_stats[nbatch][nsteps] or NULL.  Errors:
+ * SPFF_E_INVALID if cfg.evolution is SPFF_EVOL_AM (use spff_run_sequence)
+ * or an increment is not finite; otherwise as spff_run_sequence. */
+spff_status spff_run_evolution(spff_problem* p, int32_t nsteps, const double* deps, spff_step_stats* stats);
+
 /* spff_load_step_batch for a problem created with nbatch = 1. */
 spff_status spff_load_step(spff_problem* p, const double eps_bar[3], spff_step_stats* stats);
 

@@ -337,6 +337,7 @@ struct spff_problem {
   SlotCtl* host_ctl;  // pinned mirror
   std::vector<SlotParam> prm;
   std::vector<double> last_eps_bar;
+  std::vector<int> last_advance;  // advance flag of each problem's last step (1 before the first)
   bool scratch_only = false;
   std::vector<SlotPtr<double>> host_ptrs;  // layout-identical for float and double
   // profiling
@@ -783,6 +784,7 @@ spff_status engine_create(const spff_config* cfg, int32_t nbatch, const void* E_
   p->host_ctl = nullptr;
   p->prm.assign(nbatch, make_param(cfg));
   p->last_eps_bar.assign(3 * (size_t)nbatch, 0.0);
+  p->last_advance.assign((size_t)nbatch, 1);
   auto cleanup = [&](spff_status s) {
     spff_destroy_problem(p);
     return s;
@@ -830,7 +832,25 @@ spff_status spff_create_problem(const spff_config* cfg, const void* E_dev, const
   return spff_create_batch(cfg, 1, E_dev, phi_init_dev, workspace, workspace_bytes, stream, out);
 }
 
+static spff_status run_queue(spff_problem* p, int32_t nsteps, const double* eps_bar, spff_step_stats* stats,
+                             bool incr);
+
 spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps_bar, spff_step_stats* stats) {
+  return run_queue(p, nsteps, eps_bar, stats, false);
+}
+
+spff_status spff_run_evolution(spff_problem* p, int32_t nsteps, const double* deps, spff_step_stats* stats) {
+  if (p && p->cfg.evolution == SPFF_EVOL_AM)
+    return fail(SPFF_E_INVALID, "spff_run_evolution needs SPFF_EVOL_TIME or SPFF_EVOL_NEAR_EQ; use spff_run_sequence");
+  return run_queue(p, nsteps, deps, stats, true);
+}
+
+// Device step queues: per problem, steps at the given macroscopic strains
+// (incr = false) or, for the time-discretized / near-equilibrium evolution,
+// steps that continue from the previous step's final strain plus the given
+// increment when that step advanced the load (incr = true).
+static spff_status run_queue(spff_problem* p, int32_t nsteps, const double* eps_bar, spff_step_stats* stats,
+                             bool incr) {
   if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
   if (nsteps < 1) return fail(SPFF_E_INVALID, "nsteps must be >= 1");
   if (!eps_bar) return fail(SPFF_E_INVALID, "eps_bar is NULL");
@@ -854,13 +874,17 @@ spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps
     SlotSeq& h = q[0];
     h.len = len;
     h.pos = 0;
+    h.incr = incr ? 1 : 0;
     for (int k = 0; k < len; ++k)
       for (int c = 0; c < 3; ++c) h.eps_bar[k][c] = eps_bar[3 * ((size_t)s * nsteps + next[s] + k) + c];
     HIP_TRY(hipMemcpyAsync(p->d_seq() + s, &h, sizeof(SlotSeq), hipMemcpyHostToDevice, p->stream));
     // the staging struct is reused for the next slot: wait for this copy
     HIP_TRY(hipStreamSynchronize(p->stream));
     clen[s] = len;
-    start_step(p, s, h.eps_bar[0]);
+    double eb[3];
+    for (int c = 0; c < 3; ++c)
+      eb[c] = incr ? p->last_eps_bar[3 * s + c] + (p->last_advance[s] ? h.eps_bar[0][c] : 0.0) : h.eps_bar[0][c];
+    start_step(p, s, eb);
     return SPFF_OK;
   };
   for (int s = 0; s < S; ++s) {
@@ -924,6 +948,7 @@ spff_status spff_run_sequence(spff_problem* p, int32_t nsteps, const double* eps
         const double ms = (double)(r.t_end - r.t_start) / p->clock_khz;
         if (stats) fill_stats(p, c, stats[(size_t)s * nsteps + next[s] + j], ms);
         for (int m = 0; m < 3; ++m) p->last_eps_bar[3 * s + m] = r.eps_bar[m];
+        p->last_advance[s] = r.advance;
       }
       if (done == 0 && p->host_ctl[s].status < 0) {
         // failed before its record was written
@@ -1030,6 +1055,7 @@ spff_status spff_set_state(spff_problem* p, const void* src_dev, const double* e
   }
   if (eps_bar_host) {
     std::copy(eps_bar_host, eps_bar_host + 3 * p->S, p->last_eps_bar.begin());
+  std::fill(p->last_advance.begin(), p->last_advance.end(), 1);
     for (int s = 0; s < p->S; ++s)
       for (int k = 0; k < 3; ++k) p->host_ctl[s].eps_bar[k] = eps_bar_host[3 * s + k];
     HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * p->S, hipMemcpyHostToDevice, p->stream));

@@ -129,7 +129,8 @@ constexpr int SEQ_MAX = 256;
 
 struct SlotSeq {
   int32_t len, pos;
-  int32_t pad[2];
+  int32_t incr;  // 1: eps_bar[] are load increments, applied after steps that advance
+  int32_t pad;
   double eps_bar[SEQ_MAX][3];
 };
 

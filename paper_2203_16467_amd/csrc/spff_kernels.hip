@@ -1589,9 +1589,18 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
   if (restart) {
     // fresh control block for the next load step of the queue
     const SlotSeq& q = seqs[s];
-    C.eps_bar[0] = q.eps_bar[q.pos][0];
-    C.eps_bar[1] = q.eps_bar[q.pos][1];
-    C.eps_bar[2] = q.eps_bar[q.pos][2];
+    if (q.incr) {
+      // evolution queue: the next step continues from this step's final
+      // macroscopic strain, plus the increment if the algorithm advances
+      const double a = advance ? 1.0 : 0.0;
+      C.eps_bar[0] += a * q.eps_bar[q.pos][0];
+      C.eps_bar[1] += a * q.eps_bar[q.pos][1];
+      C.eps_bar[2] += a * q.eps_bar[q.pos][2];
+    } else {
+      C.eps_bar[0] = q.eps_bar[q.pos][0];
+      C.eps_bar[1] = q.eps_bar[q.pos][1];
+      C.eps_bar[2] = q.eps_bar[q.pos][2];
+    }
     C.phase = PH_M_RES;
     C.flags = FL_FIRST_OF_STEP | (P.evolution == 2 ? FL_NE_CHECK : 0);
     C.am = C.newton = C.cg = C.bccg = C.cg_newton = C.pf_it = C.newton_solve = 0;

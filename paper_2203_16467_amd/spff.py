@@ -127,6 +127,8 @@ _SIGS = {
     "spff_load_step": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(StepStats)]),
     "spff_run_sequence": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(StepStats)]),
+    "spff_run_evolution": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(StepStats)]),
     "spff_get_fields": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "spff_state_bytes": (ctypes.c_size_t, [_P]),
     "spff_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
@@ -309,6 +311,26 @@ class Problem:
         K = eb.shape[1]
         stats = (StepStats * (self.B * K))()
         st = lib().spff_run_sequence(self.handle, K, eb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), stats)
+        _check(st)
+        return st, [[stats[b * K + k].to_dict() for k in range(K)] for b in range(self.B)]
+
+    def run_evolution(self, deps, nsteps=None):
+        """spff_run_evolution (Algorithm 3 or 4 on the device).  deps: (3,)
+        constant increment (then nsteps is required), (K, 3) applied to
+        every problem, or (B, K, 3).  Returns (status, stats)."""
+        d = np.asarray(deps, dtype=np.float64)
+        if d.ndim == 1:
+            if nsteps is None:
+                raise ValueError("nsteps is required with a constant increment")
+            d = np.broadcast_to(d, (int(nsteps), 3))
+        if d.ndim == 2:
+            d = np.broadcast_to(d, (self.B,) + d.shape)
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        if d.ndim != 3 or d.shape[0] != self.B or d.shape[2] != 3:
+            raise ValueError("deps must have shape (3,), (K, 3) or (B, K, 3)")
+        K = d.shape[1]
+        stats = (StepStats * (self.B * K))()
+        st = lib().spff_run_evolution(self.handle, K, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), stats)
         _check(st)
         return st, [[stats[b * K + k].to_dict() for k in range(K)] for b in range(self.B)]
 

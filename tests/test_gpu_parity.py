@@ -551,3 +551,57 @@ def test_near_equilibrium_steps_parity(precision):
         eb = np.asarray(g["eps_bar"]) + (deps if g["advance"] else 0.0)
     assert flag and scaled >= 2
     p.close()
+
+
+@pytest.mark.parametrize("mode", ["near_eq", "time"])
+def test_run_evolution_matches_host_driven_iterations(mode):
+    """Algorithms 3 and 4 driven on the device (spff_run_evolution: each
+    iteration continues from the previous one's final macroscopic strain,
+    plus the load increment when it advanced) over a batch of two
+    microstructures: every iteration equals the same problem stepped alone
+    by the host loop of the algorithm (bit for bit; iteration counts, dt,
+    gamma and the strain path agree)."""
+    E, ramp = _c1_inputs()
+    Es = np.stack([E, si.young_modulus(64, 4.0, 0.2, 1002)])
+    deps = np.asarray(ramp[1]) - np.asarray(ramp[0])
+    if mode == "near_eq":
+        extra = dict(evolution=spff.EVOL_NEAR_EQ, fphi_max=0.35, drive_threshold=0.5,
+                     deps_max=float(np.abs(deps).max()), dphi_min=1e-3)
+    else:
+        extra = dict(evolution=spff.EVOL_TIME, eta=0.5, dt_max=1.0, dt_min=1e-3, dphi_max=20.0, dphi_min=1e-3)
+    K = 20
+    cfg = cfg_for(64, use_graph=1, ticks_per_sync=8, **extra)
+    pb = spff.Problem(torch_E(Es, "fp32"), cfg)
+    st, stats = pb.run_evolution(deps, nsteps=K)
+    assert st >= 0
+    fb = [gpu_fields(pb, i) for i in range(2)]
+    for i in range(2):
+        ps = spff.Problem(torch_E(Es[i], "fp32"), cfg_for(64, **extra))
+        eb, adv = np.zeros(3), True
+        for k in range(K):
+            eb = eb + (deps if adv else 0.0)
+            _, s1 = ps.load_step(eb)
+            g, r = s1[0], stats[i][k]
+            for key in ("cg_iters", "bccg_iters", "advance", "halvings", "ne_flag"):
+                assert g[key] == r[key], (i, k, key)
+            assert g["dt"] == r["dt"] and g["gamma"] == r["gamma"]
+            assert g["eps_bar"] == r["eps_bar"], (i, k)
+            eb, adv = np.asarray(g["eps_bar"]), bool(g["advance"])
+        fs = gpu_fields(ps)
+        for key in fb[i]:
+            assert np.array_equal(fb[i][key], fs[key]), (i, key)
+        ps.close()
+    # the device queue continues where it stopped
+    st, more = pb.run_evolution(deps, nsteps=2)
+    last = stats[0][-1]
+    first = more[0][0]
+    want = np.asarray(last["eps_bar"]) + (deps if last["advance"] else 0.0)
+    if first["gamma"] == 1.0:
+        np.testing.assert_allclose(first["eps_bar"], want, rtol=0, atol=0)
+    pb.close()
+    with pytest.raises(spff.SpffError):
+        q = spff.Problem(torch_E(E, "fp32"), cfg_for(64))
+        try:
+            q.run_evolution(deps, nsteps=2)
+        finally:
+            q.close()
