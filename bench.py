@@ -201,6 +201,93 @@ def plain_leg(args):
             "seconds": tot_s, "runs": runs}
 
 
+def variants_leg(args):
+    """The model and evolution variants beyond the headline configuration,
+    each on a batch of 16 realizations of 256^2 (E = max(1+0.2z, 0.5), corr
+    8 px, seeds 6000..), l = 2 px, 100-step uniaxial ramp to 1.5 eps_M,
+    captured graphs, autotuned-plan-free built-in plans:
+      voldev          alternating minimisation, vol.-dev. split (variational)
+      production      alternating minimisation, spectral driving force,
+                      stress-free isotropic contact, damage irreversibility
+      time_alg3       Algorithm 3 (eta = 0.5, dt in [1e-3, 1], dphi_max 20 px,
+                      dphi_min 1e-3), device-driven iterations
+      near_eq_alg4    Algorithm 4 ((-F_phi)_max = 0.7 G_c/l, threshold
+                      1 G_c/l), device-driven iterations
+    Steps (iterations) 0..1 untimed (graph capture); timed with the kernel
+    timers in chunks of 8: load steps 2..49 (through crack nucleation,
+    before complete separation), iterations 2..119 for Algorithms 3 and 4
+    (whose iterations do not advance the load while phi evolves): grid-point
+    Krylov iterations per second and the achieved algorithmic bandwidth of
+    the dominant kernel."""
+    import numpy as np
+    import torch
+
+    import spff_inputs as si
+    from paper_2203_16467_amd import spff
+
+    n, B = 256, 16
+    E = np.stack([si.young_modulus(n, 8.0, 0.2, 6000 + i) for i in range(B)])
+    ramp = si.uniaxial_ramp(100, 0.2, 2.0)
+    deps = ramp[0].copy()
+    ell = 2.0
+    variants = {
+        "voldev": (dict(split=spff.SPLIT_VOLDEV), "seq"),
+        "production": (dict(split=spff.SPLIT_SPECTRAL, contact=spff.SPLIT_NONE,
+                            irreversibility=spff.IRR_DAMAGE), "seq"),
+        "time_alg3": (dict(evolution=spff.EVOL_TIME, eta=0.5, dt_max=1.0, dt_min=1e-3, dphi_max=20.0,
+                           dphi_min=1e-3), "evo"),
+        "near_eq_alg4": (dict(evolution=spff.EVOL_NEAR_EQ, fphi_max=0.7 / ell, drive_threshold=1.0 / ell,
+                              deps_max=float(np.abs(deps).max()), dphi_min=1e-3), "evo"),
+    }
+    out = {}
+    K, K_EVO, CH = 50, 120, 8
+    for name, (kw, kind) in variants.items():
+        cfg = spff.default_config(nx=n, ny=n, ell=ell, use_graph=1, ticks_per_sync=16, **kw)
+        p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
+        # untimed: the first two steps (captures the full-batch graphs)
+        if kind == "seq":
+            p.run_sequence(ramp[:2])
+        else:
+            p.run_evolution(deps, nsteps=2)
+        p.profile_enable(True)
+        stats = [[] for _ in range(B)]
+        dt, st = 0.0, 0
+        Kv = K if kind == "seq" else K_EVO
+        for c0 in range(2, Kv, CH):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if kind == "seq":
+                st_c, s_c = p.run_sequence(ramp[c0:min(c0 + CH, Kv)])
+            else:
+                st_c, s_c = p.run_evolution(deps, nsteps=min(CH, Kv - c0))
+            torch.cuda.synchronize()
+            dt += time.perf_counter() - t0
+            st = min(st, st_c) if st_c < 0 or st < 0 else max(st, st_c)
+            for b in range(B):
+                stats[b] += s_c[b]
+            log(f"[bench] variant {name}: steps {c0}..{min(c0 + CH, Kv) - 1} done ({dt:.2f}s)")
+        pr = p.profile_read()
+        p.close()
+        cg, pf = iters(stats)
+        kt = {k: 0.5 * (pr["kernel_ms"][k] + pr["kernel_span_ms"][k]) for k in KERNELS}
+        dom = max(KERNELS, key=lambda k: kt[k])
+        gbs = pr["alg_bytes"][dom] / (kt[dom] * 1e-3) / 1e9 if kt[dom] > 0 else 0.0
+        res = {"seconds": dt, "value": (cg + pf) * n * n / dt, "unit": "grid-pt-iters/s",
+               "cg_iters": cg, "bccg_iters": pf, "status": st,
+               "cracked": sum(1 for row in stats if row[-1]["crack_px"] > 0),
+               "dominant_kernel": dom, "achieved_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+        if kind == "evo":
+            res["advanced"] = sum(s["advance"] for row in stats for s in row)
+            res["final_eps_yy_mean"] = float(np.mean([row[-1]["eps_bar"][1] for row in stats]))
+        out[name] = res
+        log(f"[bench] variant {name}: {res['value']:.3e} grid-pt-iters/s in {res['seconds']:.2f}s, "
+            f"{res['dominant_kernel']} {res['achieved_GBs']:.0f} GB/s")
+    return {"workload": "16 realizations of 256x256 (E = max(1+0.2z,0.5), corr 8 px, seeds 6000..), l = 2 px, "
+                        "alternating minimisation: load steps 2..49 of a 100-step uniaxial ramp to 1.5 eps_M "
+                        "(crack nucleation from about step 42); Algorithms 3, 4: iterations 2..119 with the "
+                        "ramp's increment (eps_M / 66.7); timed in chunks of 8", "runs": out}
+
+
 def serving_leg(args):
     """Serving workload: resident microstructures with grid sizes drawn
     uniformly from {128, 256, 512, 1024}^2, AT1/AT2 half and half, requests =
@@ -337,6 +424,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-serving", dest="serving", action="store_false")
+    ap.add_argument("--no-variants", dest="variants", action="store_false")
     ap.add_argument("--serve-problems", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
@@ -412,6 +500,8 @@ def main():
         out["vs_plain"] = value / pl["value"]
     if args.serving:
         out["serving"] = serving_leg(args)
+    if args.variants:
+        out["variants"] = variants_leg(args)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_leg(res, args.cpu_budget)
     print(json.dumps(out), flush=True)
