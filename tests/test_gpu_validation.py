@@ -12,11 +12,10 @@ near the ideal 100 G_c l (the paper's void run ends at 103.0).  Measured
 here (FP32): crack IC stiffness 0.60, peak stress 0.099 sigma_M (paper
 0.16), final F_f 109.2 G_c l; void IC stiffness 1.00, peak 0.757 sigma_M,
 final F_f 109.1 G_c l.  The final profiles are about 20% (L1) from the
-analytical one, against 5.6% / 6.6% in the paper: the crack centre is two
-pixel rows wide after the last (separating) step, where the mechanics
-problem loses its stiffness across the crack; the relaxed initial crack
-itself is 5.4% from the analytical profile.  These bounds are loose on
-purpose and the differences are open."""
+analytical one, against 5.6% / 6.6% in the paper: at the end the crack
+centre is two pixel rows wide along the whole crack (FP64 the same); the
+relaxed initial crack itself is 5.4% from the analytical profile.  These
+bounds are loose on purpose and the differences are open."""
 
 import numpy as np
 import pytest
