@@ -657,21 +657,24 @@ void fill_stats(const spff_problem* p, const SlotCtl& c, spff_step_stats& o, dou
   o.wall_ms = wall_ms;
 }
 
-void start_step(spff_problem* p, int s, const double* eb) {
-  // the time step of the time-discretized evolution and the trigger flag
-  // of the near-equilibrium evolution carry over
-  const double dt = p->host_ctl[s].dt > 0.0 ? p->host_ctl[s].dt : p->cfg.dt_max;
+// Start a load step of slot s under configuration cfg (the handle's, or a
+// served problem's).  The time step of the time-discretized evolution and
+// the trigger flag of the near-equilibrium evolution carry over from the
+// slot's control block (the server stores them per problem and restores
+// them before each request).
+void start_step(spff_problem* p, int s, const double* eb, const spff_config& cfg) {
+  const double dt = p->host_ctl[s].dt > 0.0 ? p->host_ctl[s].dt : cfg.dt_max;
   const int ne_flag = p->host_ctl[s].ne_flag;
   reset_ctl(p, s);
   SlotCtl& c = p->host_ctl[s];
   for (int k = 0; k < 3; ++k) c.eps_bar[k] = eb[k];
-  const int evol = p->cfg.evolution;
+  const int evol = cfg.evolution;
   c.phase = PH_M_RES;
   c.flags = FL_FIRST_OF_STEP | (evol == SPFF_EVOL_NEAR_EQ ? FL_NE_CHECK : 0);
   c.dt = dt;
-  c.eta_dt = evol == SPFF_EVOL_TIME      ? p->cfg.eta / dt
-             : evol == SPFF_EVOL_NEAR_EQ ? p->cfg.eta / p->cfg.dt_max
-                                         : p->cfg.eta_over_dt;
+  c.eta_dt = evol == SPFF_EVOL_TIME      ? cfg.eta / dt
+             : evol == SPFF_EVOL_NEAR_EQ ? cfg.eta / cfg.dt_max
+                                         : cfg.eta_over_dt;
   c.gamma = 1.0;
   c.ne_flag = ne_flag;
 }
@@ -884,7 +887,7 @@ static spff_status run_queue(spff_problem* p, int32_t nsteps, const double* eps_
     double eb[3];
     for (int c = 0; c < 3; ++c)
       eb[c] = incr ? p->last_eps_bar[3 * s + c] + (p->last_advance[s] ? h.eps_bar[0][c] : 0.0) : h.eps_bar[0][c];
-    start_step(p, s, eb);
+    start_step(p, s, eb, p->cfg);
     return SPFF_OK;
   };
   for (int s = 0; s < S; ++s) {
@@ -1225,6 +1228,8 @@ struct SrvProblem {
   bool running = false;
   double t_submit = 0.0;
   uint64_t ticket = 0;
+  double dt = 0.0;  // time-discretized evolution: the problem's dt (0: dt_max)
+  int ne_flag = 0;  // near-equilibrium evolution: the problem's trigger flag
 };
 
 struct SrvClass {
@@ -1318,7 +1323,9 @@ spff_status class_admit(spff_server* sv, SrvClass& C, int s, int id) {
   HIP_TRY(hipMemcpyAsync(static_cast<unsigned char*>(e->d_ptr()) + s * sizeof(SlotPtr<double>), &ptr,
                          sizeof(SlotPtr<double>), hipMemcpyHostToDevice, C.stream));
   HIP_TRY(hipMemcpyAsync(e->d_prm() + s, &e->prm[s], sizeof(SlotParam), hipMemcpyHostToDevice, C.stream));
-  start_step(e, s, rq.eb);
+  e->host_ctl[s].dt = P.dt;
+  e->host_ctl[s].ne_flag = P.ne_flag;
+  start_step(e, s, rq.eb, P.cfg);
   return SPFF_OK;
 }
 
@@ -1473,6 +1480,8 @@ spff_status spff_server_progress(spff_server* sv, int32_t max_rounds, int32_t* c
         SrvProblem& P = sv->probs[id];
         spff_step_stats o;
         fill_stats(e, e->host_ctl[s], o, t - P.t_submit);
+        P.dt = e->host_ctl[s].dt;
+        P.ne_flag = e->host_ctl[s].ne_flag;
         sv->done[P.ticket] = o;
         sv->live.erase(P.ticket);
         P.running = false;

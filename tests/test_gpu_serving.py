@@ -126,3 +126,57 @@ def test_poisson_driver_smoke():
     thr, lat2, offered = serving.run_poisson(sv, ramps, 2, rate=0.5 * rate, n_requests=12, seed=1)
     assert len(lat2) == 12 and thr > 0
     sv.close()
+
+
+@pytest.mark.parametrize("mode", ["time", "near_eq"])
+def test_evolution_state_is_kept_per_problem(mode):
+    """Algorithms 3 and 4 carry state between iterations (dt, the trigger
+    flag).  Served problems share slots (the scratch budget holds two slots
+    for four problems), so the server keeps that state per problem: each
+    problem's iterations equal those of the same problem run alone, bit for
+    bit with fixed launch plans, whatever slot served each request."""
+    import torch
+    ramp = si.uniaxial_ramp(20, 0.2, 2.0)
+    deps = ramp[1] - ramp[0]
+    if mode == "time":
+        extra = dict(evolution=spff.EVOL_TIME, eta=0.5, dt_max=1.0, dt_min=1e-3, dphi_max=20.0, dphi_min=1e-3)
+    else:
+        extra = dict(evolution=spff.EVOL_NEAR_EQ, fphi_max=0.35, drive_threshold=0.5,
+                     deps_max=float(np.abs(deps).max()), dphi_min=1e-3)
+    Es = [si.young_modulus(64, 4.0, 0.1, 1000)] + [si.young_modulus(64, 4.0, 0.2, 1001 + i) for i in range(3)]
+    kw = dict(nx=64, ny=64, at=1, **extra, **PLAN)
+    sv = spff.Server(arena_bytes=64 << 20, scratch_budget_bytes=2 * 64 * 64 * 48 * 2, ticks_per_sync=4,
+                     use_graph=1)
+    ids = [sv.register(spff.default_config(**kw), torch.as_tensor(E, device=device())) for E in Es]
+    K = 10
+    eb = {i: np.asarray(ramp[11], dtype=np.float64) for i in ids}
+    hist = {i: [] for i in ids}
+    for k in range(K):
+        tickets = {i: sv.submit(i, eb[i]) for i in ids}
+        while True:
+            _, pending = sv.progress(4)
+            if pending == 0:
+                break
+        for i in ids:
+            s = sv.poll(tickets[i])
+            hist[i].append(s)
+            eb[i] = np.asarray(s["eps_bar"]) + (deps if s["advance"] else 0.0)
+    for i, E in zip(ids, Es):
+        p = spff.Problem(torch.as_tensor(E, device=device()), spff.default_config(**kw))
+        e = np.asarray(ramp[11], dtype=np.float64)
+        for k in range(K):
+            _, st = p.load_step(e)
+            a, b = hist[i][k], st[0]
+            for key in ("cg_iters", "bccg_iters", "advance", "halvings", "ne_flag"):
+                assert a[key] == b[key], (i, k, key)
+            assert a["dt"] == b["dt"] and a["gamma"] == b["gamma"] and a["eps_bar"] == b["eps_bar"], (i, k)
+            e = np.asarray(b["eps_bar"]) + (deps if b["advance"] else 0.0)
+        f = sv.get_fields(i, spff.FIELD_PHI)["phi"].double().cpu().numpy()
+        g = p.get_fields(spff.FIELD_PHI, 0)["phi"].double().cpu().numpy()
+        assert np.array_equal(f, g), i
+        p.close()
+    if mode == "time":
+        assert any(s["halvings"] > 0 for h in hist.values() for s in h)
+    else:
+        assert any(s["gamma"] < 1.0 for h in hist.values() for s in h)
+    sv.close()
