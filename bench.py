@@ -144,7 +144,13 @@ def batched_leg(args):
     if args.warmup > 0:
         p.run_sequence(ramp[s0:args.start])
     log(f"[bench] warmup steps {s0}..{args.start - 1} done")
-    p.profile_enable(args.profile)  # reset the kernel totals for the timed region
+    # the timed region runs without the kernel timers (they cost a few
+    # percent: every work-group stamps its start and end, the controller
+    # folds them); it is then replayed from the same state with the timers
+    # on for the per-kernel figures (deterministic: same iterations, same
+    # launches)
+    snap = p.get_state() if args.profile else None
+    p.profile_enable(False)
     torch.cuda.synchronize()
     ROCTX.push("bench_timed")
     t0 = time.perf_counter()
@@ -152,13 +158,26 @@ def batched_leg(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ROCTX.pop()
-    prof = p.profile_read()
     cg, pf = iters(stats)
+    prof, replay = None, None
+    if args.profile:
+        p.set_state(*snap)
+        del snap
+        p.profile_enable(True)
+        torch.cuda.synchronize()
+        ROCTX.push("bench_profiled")
+        t1 = time.perf_counter()
+        _, stats2 = p.run_sequence(ramp[args.start:args.start + args.steps])
+        torch.cuda.synchronize()
+        replay = {"seconds": time.perf_counter() - t1, "iterations_equal": iters(stats2) == (cg, pf)}
+        ROCTX.pop()
+        prof = p.profile_read()
+        log(f"[bench] profiled replay in {replay['seconds']:.2f}s (same iterations: {replay['iterations_equal']})")
     ncrack = sum(1 for row in stats if row[-1]["crack_px"] > 0)
     log(f"[bench] timed {args.steps} steps in {dt:.2f}s: cg {cg} bccg {pf}, cracked {ncrack}/{B}, status {st}")
     p.close()
     return {"dt": dt, "cg": cg, "pf": pf, "status": st, "prof": prof, "ncrack": ncrack, "E0": E[0],
-            "ramp": ramp, "n": n, "B": B, "tuned": tuned, "steady": steady}
+            "ramp": ramp, "n": n, "B": B, "tuned": tuned, "steady": steady, "replay": replay}
 
 
 def plain_leg(args):
@@ -439,7 +458,7 @@ def main():
     ap.add_argument("--steady-steps", type=int, default=10)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-profile", dest="profile", action="store_false",
-                    help="time the window without the kernel timers (diagnostic: no roofline)")
+                    help="skip the replay of the window with the kernel timers (no roofline figures)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs one process on one MI355X "
@@ -452,6 +471,9 @@ def main():
     res = batched_leg(args)
     value = (res["cg"] + res["pf"]) * res["n"] ** 2 / res["dt"]
     prof = res["prof"]
+    if prof is None:  # --no-profile: no per-kernel figures
+        prof = {"kernel_ms": {k: 0.0 for k in KERNELS + ("ctrl",)}, "kernel_span_ms": {k: 0.0 for k in KERNELS + ("ctrl",)},
+                "launches": {k: 0 for k in KERNELS + ("ctrl",)}, "alg_bytes": {k: 0.0 for k in KERNELS + ("ctrl",)}}
     # a launch's time: its work-group activity plus half of the dead time to
     # the next kernel (drain and write-back belong to it, the next dispatch
     # does not); a kernel trace's duration lies between the two figures
@@ -487,6 +509,7 @@ def main():
                       "kernel_span_ms": prof["kernel_span_ms"], "kernel_launches": prof["launches"],
                       "kernel_alg_bytes": prof["alg_bytes"],
                       "alg_GBs_all_fft_kernels": all_b / (all_ms * 1e-3) / 1e9 if all_ms > 0 else None,
+                      "profiled_replay": res["replay"],
                       "steady_all_active": res["steady"]},
         "autotune": res["tuned"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
