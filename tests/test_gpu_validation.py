@@ -15,7 +15,14 @@ final F_f 109.1 G_c l.  The final profiles are about 20% (L1) from the
 analytical one, against 5.6% / 6.6% in the paper: at the end the crack
 centre is two pixel rows wide along the whole crack (FP64 the same); the
 relaxed initial crack itself is 5.4% from the analytical profile.  These
-bounds are loose on purpose and the differences are open."""
+bounds are loose on purpose and the differences are open.
+
+The near-equilibrium runs (Algorithm 4 as a device-driven evolution,
+(-F_phi)_max = 0.7 G_c/l, trigger 1 G_c/l, (d phi)_min = 1e-3 l^2) show the
+paper's snap-back: the macroscopic strain falls while the crack runs (void:
+from 0.0045 to 0.0005, the paper reports almost 3x).  Measured: crack IC
+1584 iterations, peak 0.103 sigma_M, F_f 109.7; void IC 2299 iterations
+(paper 3024), peak 0.774 sigma_M, F_f 108.9 (paper 102.6)."""
 
 import numpy as np
 import pytest
@@ -90,3 +97,46 @@ def test_homogeneous_tension_small_void():
           f"F_f {ff:.2f} G_c l, L1 {err:.3f}")
     assert c0 == pytest.approx(1.0, abs=0.02)
     assert peak == pytest.approx(0.77, rel=0.05)
+
+
+def _run_near_eq(phi0, max_iter=6000):
+    import torch
+    cfg = spff.default_config(nx=N, ny=N, at=1, split=spff.SPLIT_SPECTRAL, contact=spff.SPLIT_NONE,
+                              irreversibility=spff.IRR_DAMAGE, ell=ELL, gc=1.0, nu=0.2, tol_mech=1e-6,
+                              tol_pf=1e-6, use_graph=1, ticks_per_sync=16, evolution=spff.EVOL_NEAR_EQ,
+                              fphi_max=0.7 / ELL, drive_threshold=1.0 / ELL, deps_max=1e-4, eta=0.0,
+                              dt_max=1.0, dphi_min=1e-3 * ELL * ELL)
+    p = spff.Problem(torch_E(np.full((N, N), E0), "fp32"), cfg, phi_init=torch.as_tensor(phi0, device="cuda:0"))
+    hist = []
+    while len(hist) < max_iter:
+        st, stats = p.run_evolution((0.0, 1e-4, 0.0), nsteps=200)
+        assert st >= 0
+        done = False
+        for s in stats[0]:
+            hist.append(s)
+            if s["C_bar"] < 0.01 * E0:
+                done = True
+                break
+        if done:
+            break
+    phi = p.get_fields(spff.FIELD_PHI, index=0)["phi"][0].double().cpu().numpy()
+    p.close()
+    return hist, phi
+
+
+@pytest.mark.parametrize("ic", ["crack", "void"])
+def test_homogeneous_tension_near_equilibrium(ic):
+    phi0 = si.edge_crack(N, N, ELL, 50 * ELL) if ic == "crack" else si.round_void(N, N, ELL)
+    hist, phi = _run_near_eq(phi0)
+    i_peak = int(np.argmax([s["sigma_bar"][1] for s in hist]))
+    peak = hist[i_peak]["sigma_bar"][1] / SIGMA_M
+    eps_peak = hist[i_peak]["eps_bar"][1]
+    eps_min_after = min(s["eps_bar"][1] for s in hist[i_peak:])
+    ff, err = _final_checks(hist, phi)
+    print(f"near-eq {ic} IC: {len(hist)} iterations, peak {peak:.3f} sigma_M at eps {eps_peak:.5f}, "
+          f"strain falls to {eps_min_after:.5f}, F_f {ff:.2f} G_c l, L1 {err:.3f}")
+    assert any(s["gamma"] < 1.0 for s in hist)
+    # snap-back: the algorithm lowers the macroscopic strain during fracture
+    assert eps_min_after < 0.7 * eps_peak
+    if ic == "void":
+        assert peak == pytest.approx(0.77, rel=0.05)
