@@ -307,6 +307,56 @@ def variants_leg(args):
                         "ramp's increment (eps_M / 66.7); timed in chunks of 8", "runs": out}
 
 
+def large_leg(args):
+    """One large instance: 2048^2 (E = max(1+0.3z, 0.5), corr 32 px, seed
+    5000), AT1, spectral split, l = 1 px, crack set, 500-step uniaxial ramp
+    to 1.5 eps_M; load steps 0..39 untimed, 40..59 timed without the kernel
+    timers, then replayed from the same state with them on for the dominant
+    kernel's achieved algorithmic bandwidth."""
+    import torch
+
+    import spff_inputs as si
+    from paper_2203_16467_amd import spff
+
+    n = 2048
+    E = si.young_modulus(n, 32.0, 0.3, 5000)
+    ramp = si.uniaxial_ramp(500, 0.2, 1.0)
+    cfg = spff.default_config(nx=n, ny=n, ell=1.0, use_graph=1, ticks_per_sync=16)
+    p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
+    tuned = None
+    if args is None or args.autotune:
+        from paper_2203_16467_amd import autotune
+        plans, _, source = autotune.tune(n, n, 1, cache=(args.plan_cache if args else None) or autotune.DEFAULT_CACHE)
+        autotune.apply(p, plans)
+        tuned = {"source": source, "plan": plans[1]}
+    p.run_sequence(ramp[:40])
+    snap = p.get_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, stats = p.run_sequence(ramp[40:60])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cg, pf = iters(stats)
+    p.set_state(*snap)
+    del snap
+    p.profile_enable(True)
+    _, stats2 = p.run_sequence(ramp[40:60])
+    pr = p.profile_read()
+    p.close()
+    kt = {k: 0.5 * (pr["kernel_ms"][k] + pr["kernel_span_ms"][k]) for k in KERNELS}
+    dom = max(KERNELS, key=lambda k: kt[k])
+    gbs = pr["alg_bytes"][dom] / (kt[dom] * 1e-3) / 1e9 if kt[dom] > 0 else 0.0
+    out = {"workload": "one 2048x2048 problem (E = max(1+0.3z,0.5), corr 32 px, seed 5000), AT1, spectral, "
+                       "l = 1 px, crack set, 500-step ramp to 1.5 eps_M; load steps 40..59 (elastic)",
+           "seconds": dt, "value": (cg + pf) * n * n / dt, "unit": "grid-pt-iters/s", "cg_iters": cg,
+           "bccg_iters": pf, "status": st, "replay_iterations_equal": iters(stats2) == (cg, pf),
+           "dominant_kernel": dom, "avg_launch_us": kt[dom] * 1e3 / max(pr["launches"][dom], 1),
+           "alg_bytes_per_launch": pr["alg_bytes"][dom] / max(pr["launches"][dom], 1),
+           "achieved_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS, "plan": tuned}
+    log(f"[bench] large 2048^2: {out['value']:.3e} grid-pt-iters/s in {dt:.2f}s, {dom} {gbs:.0f} GB/s")
+    return out
+
+
 def serving_leg(args):
     """Serving workload: resident microstructures with grid sizes drawn
     uniformly from {128, 256, 512, 1024}^2, AT1/AT2 half and half, requests =
@@ -444,6 +494,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-serving", dest="serving", action="store_false")
     ap.add_argument("--no-variants", dest="variants", action="store_false")
+    ap.add_argument("--no-large", dest="large", action="store_false")
     ap.add_argument("--serve-problems", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
@@ -525,6 +576,8 @@ def main():
         out["serving"] = serving_leg(args)
     if args.variants:
         out["variants"] = variants_leg(args)
+    if args.large:
+        out["large"] = large_leg(args)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_leg(res, args.cpu_budget)
     print(json.dumps(out), flush=True)
