@@ -58,6 +58,22 @@ def uniaxial_ramp(steps, nu, ell, gc=1.0, factor=1.5):
     return out
 
 
+def centre_crack(ny, nx, ell, length, dx=1.0):
+    """Initial phase field of a straight crack of length ``length`` centred
+    on the grid (Sec. 4.1.1): phi = (1 - |r| / (2 l))^2 where |r| <= 2 l, 0
+    elsewhere, r = (max(|x| - L_crack/2, 0), y) on a grid centred at the
+    origin.  Readings: the printed r lost the absolute value of x (with it
+    the crack has the stated length L_crack; without it the crack would run
+    from the periodic boundary to x = L_crack/2); the cut-off "|r| <= 2" is
+    |r| <= 2 l.  Returns float32."""
+    y = (np.arange(ny) - ny // 2)[:, None] * dx
+    x = (np.arange(nx) - nx // 2)[None, :] * dx
+    rx = np.maximum(np.abs(x) - 0.5 * length, 0.0)
+    r = np.sqrt(rx ** 2 + y ** 2)
+    phi = np.where(r <= 2.0 * ell, (1.0 - r / (2.0 * ell)) ** 2, 0.0)
+    return phi.astype(np.float32)
+
+
 def edge_crack(ny, nx, ell, length, dx=1.0):
     """Initial phase field of a straight crack (Sec. 4.1.1, initial crack
     condition): phi = (1 - |r| / (2 l))^2 where |r| <= 2 l, 0 elsewhere, with

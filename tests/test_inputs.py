@@ -59,13 +59,18 @@ def test_allen_cahn_smoothing_relaxes_to_the_equilibrium_interface():
 
 
 def test_initial_crack_and_void_fields():
-    """Sec. 4.1.1: the crack is the AT1 profile (1 - |r|/(2 l))^2 around the
-    segment y = 0, x <= L/2 (grid centred at the origin); the void is the
-    same profile around the origin."""
+    """Sec. 4.1.1: the crack is the AT1 profile (1 - |r|/(2 l))^2 around a
+    segment of y = 0 (centred: |x| <= L/2; the literal printed form: x <= L/2
+    on a grid centred at the origin); the void is the same profile around
+    the origin."""
     n, ell = 64, 3.0
     phi = si.edge_crack(n, n, ell, 20.0)
     assert phi[n // 2, 0] == 1.0 and phi[n // 2, n // 2 + 10] == 1.0 and phi[n // 2, n // 2 + 17] == 0.0
     assert phi[n // 2 + 3, 5] == pytest.approx(0.25)
+    c = si.centre_crack(n, n, ell, 20.0)
+    assert c[n // 2, n // 2 - 10] == 1.0 and c[n // 2, n // 2 + 10] == 1.0 and c[n // 2, 0] == 0.0
+    assert c[n // 2, n // 2 + 13] == pytest.approx(0.25) and c[n // 2, n // 2 - 13] == pytest.approx(0.25)
+    np.testing.assert_array_equal(c[:, n // 2 + 1:n // 2 + 31], c[:, n // 2 - 1:n // 2 - 31:-1])
     v = si.round_void(n, n, ell)
     assert v[n // 2, n // 2] == 1.0 and v.sum() > 0
     assert v[n // 2 + 3, n // 2] == pytest.approx(0.25) and v[n // 2, n // 2 - 3] == pytest.approx(0.25)

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+import spff_inputs as si
 from oracle import constitutive as cm
 from oracle import mechanics as mech
 from oracle import phasefield as pf
@@ -359,3 +360,21 @@ def test_near_equilibrium_trigger_flag_persists_and_advance():
     r = oracle.Problem(np.full((n, n), 1.0), nu=0.2, ell=2.0, gc=1.0, at=1, split="spectral")
     st = r.near_equilibrium_step((0.0, 0.1, 0.0), (0.0, 1e-3, 0.0), fmax, 0.0, dphi_min=1e-6)
     assert st["gamma"] == 1.0 and st["dphi"] == 0.0 and st["advance"] and not st["ne_flag"]
+
+
+@pytest.mark.parametrize("ic,want,rel", [("crack", 0.65, 0.05), ("void", 1.0, 0.02)])
+def test_homogeneous_tension_stiffness_on_odd_grid(ic, want, rel):
+    """Sec. 4.1.1 on an odd grid (the paper's discretisation; 255^2, l = 2.55
+    px, E0 = 1e4 G_c/l, production model): the stiffness before fracture,
+    C_bar = sigma_bar_22 / eps_bar_22, is printed as 0.65 sigma_M/eps_M for
+    the 50 l crack and nearly 1 for the small void (sigma_M/eps_M = lambda +
+    2 mu at E0).  The oracle gives 0.665 and 1.00."""
+    n = 255
+    ell = n / 100.0
+    E0 = 1e4 / ell
+    phi0 = (si.centre_crack(n, n, ell, 50 * ell) if ic == "crack" else si.round_void(n, n, ell)).astype(np.float64)
+    p = oracle.Problem(np.full((n, n), E0), nu=0.2, ell=ell, gc=1.0, at=1, split="spectral", contact="none",
+                       irreversibility="damage", tol_mech=1e-8, tol_pf=1e-8, phi_init=phi0)
+    st = p.load_step((0.0, 1e-4, 0.0))
+    lam, mu = cm.lame(E0, 0.2)
+    assert st["C_bar"] / (lam + 2 * mu) == pytest.approx(want, rel=rel)
