@@ -304,18 +304,20 @@ spff_status spff_profile_read(spff_problem* p, spff_profile* out);
  * sums (so results by rounding only), never the arithmetic.
  *   row_kind / col_kind: SPFF_FFT_LDS -- Stockham radix-4/2 passes through
  *     LDS, one point pair per thread (any size); SPFF_FFT_REG -- radix-8
- *     Stockham on registers, 8 points per lane, wavefront-local LDS
- *     exchanges (FP32 only; rows: 128 <= nx <= 1024, columns: ny in
- *     {128, 256, 512}); SPFF_FFT_REG4 (rows only) -- the same with 4
- *     points per lane and radix-4 passes (twice the lanes per row, for
- *     launches with few problems; 128 <= nx <= 512).
+ *     Stockham on registers, 8 points per lane (16 for 1024-point
+ *     transforms), wavefront-local LDS exchanges (FP32 only; rows:
+ *     128 <= nx <= 2048, columns: ny in {128, 256, 512, 1024});
+ *     SPFF_FFT_REG4 (rows only) -- 4 points per lane and radix-4 passes
+ *     (twice the lanes per row, for launches with few problems;
+ *     128 <= nx <= 512).
  *   rows / cols: rows per row work-group, columns per column work-group
  *     (powers of two).
  *   row_threads / col_threads: threads per work-group for the LDS kind
  *     (64, 128 or 256, times 8 covering the transform); for the register
- *     kinds derived as rows * nx/16 (rows * nx/8 for SPFF_FFT_REG4;
- *     cols * ny/8), which must be a power of two in [64, 256] -- filled in
- *     on return. */
+ *     kinds derived as rows * (lanes per row: nx/16, nx/32 for nx = 2048,
+ *     nx/8 for SPFF_FFT_REG4) and cols * (lanes per column: ny/8, ny/16
+ *     for ny = 1024), which must be a power of two in [64, 256] -- filled
+ *     in on return. */
 enum { SPFF_FFT_LDS = 1, SPFF_FFT_REG = 2, SPFF_FFT_REG4 = 3 };
 typedef struct spff_plan {
   int32_t row_kind, rows, row_threads;

@@ -4,8 +4,8 @@ A handle launches its three FFT kernels (row-forward, column, row-inverse)
 over a power-of-two bucket of active problem slots; for every bucket the
 library holds a launch plan (``spff_plan``): the kind of FFT kernel for rows
 and for columns (LDS Stockham radix-4/2 with one point pair per thread, or
-register-resident radix-8 with eight points per lane, or for rows radix-4
-with four), rows / columns per
+register-resident radix-8 with eight points per lane -- sixteen for
+1024-point transforms --, or for rows radix-4 with four), rows / columns per
 work-group and threads per work-group.  The built-in plans come from a
 heuristic; this module times the alternatives on the device and installs the
 fastest.
@@ -50,7 +50,7 @@ def row_candidates(cfg):
         for T in (128, 256):
             if T * 8 >= M and 3 * R * (M + 1) * csize <= LDS_BYTES // 2:
                 out.append((spff.FFT_LDS, R, T))
-    for kind, E, Mmax in ((spff.FFT_REG, 8, 512), (spff.FFT_REG4, 4, 256)):
+    for kind, E, Mmax in ((spff.FFT_REG, 8 if M <= 512 else 16, 1024), (spff.FFT_REG4, 4, 256)):
         if cfg.precision == spff.FP32 and 64 <= M <= Mmax:
             L = M // E
             for R in _pow2_range(max(1, 64 // L), THREADS // L):
@@ -68,8 +68,8 @@ def col_candidates(cfg):
         for T in (128, 256):
             if T * 8 >= cfg.ny and 3 * W * (cfg.ny + 1) * csize <= LDS_BYTES // 2:
                 out.append((spff.FFT_LDS, W, T))
-    if cfg.precision == spff.FP32 and cfg.ny in (128, 256, 512):
-        L = cfg.ny // 8
+    if cfg.precision == spff.FP32 and cfg.ny in (128, 256, 512, 1024):
+        L = cfg.ny // (8 if cfg.ny <= 512 else 16)
         for W in _pow2_range(max(1, 64 // L), THREADS // L):
             if W <= M:
                 out.append((spff.FFT_REG, W, W * L))

@@ -119,11 +119,14 @@ spff_status check_config(const spff_config* c) {
 // ---------------------------------------------------------------------------
 bool reg_rows_ok(const spff_config* c, int kind = SPFF_FFT_REG) {
   const int M = c->nx / 2;
-  return c->precision == SPFF_FP32 && M >= 64 && M <= (kind == SPFF_FFT_REG4 ? 256 : 512);
+  return c->precision == SPFF_FP32 && M >= 64 && M <= (kind == SPFF_FFT_REG4 ? 256 : 1024);
 }
 bool reg_cols_ok(const spff_config* c) {
-  return c->precision == SPFF_FP32 && (c->ny == 128 || c->ny == 256 || c->ny == 512);
+  return c->precision == SPFF_FP32 && (c->ny == 128 || c->ny == 256 || c->ny == 512 || c->ny == 1024);
 }
+// points per lane of the register kinds: 8 up to 512-point transforms, 16
+// for 1024 (a group never exceeds one wavefront); REG4 rows: 4
+int reg_points(int n) { return n > 512 ? 16 : 8; }
 
 spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
   spff_plan pl{};
@@ -147,12 +150,12 @@ spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
   pl.col_kind = SPFF_FFT_LDS;
   pl.cols = W;
   pl.col_threads = T;
-  // FP32 columns of 128..512 points: register-resident transforms, a group
-  // of ny/8 lanes per column, W columns per work-group (at least one
+  // FP32 columns of 128..1024 points: register-resident transforms, a group
+  // of ny/8 (ny/16 for 1024) lanes per column, W columns per work-group (at least one
   // wavefront, at most THREADS lanes); W is fixed by plan_cols if given so
   // that the partial sums (hence the results) do not depend on the batch
   if (reg_cols_ok(c)) {
-    const int Lc = c->ny / 8;
+    const int Lc = c->ny / reg_points(c->ny);
     const int wmin = 64 / Lc, wmax = THREADS / Lc;
     if (wmin <= M) {
       int Wr = wmin;
@@ -168,8 +171,8 @@ spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
       }
     }
   }
-  // FP32 rows of 64..512 complex points (nx = 128..1024): register-resident
-  // transforms, a group of nx/16 lanes per row, R rows per work-group (at
+  // FP32 rows of 64..1024 complex points (nx = 128..2048): register-resident
+  // transforms, a group of nx/16 (nx/32 for 2048) lanes per row, R rows per work-group (at
   // least one wavefront, at most THREADS lanes); R fixed by plan_rows if
   // given.  A lane walks 8 pixel pairs of its row one after the other, so
   // the path needs enough wavefronts in flight to hide that: below ~8 per
@@ -177,7 +180,7 @@ spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
   // take one pixel pair each, finish sooner.
   const bool many_waves = (long)S * c->ny * (M / 8) / 64 >= 2048;
   if (reg_rows_ok(c) && (many_waves || c->plan_rows > 0)) {
-    const int Lr = M / 8;
+    const int Lr = M / reg_points(M);
     const int rmin = std::max(1, 64 / Lr), rmax = THREADS / Lr;
     if (rmin <= c->ny) {
       int Rr = rmin;
@@ -212,10 +215,11 @@ spff_status check_plan(const spff_config* c, spff_plan* pl, size_t csize) {
   const int M = c->nx / 2;
   if (pl->row_kind == SPFF_FFT_REG || pl->row_kind == SPFF_FFT_REG4) {
     if (!reg_rows_ok(c, pl->row_kind))
-      return fail(SPFF_E_INVALID, "register row FFT needs FP32 and 128 <= nx <= 1024 (512 with 4 points per lane)");
-    const int Lr = M / (pl->row_kind == SPFF_FFT_REG4 ? 4 : 8);
+      return fail(SPFF_E_INVALID, "register row FFT needs FP32 and 128 <= nx <= 2048 (512 with 4 points per lane)");
+    const int Lr = M / (pl->row_kind == SPFF_FFT_REG4 ? 4 : reg_points(M));
     if (!pow2(pl->rows) || pl->rows * Lr < 64 || pl->rows * Lr > THREADS || pl->rows > c->ny)
-      return fail(SPFF_E_INVALID, "register row FFT: rows * nx/16 must be a power of two in [64, %d]", THREADS);
+      return fail(SPFF_E_INVALID, "register row FFT: rows * lanes per row must be a power of two in [64, %d]",
+                  THREADS);
     pl->row_threads = pl->rows * Lr;
   } else if (pl->row_kind == SPFF_FFT_LDS) {
     if (!pow2(pl->rows) || pl->rows > c->ny) return fail(SPFF_E_INVALID, "rows must be a power of two <= ny");
@@ -227,10 +231,12 @@ spff_status check_plan(const spff_config* c, spff_plan* pl, size_t csize) {
     return fail(SPFF_E_INVALID, "bad row_kind");
   }
   if (pl->col_kind == SPFF_FFT_REG) {
-    if (!reg_cols_ok(c)) return fail(SPFF_E_INVALID, "register column FFT needs FP32 and ny in {128, 256, 512}");
-    const int Lc = c->ny / 8;
+    if (!reg_cols_ok(c))
+      return fail(SPFF_E_INVALID, "register column FFT needs FP32 and ny in {128, 256, 512, 1024}");
+    const int Lc = c->ny / reg_points(c->ny);
     if (!pow2(pl->cols) || pl->cols * Lc < 64 || pl->cols * Lc > THREADS || pl->cols > M)
-      return fail(SPFF_E_INVALID, "register column FFT: cols * ny/8 must be a power of two in [64, %d]", THREADS);
+      return fail(SPFF_E_INVALID, "register column FFT: cols * lanes per column must be a power of two in [64, %d]",
+                  THREADS);
     pl->col_threads = pl->cols * Lc;
   } else if (pl->col_kind == SPFF_FFT_LDS) {
     if (!pow2(pl->cols) || pl->cols > M) return fail(SPFF_E_INVALID, "cols must be a power of two <= nx/2");

@@ -284,7 +284,10 @@ template <typename real, bool INV, int N, int E, int NS = 1>
 __device__ __forceinline__ void reg_fft(cplx<real> (&v)[E], cplx<real>* x, int lane,
                                         const cplx<real>* __restrict__ tw, int twmul) {
   if constexpr (NS < N) {
-    constexpr int RD = (N / NS) >= E ? E : (N / NS);
+    // radix E while the remaining factor allows, at most 8 (a lane then
+    // computes E / 8 butterflies per pass)
+    constexpr int RD0 = (N / NS) >= E ? E : (N / NS);
+    constexpr int RD = RD0 > 8 ? 8 : RD0;
     reg_pass<real, INV, N, E, RD, NS>(v, x, lane, tw, twmul);
     reg_fft<real, INV, N, E, NS * RD>(v, x, lane, tw, twmul);
   }

@@ -629,7 +629,8 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
                                             const cplx<real>* __restrict__ twy, double* __restrict__ part, int nx,
                                             int ngc) {
   using C = cplx<real>;
-  constexpr int E = 8, L = N / E;
+  // eight points per lane up to 512-point columns, sixteen for 1024
+  constexpr int E = N <= 512 ? 8 : N / 64, L = N / E;
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_COL];
   const int s = list[blockIdx.y], g = blockIdx.x;
@@ -1886,7 +1887,8 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
           case 128: SPFF_ROWS_FWD(64, 8); break;
           case 256: SPFF_ROWS_FWD(128, 8); break;
           case 512: SPFF_ROWS_FWD(256, 8); break;
-          default: SPFF_ROWS_FWD(512, 8); break;
+          case 1024: SPFF_ROWS_FWD(512, 8); break;
+          default: SPFF_ROWS_FWD(1024, 16); break;
         }
       }
 #undef SPFF_ROWS_FWD
@@ -1909,8 +1911,12 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
         hipLaunchKernelGGL((k_colr<real, 256>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
                            twy, pcol, G.nx, G.ngc, ktc);
         break;
-      default:
+      case 512:
         hipLaunchKernelGGL((k_colr<real, 512>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
+                           twy, pcol, G.nx, G.ngc, ktc);
+        break;
+      default:
+        hipLaunchKernelGGL((k_colr<real, 1024>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
                            twy, pcol, G.nx, G.ngc, ktc);
         break;
       }
@@ -1935,7 +1941,8 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
           case 128: SPFF_ROWS_INV(64, 8); break;
           case 256: SPFF_ROWS_INV(128, 8); break;
           case 512: SPFF_ROWS_INV(256, 8); break;
-          default: SPFF_ROWS_INV(512, 8); break;
+          case 1024: SPFF_ROWS_INV(512, 8); break;
+          default: SPFF_ROWS_INV(1024, 16); break;
         }
       }
 #undef SPFF_ROWS_INV

@@ -75,7 +75,8 @@ def _check_ops(p, x3, x1, tol=2e-6):
         assert rel_l2(out1[b], want1) < tol
 
 
-@pytest.mark.parametrize("nx,ny", [(128, 128), (256, 512), (512, 256), (1024, 128), (64, 512)])
+@pytest.mark.parametrize("nx,ny", [(128, 128), (256, 512), (512, 256), (1024, 128), (64, 512), (2048, 1024),
+                                   (128, 1024)])
 def test_every_plan_candidate_gives_the_operators(nx, ny):
     """Every launch plan the autotuner may install (LDS and register FFT
     kinds, all work-group shapes) computes the same operators."""
@@ -99,11 +100,11 @@ def test_every_plan_candidate_gives_the_operators(nx, ny):
         _check_ops(p, x3, x1)
         kinds.add(("col", kind))
     assert ("row", spff.FFT_LDS) in kinds and ("col", spff.FFT_LDS) in kinds
-    if 128 <= nx <= 1024:
+    if 128 <= nx <= 2048:
         assert ("row", spff.FFT_REG) in kinds
     if 128 <= nx <= 512:
         assert ("row", spff.FFT_REG4) in kinds
-    if ny in (128, 256, 512):
+    if ny in (128, 256, 512, 1024):
         assert ("col", spff.FFT_REG) in kinds
     p.close()
 
