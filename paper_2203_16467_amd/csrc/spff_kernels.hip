@@ -888,8 +888,8 @@ __device__ __forceinline__ void row_epilogue_n(const RowCtx<real>& X, const Slot
 }
 
 // ---------------------------------------------------------------------------
-// Row kernels with register-resident transforms (M = nx/2 in {64 .. 512},
-// FP32): a group of L = M/E lanes (E = 8 or 4 points per lane) owns one row
+// Row kernels with register-resident transforms (M = nx/2 in {64 .. 1024},
+// FP32): a group of L = M/E lanes (E = 4, 8, or 16 for M = 1024) owns one row
 // (R = blockDim/L rows per work-group); lane l holds z[h] = x[2h] + i x[2h+1]
 // for h = l + m L.  The
 // prologue / epilogue run per pixel pair on the registers; the real <->
