@@ -108,7 +108,7 @@ def batched_leg(args):
         tuned = {"source": source, "seconds": time.time() - t,
                  "plans": {str(v): plans[v] for v in plans}, "timing_us_per_tick": {str(v): timing[v] for v in timing}}
         log(f"[bench] autotuned launch plans for {len(plans)} buckets ({source}) in {tuned['seconds']:.1f}s")
-    cfg = spff.default_config(nx=n, ny=n, use_graph=1, ticks_per_sync=16)
+    cfg = spff.default_config(nx=n, ny=n, use_graph=1, ticks_per_sync=args.ticks_per_sync)
     p = spff.Problem(torch.as_tensor(E, device="cuda:0"), cfg)
     if tuned:
         autotune.apply(p, plans)
@@ -495,6 +495,9 @@ def main():
     ap.add_argument("--no-serving", dest="serving", action="store_false")
     ap.add_argument("--no-variants", dest="variants", action="store_false")
     ap.add_argument("--no-large", dest="large", action="store_false")
+    ap.add_argument("--ticks-per-sync", type=int, default=32,
+                    help="solver ticks per captured graph block between host status checks (32: the host "
+                         "turnaround is ~1%% of the window; 16 costs ~2%%)")
     ap.add_argument("--serve-problems", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
