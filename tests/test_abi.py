@@ -125,3 +125,37 @@ def test_create_rejects_null_arguments_without_device():
     assert L.spff_load_step(None, None, None) == spff.E_INVALID
     assert L.spff_get_fields(None, 0, 1, None) == spff.E_INVALID
     assert L.spff_destroy_problem(None) == spff.OK
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of spff_config, spff_step_stats, spff_profile and
+    spff_plan have the header's size and field offsets (compiled with the
+    host C compiler against include/spff.h)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"spff_config": spff.Config, "spff_step_stats": spff.StepStats, "spff_profile": spff.Profile,
+               "spff_plan": spff.Plan}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "spff.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        parts = line.split()
+        if len(parts) == 3:
+            got[(parts[0], parts[1])] = int(parts[2])
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
