@@ -605,3 +605,27 @@ def test_run_evolution_matches_host_driven_iterations(mode):
             q.run_evolution(deps, nsteps=2)
         finally:
             q.close()
+
+
+def test_run_evolution_across_device_queue_chunks():
+    """A device evolution queue longer than one chunk of queued steps (256)
+    continues across the chunk boundary exactly as two shorter calls do
+    (Algorithm 4, FP32, bit for bit)."""
+    E, ramp = _c1_inputs()
+    deps = np.asarray(ramp[1]) - np.asarray(ramp[0])
+    extra = dict(evolution=spff.EVOL_NEAR_EQ, fphi_max=0.35, drive_threshold=0.5,
+                 deps_max=float(np.abs(deps).max()), dphi_min=1e-3)
+    a = spff.Problem(torch_E(E, "fp32"), cfg_for(64, use_graph=1, ticks_per_sync=8, **extra))
+    b = spff.Problem(torch_E(E, "fp32"), cfg_for(64, use_graph=1, ticks_per_sync=8, **extra))
+    _, sa = a.run_evolution(deps, nsteps=300)
+    _, sb1 = b.run_evolution(deps, nsteps=150)
+    _, sb2 = b.run_evolution(deps, nsteps=150)
+    sb = sb1[0] + sb2[0]
+    for k in range(300):
+        assert sa[0][k]["eps_bar"] == sb[k]["eps_bar"] and sa[0][k]["cg_iters"] == sb[k]["cg_iters"], k
+    assert any(s["gamma"] < 1.0 for s in sa[0])
+    fa, fb = gpu_fields(a), gpu_fields(b)
+    for key in fa:
+        assert np.array_equal(fa[key], fb[key]), key
+    a.close()
+    b.close()
