@@ -361,15 +361,18 @@ typedef struct spff_server spff_server;
 /* arena_dev: device memory owned by the caller (256-byte aligned), used for
  * resident state and class engines.  scratch_budget_bytes: upper bound on
  * engine scratch over all classes (0 = no bound beyond the arena).
- * ticks_per_sync / use_graph as in spff_config.  stream is unused (each class
- * creates its own non-blocking stream of default priority). */
+ * ticks_per_sync / use_graph as in spff_config.  Each size class creates
+ * its own non-blocking stream of default priority. */
 spff_status spff_server_create(void* arena_dev, size_t arena_bytes, size_t scratch_budget_bytes,
                                int32_t ticks_per_sync, int32_t use_graph, spff_server** out);
 
 /* Register a problem (copies E, real[ny][nx] on the device, into the arena;
- * phi = eps* = 0).  cfg->nx, ny, precision pick the class; the physical and
- * solver fields are per problem.  Fails with SPFF_E_NOMEM when the arena is
- * full.  Problems may be registered while others run. */
+ * phi = eps* = 0).  cfg->nx, ny, precision pick the class; the physical,
+ * solver and evolution fields are per problem (a request is one load step
+ * of cfg->evolution; the time step of Algorithm 3 and the trigger flag of
+ * Algorithm 4 are kept per problem between its requests, whatever slot
+ * serves them).  Fails with SPFF_E_NOMEM when the arena is full.  Problems
+ * may be registered while others run. */
 spff_status spff_server_register(spff_server* sv, const spff_config* cfg, const void* E_dev, int32_t* id);
 
 /* Queue one load step of problem id at eps_bar (host double[3]). */
