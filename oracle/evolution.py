@@ -56,14 +56,16 @@ class Problem:
     field E (ny, nx), Poisson ratio nu, length scale ell (pixels), G_c, AT
     model (1 or 2), split ('none' | 'spectral' | 'voldev': the crack
     driving force model), contact (the stress model; None: same as split),
-    irreversibility ('crack_set' | 'damage').
+    irreversibility ('crack_set' | 'damage'), nyquist ('zero' | 'free':
+    the strain fluctuation's Nyquist modes on even grids, see
+    ``spectral.project_hat``).
     """
 
     def __init__(self, E, nu=0.2, ell=2.0, gc=1.0, at=1, split="spectral", contact=None,
                  irreversibility="crack_set", threshold=0.9, k_res=0.0,
                  eta_over_dt=0.0, tol_mech=1e-8, tol_pf=1e-8, tol_am=None,
                  tol_abs_mech=0.0, tol_abs_pf=0.0, max_cg=10000,
-                 max_newton=30, max_bccg=10000, max_am=1000, phi_init=None):
+                 max_newton=30, max_bccg=10000, max_am=1000, phi_init=None, nyquist="zero"):
         self.E = np.asarray(E, dtype=np.float64)
         self.ny, self.nx = self.E.shape
         self.nu, self.ell, self.gc, self.at = float(nu), float(ell), float(gc), int(at)
@@ -75,6 +77,7 @@ class Problem:
         self.tol_am = 1e-3 * self.ell ** 2 if tol_am is None else float(tol_am)
         self.max_cg, self.max_newton = int(max_cg), int(max_newton)
         self.max_bccg, self.max_am = int(max_bccg), int(max_am)
+        self.nyquist = nyquist
         self.lam, self.mu = cm.lame(self.E, self.nu)
         self.eps_star = np.zeros((self.ny, self.nx, 2, 2))
         self.eps_bar = np.zeros((2, 2))
@@ -115,7 +118,8 @@ class Problem:
     def solve_mechanics(self):
         self.eps_star, info = mech.solve(self.eps_star, self.eps_bar, self.phi, self.lam,
                                          self.mu, self.contact, self.k_res, self.tol_mech,
-                                         self.tol_abs_mech, self.max_newton, self.max_cg)
+                                         self.tol_abs_mech, self.max_newton, self.max_cg,
+                                         self.nyquist)
         return info
 
     def solve_phase_field(self, lo, phi_old=None):

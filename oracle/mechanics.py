@@ -32,10 +32,10 @@ def inner(a, b):
     return float(np.sum(a * b))
 
 
-def residual(eps_star, eps_bar, phi, lam, mu, split, k_res):
+def residual(eps_star, eps_bar, phi, lam, mu, split, k_res, nyquist="zero"):
     """R = G[sigma(eps_bar + eps*)] (Sec. 3.1.1, nodal equilibrium)."""
     eps = eps_bar + eps_star
-    return sp.project(cm.stress(eps, phi, lam, mu, split, k_res))
+    return sp.project(cm.stress(eps, phi, lam, mu, split, k_res), nyquist)
 
 
 def cg(apply_k, b, tol_abs, max_iter):
@@ -65,7 +65,7 @@ def cg(apply_k, b, tol_abs, max_iter):
 
 
 def solve(eps_star, eps_bar, phi, lam, mu, split, k_res=0.0, tol_rel=1e-8,
-          tol_abs=0.0, max_newton=30, max_cg=10000):
+          tol_abs=0.0, max_newton=30, max_cg=10000, nyquist="zero"):
     """Solve the mechanics sub-problem at fixed phi and eps_bar.
 
     ``eps_star`` is the warm start (shape (ny, nx, 2, 2)); ``eps_bar`` a
@@ -74,14 +74,14 @@ def solve(eps_star, eps_bar, phi, lam, mu, split, k_res=0.0, tol_rel=1e-8,
     eps_bar = np.asarray(eps_bar, dtype=np.float64)
     hom = eps_bar * np.ones_like(eps_star)
     sig_hom = cm.stress(hom, phi, lam, mu, split, k_res)
-    R0 = residual(eps_star, eps_bar, phi, lam, mu, split, k_res)
+    R0 = residual(eps_star, eps_bar, phi, lam, mu, split, k_res, nyquist)
     ref = max(np.sqrt(inner(sig_hom, sig_hom)), np.sqrt(inner(R0, R0)))
     target = tol_rel * ref + tol_abs
     newton = 0
     cg_total = 0
     converged = False
     while True:
-        R = residual(eps_star, eps_bar, phi, lam, mu, split, k_res)
+        R = residual(eps_star, eps_bar, phi, lam, mu, split, k_res, nyquist)
         res = np.sqrt(inner(R, R))
         if res <= target:
             converged = True
@@ -95,7 +95,7 @@ def solve(eps_star, eps_bar, phi, lam, mu, split, k_res=0.0, tol_rel=1e-8,
             inner_tol = max(0.1 * res, target)
 
         def apply_k(d):
-            return sp.project(cm.tangent_action(eps_m, d, phi, lam, mu, split, k_res))
+            return sp.project(cm.tangent_action(eps_m, d, phi, lam, mu, split, k_res), nyquist)
 
         theta, its, _, _ = cg(apply_k, -R, inner_tol, max_cg)
         cg_total += its

@@ -75,7 +75,20 @@ def ifft_field(a_hat):
     return np.fft.ifft2(a_hat, axes=(0, 1)).real
 
 
-def project_hat(a_hat):
+def nyquist_modes(ny, nx):
+    """Boolean (ny, nx) mask of the modes with a Nyquist index |k| = N/2 in
+    either direction (even N only)."""
+    ky = signed_indices(ny)[:, None] * np.ones((1, nx), dtype=np.int64)
+    kx = signed_indices(nx)[None, :] * np.ones((ny, 1), dtype=np.int64)
+    m = np.zeros((ny, nx), dtype=bool)
+    if ny % 2 == 0:
+        m |= np.abs(ky) == ny // 2
+    if nx % 2 == 0:
+        m |= np.abs(kx) == nx // 2
+    return m
+
+
+def project_hat(a_hat, nyquist="zero"):
     """Apply the Fourier-space compatibility projection G^ to a tensor field.
 
     Sec. 3.1.1: G projects an arbitrary symmetric tensor field onto the
@@ -89,6 +102,14 @@ def project_hat(a_hat):
         G^ : A = 0                               (xi  = 0; the mean strain is
                                                   fixed by the load).
     ``a_hat`` has shape (ny, nx, 2, 2), complex; vector index order is (x, y).
+
+    Even grids (not covered by the paper, which uses odd ones): with
+    ``nyquist="zero"`` the gradient wavevector component at a Nyquist index
+    is zero, so the strain fluctuation has no Nyquist component along that
+    direction; with ``nyquist="free"`` the modes with a Nyquist index are
+    left unconstrained (G^ = identity there), i.e. G is the orthogonal
+    projector onto the compatible fields plus every field supported on
+    those modes.
     """
     ny, nx = a_hat.shape[:2]
     xi_y, xi_x = gradient_wavevectors(ny, nx)
@@ -101,12 +122,17 @@ def project_hat(a_hat):
     tat = np.einsum("...i,...ij,...j->...", t, a_hat, t)
     out = a_hat - tat[..., None, None] * tt
     out[~nz] = 0.0
+    if nyquist == "free":
+        m = nyquist_modes(ny, nx)
+        out[m] = a_hat[m]
+    elif nyquist != "zero":
+        raise ValueError(nyquist)
     return out
 
 
-def project(a):
+def project(a, nyquist="zero"):
     """G applied to a real tensor field of shape (ny, nx, 2, 2)."""
-    return ifft_field(project_hat(fft_field(a)))
+    return ifft_field(project_hat(fft_field(a), nyquist))
 
 
 def laplacian(g):

@@ -164,3 +164,29 @@ def test_residual_small_after_solve():
     assert np.sqrt(np.sum(R * R)) <= info["target"] * (1 + 1e-12)
     # eps* stays compatible and zero mean
     np.testing.assert_allclose(sp.project(eps_star), eps_star, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (16, 6)])
+@pytest.mark.parametrize("split", ["none", "spectral"])
+def test_laminate_uniaxial_even_grid_nyquist_free(shape, split):
+    """On an even grid the layer strain e_yy(y) has a Nyquist component.
+    With the Nyquist modes of the strain fluctuation unconstrained
+    (nyquist='free') the laminate is exact again: sigma_yy uniform,
+    e / mean(1/M); with them suppressed (nyquist='zero') it is not (here
+    the layers alternate pixel by pixel, the pure Nyquist pattern)."""
+    ny, nx = shape
+    Ey = np.where(np.arange(ny) % 2 == 0, 1.0, 0.1)
+    E = Ey[:, None] * np.ones((1, nx))
+    phi = np.zeros(shape)
+    e = 0.2
+    lam, mu = cm.lame(E, 0.2)
+    lam1, mu1 = cm.lame(Ey, 0.2)
+    want = e / np.mean(1.0 / (lam1 + 2 * mu1))
+    out = {}
+    for nyq in ("free", "zero"):
+        eps_star, info = mech.solve(np.zeros(shape + (2, 2)), np.diag([0.0, e]), phi, lam, mu, split,
+                                    tol_rel=1e-11, max_newton=50, nyquist=nyq)
+        assert info["converged"], info
+        out[nyq] = cm.stress(np.diag([0.0, e]) + eps_star, phi, lam, mu, split, 0.0)
+    np.testing.assert_allclose(out["free"][..., 1, 1], want, rtol=1e-9)
+    assert np.abs(out["zero"][..., 1, 1].mean() / want - 1) > 0.5

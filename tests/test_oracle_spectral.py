@@ -126,3 +126,52 @@ def test_displacement_recovery_roundtrip(shape):
     u2 = sp.displacement_from_strain(eps)
     np.testing.assert_allclose(sp.symmetric_gradient(u2), eps, atol=1e-11)
     np.testing.assert_allclose(u2.mean(axis=(0, 1)), 0.0, atol=1e-12)
+
+
+def _dense_projector_with_nyquist(ny, nx):
+    """Orthogonal projector onto the symmetric gradients plus every real
+    tensor field supported on the modes with a Nyquist index (same
+    coordinates as _dense_range_projector)."""
+    n = ny * nx
+    P = _dense_range_projector(ny, nx)
+    U0 = np.linalg.svd(P)[0][:, :int(round(np.trace(P)))]
+    extra = []
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    mask = sp.nyquist_modes(ny, nx)
+    for ky, kx in zip(*np.nonzero(mask)):
+        ph = 2 * np.pi * (sp.signed_indices(nx)[kx] * xx / nx + sp.signed_indices(ny)[ky] * yy / ny)
+        for wave in (np.cos(ph), np.sin(ph)):
+            for c in range(3):
+                v = np.zeros(3 * n)
+                v[c * n:(c + 1) * n] = wave.ravel()
+                extra.append(v)
+    B = np.concatenate([U0, np.array(extra).T], axis=1) if extra else U0
+    U, s, _ = np.linalg.svd(B, full_matrices=False)
+    rank = int(np.sum(s > 1e-9 * s.max()))
+    return U[:, :rank] @ U[:, :rank].T
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (4, 6), (5, 6), (3, 5)])
+def test_projection_nyquist_free_equals_dense_projector(shape):
+    """nyquist='free' (even grids): G is the orthogonal projector onto the
+    compatible fields plus all fields on the Nyquist modes; on odd grids it
+    is the same operator as nyquist='zero'."""
+    ny, nx = shape
+    n = ny * nx
+    P = _dense_projector_with_nyquist(ny, nx)
+    G = np.zeros((3 * n, 3 * n))
+    for k in range(3 * n):
+        v = np.zeros(3 * n)
+        v[k] = 1.0
+        a = np.zeros((ny, nx, 2, 2))
+        a[..., 0, 0] = v[:n].reshape(ny, nx)
+        a[..., 0, 1] = a[..., 1, 0] = v[n:2 * n].reshape(ny, nx) / np.sqrt(2)
+        a[..., 1, 1] = v[2 * n:].reshape(ny, nx)
+        g = sp.project(a, "free")
+        G[:, k] = np.concatenate([g[..., 0, 0].ravel(), np.sqrt(2) * g[..., 0, 1].ravel(),
+                                  g[..., 1, 1].ravel()])
+    np.testing.assert_allclose(G, P, atol=1e-10)
+    if ny % 2 and nx % 2:
+        rng = np.random.default_rng(5)
+        a = _rand_sym(rng, shape)
+        np.testing.assert_allclose(sp.project(a, "free"), sp.project(a, "zero"), atol=1e-14)
