@@ -74,6 +74,13 @@ enum { SPFF_CONTACT_SAME = -1 };
  * (Algorithm 4). */
 enum { SPFF_EVOL_AM = 0, SPFF_EVOL_TIME = 1, SPFF_EVOL_NEAR_EQ = 2 };
 enum { SPFF_IRR_CRACK_SET = 0, SPFF_IRR_DAMAGE = 1 };
+/* Nyquist modes of the strain fluctuation on even grids (the paper uses odd
+ * grids, which have none).  ZERO: the gradient component along a Nyquist
+ * direction is zero, so those strain components are absent.  FREE: modes
+ * with a Nyquist index are unconstrained by the projection (G^ = identity
+ * there): laminates are exact again and a pixel-wide crack can open, as on
+ * an odd grid. */
+enum { SPFF_NYQ_ZERO = 0, SPFF_NYQ_FREE = 1 };
 enum { SPFF_FP32 = 0, SPFF_FP64 = 1 };
 
 /* Field selection bits for spff_get_fields, in output order. */
@@ -151,6 +158,7 @@ typedef struct spff_config {
   double fphi_max;         /* bound on -F_phi, > 0 */
   double drive_threshold;  /* trigger threshold on -h'(phi) psi0+, >= 0 */
   double deps_max;         /* max |component| of the load increment, >= 0 */
+  int32_t nyquist;         /* SPFF_NYQ_ZERO (default) or SPFF_NYQ_FREE (even grids) */
 } spff_config;
 
 /* Per-problem result of one load step (Sec. 3.2.1 quantities). */

@@ -72,6 +72,7 @@ spff_status check_config(const spff_config* c) {
   if (c->contact != SPFF_CONTACT_SAME && c->contact != SPFF_SPLIT_NONE && c->contact != SPFF_SPLIT_SPECTRAL &&
       c->contact != SPFF_SPLIT_VOLDEV)
     return fail(SPFF_E_INVALID, "bad contact model");
+  if (c->nyquist != SPFF_NYQ_ZERO && c->nyquist != SPFF_NYQ_FREE) return fail(SPFF_E_INVALID, "bad nyquist");
   if (c->evolution != SPFF_EVOL_AM && c->evolution != SPFF_EVOL_TIME && c->evolution != SPFF_EVOL_NEAR_EQ)
     return fail(SPFF_E_INVALID, "bad evolution");
   if (c->evolution == SPFF_EVOL_NEAR_EQ &&
@@ -267,6 +268,7 @@ LaunchGeom geom_from_plan(const spff_config* c, int S, size_t csize, const spff_
   G.ngc = M / pl.cols;
   G.threads_col = pl.col_threads;
   G.col_reg = pl.col_kind == SPFF_FFT_REG;
+  G.nyq_free = c->nyquist == SPFF_NYQ_FREE ? 1 : 0;
   G.lds_col = G.col_reg ? (size_t)pl.cols * (c->ny + c->ny / 8) * csize
                         : 3 * (size_t)pl.cols * (c->ny + PAD) * csize;
   return G;
@@ -710,6 +712,7 @@ void spff_default_config(spff_config* c) {
   c->fphi_max = 0.35;        // 0.7 G_c / l at the default G_c = 1, l = 2
   c->drive_threshold = 0.5;  // 1 G_c / l
   c->deps_max = 0.0;
+  c->nyquist = SPFF_NYQ_ZERO;
   c->irreversibility = SPFF_IRR_CRACK_SET;
   c->precision = SPFF_FP32;
   c->nu = 0.2;
@@ -1239,7 +1242,7 @@ struct SrvProblem {
 };
 
 struct SrvClass {
-  int nx, ny, precision;
+  int nx, ny, precision, nyquist;
   spff_problem* eng = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done_ev = nullptr;
@@ -1370,7 +1373,8 @@ spff_status spff_server_register(spff_server* sv, const spff_config* cfg, const 
   const size_t rb = rsize * (size_t)cfg->nx * cfg->ny;
   int c = -1;
   for (size_t k = 0; k < sv->classes.size(); ++k)
-    if (sv->classes[k].nx == cfg->nx && sv->classes[k].ny == cfg->ny && sv->classes[k].precision == cfg->precision)
+    if (sv->classes[k].nx == cfg->nx && sv->classes[k].ny == cfg->ny && sv->classes[k].precision == cfg->precision &&
+        sv->classes[k].nyquist == cfg->nyquist)
       c = (int)k;
   const size_t used0 = sv->used;
   SrvProblem P;
@@ -1408,6 +1412,7 @@ spff_status spff_server_register(spff_server* sv, const spff_config* cfg, const 
     C.nx = cfg->nx;
     C.ny = cfg->ny;
     C.precision = cfg->precision;
+    C.nyquist = cfg->nyquist;
     sv->classes.push_back(C);
     c = (int)sv->classes.size() - 1;
   }

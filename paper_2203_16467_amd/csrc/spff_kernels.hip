@@ -468,12 +468,22 @@ __device__ __forceinline__ void project3(real* a, real fx, real fy) {
   a[2] -= sdot * txy;
 }
 
+// Projection at one mode of an even grid.  nyq: the mode has a Nyquist
+// index (ky = ny/2, or the kx = nx/2 column); its gradient component along
+// that direction is already zero in (fx, fy).  With the free Nyquist
+// treatment such a mode is left unconstrained (identity).
+template <typename real>
+__device__ __forceinline__ void project3_mode(real* a, real fx, real fy, bool nyq, int nyq_free) {
+  if (nyq && nyq_free) return;
+  project3(a, fx, fy);
+}
+
 template <typename real>
 __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                                  const SlotParam* __restrict__ prms,
                                                  const SlotCtl* __restrict__ ctls,
                                                  const cplx<real>* __restrict__ twy, double* __restrict__ part,
-                                                 int nx, int ny, int W, int ngc) {
+                                                 int nx, int ny, int W, int ngc, int nyq_free) {
   using C = cplx<real>;
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_COL];
@@ -542,8 +552,8 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
         C* a1 = buf + (1 * W + w) * stride + ky;
         C* a2 = buf + (2 * W + w) * stride + ky;
         real re[3] = {a0->x, a1->x, a2->x}, im[3] = {a0->y, a1->y, a2->y};
-        project3(re, fx, fy_grad);
-        project3(im, fx, fy_grad);
+        project3_mode(re, fx, fy_grad, 2 * ky == ny, nyq_free);
+        project3_mode(im, fx, fy_grad, 2 * ky == ny, nyq_free);
         *a0 = mk<C>(re[0] * inv_n, im[0] * inv_n);
         *a1 = mk<C>(re[1] * inv_n, im[1] * inv_n);
         *a2 = mk<C>(re[2] * inv_n, im[2] * inv_n);
@@ -574,11 +584,11 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
         }
         real ar[3] = {Aa[0].x, Aa[1].x, Aa[2].x}, ai[3] = {Aa[0].y, Aa[1].y, Aa[2].y};
         real br[3] = {Bb[0].x, Bb[1].x, Bb[2].x}, bi[3] = {Bb[0].y, Bb[1].y, Bb[2].y};
-        project3(ar, real(0), fy_grad);
-        project3(ai, real(0), fy_grad);
+        project3_mode(ar, real(0), fy_grad, 2 * ky == ny, nyq_free);
+        project3_mode(ai, real(0), fy_grad, 2 * ky == ny, nyq_free);
         // kx = nx/2: gradient wavevector x-component is zero (Nyquist)
-        project3(br, real(0), fy_grad);
-        project3(bi, real(0), fy_grad);
+        project3_mode(br, real(0), fy_grad, true, nyq_free);
+        project3_mode(bi, real(0), fy_grad, true, nyq_free);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const C A = mk<C>(ar[c] * inv_n, ai[c] * inv_n), B = mk<C>(br[c] * inv_n, bi[c] * inv_n);
@@ -627,7 +637,7 @@ template <typename real, int N>
 __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                             const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
                                             const cplx<real>* __restrict__ twy, double* __restrict__ part, int nx,
-                                            int ngc) {
+                                            int ngc, int nyq_free) {
   using C = cplx<real>;
   // eight points per lane up to 512-point columns, sixteen for 1024
   constexpr int E = N <= 512 ? 8 : N / 64, L = N / E;
@@ -694,8 +704,8 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
       const real fy_grad = (2 * ky == N) ? real(0) : fy_true;
       if (mode == 0) {
         real re[3] = {v[0][m].x, v[1][m].x, v[2][m].x}, im[3] = {v[0][m].y, v[1][m].y, v[2][m].y};
-        project3(re, fx, fy_grad);
-        project3(im, fx, fy_grad);
+        project3_mode(re, fx, fy_grad, 2 * ky == N, nyq_free);
+        project3_mode(im, fx, fy_grad, 2 * ky == N, nyq_free);
 #pragma unroll
         for (int c = 0; c < 3; ++c) v[c][m] = mk<C>(re[c] * inv_n, im[c] * inv_n);
       } else {
@@ -745,11 +755,11 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
           br[c] = Bq.x;
           bi[c] = Bq.y;
         }
-        project3(ar, real(0), fy_grad);
-        project3(ai, real(0), fy_grad);
+        project3_mode(ar, real(0), fy_grad, 2 * ky == N, nyq_free);
+        project3_mode(ai, real(0), fy_grad, 2 * ky == N, nyq_free);
         // kx = nx/2: gradient wavevector x-component is zero (Nyquist)
-        project3(br, real(0), fy_grad);
-        project3(bi, real(0), fy_grad);
+        project3_mode(br, real(0), fy_grad, true, nyq_free);
+        project3_mode(bi, real(0), fy_grad, true, nyq_free);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const C A = mk<C>(ar[c] * inv_n, ai[c] * inv_n), Bq = mk<C>(br[c] * inv_n, bi[c] * inv_n);
@@ -1700,9 +1710,9 @@ __global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, c
                                                  const SlotParam* __restrict__ prms,
                                                  const SlotCtl* __restrict__ ctls,
                                                  const cplx<real>* __restrict__ twy, double* __restrict__ part,
-                                                 int nx, int ny, int W, int ngc, KTime* kt) {
+                                                 int nx, int ny, int W, int ngc, int nyq_free, KTime* kt) {
   kt_begin(kt);
-  k_col_body<real>(list, ptrs, prms, ctls, twy, part, nx, ny, W, ngc);
+  k_col_body<real>(list, ptrs, prms, ctls, twy, part, nx, ny, W, ngc, nyq_free);
   kt_end(kt);
 }
 
@@ -1711,9 +1721,9 @@ __global__ __launch_bounds__(THREADS) void k_colr(const int* __restrict__ list, 
                                                   const SlotParam* __restrict__ prms,
                                                   const SlotCtl* __restrict__ ctls,
                                                   const cplx<real>* __restrict__ twy, double* __restrict__ part,
-                                                  int nx, int ngc, KTime* kt) {
+                                                  int nx, int ngc, int nyq_free, KTime* kt) {
   kt_begin(kt);
-  k_colr_body<real, N>(list, ptrs, prms, ctls, twy, part, nx, ngc);
+  k_colr_body<real, N>(list, ptrs, prms, ctls, twy, part, nx, ngc, nyq_free);
   kt_end(kt);
 }
 
@@ -1905,26 +1915,26 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
       switch (G.ny) {
       case 128:
         hipLaunchKernelGGL((k_colr<real, 128>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
-                           twy, pcol, G.nx, G.ngc, ktc);
+                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
         break;
       case 256:
         hipLaunchKernelGGL((k_colr<real, 256>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
-                           twy, pcol, G.nx, G.ngc, ktc);
+                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
         break;
       case 512:
         hipLaunchKernelGGL((k_colr<real, 512>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
-                           twy, pcol, G.nx, G.ngc, ktc);
+                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
         break;
       default:
         hipLaunchKernelGGL((k_colr<real, 1024>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
-                           twy, pcol, G.nx, G.ngc, ktc);
+                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
         break;
       }
     }
   }
   if (!col_done)
     hipLaunchKernelGGL(k_col<real>, gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls, twy, pcol,
-                       G.nx, G.ny, G.W, G.ngc, ktc);
+                       G.nx, G.ny, G.W, G.ngc, G.nyq_free, ktc);
   if (row_done) {
     if constexpr (std::is_same<real, float>::value) {
 #define SPFF_ROWS_INV(MM, EE)                                                                                   \

@@ -19,6 +19,7 @@ struct LaunchGeom {
   int threads_col;  // threads per column work-group
   int col_reg;      // column kernel with register-resident transforms
   int row_reg;      // row kernels with register-resident transforms: 1 = 8, 2 = 4 points per lane
+  int nyq_free;     // even grids: Nyquist modes of the strain fluctuation unconstrained
   size_t lds_row, lds_col;
 };
 

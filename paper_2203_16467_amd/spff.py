@@ -23,6 +23,7 @@ AT1, AT2 = 1, 2
 SPLIT_NONE, SPLIT_SPECTRAL, SPLIT_VOLDEV = 0, 1, 2
 CONTACT_SAME = -1
 EVOL_AM, EVOL_TIME, EVOL_NEAR_EQ = 0, 1, 2
+NYQ_ZERO, NYQ_FREE = 0, 1
 IRR_CRACK_SET, IRR_DAMAGE = 0, 1
 FP32, FP64 = 0, 1
 OP_PROJECT, OP_NEG_LAPLACIAN = 0, 1
@@ -59,6 +60,7 @@ class Config(ctypes.Structure):
         ("eta", ctypes.c_double), ("dt_max", ctypes.c_double), ("dt_min", ctypes.c_double),
         ("dphi_max", ctypes.c_double), ("dphi_min", ctypes.c_double),
         ("fphi_max", ctypes.c_double), ("drive_threshold", ctypes.c_double), ("deps_max", ctypes.c_double),
+        ("nyquist", ctypes.c_int32),
     ]
 
 

@@ -42,7 +42,7 @@ def oracle_for(E, cfg, tol=1e-10, **kw):
     irr = "crack_set" if cfg.irreversibility == spff.IRR_CRACK_SET else "damage"
     args = dict(nu=cfg.nu, ell=cfg.ell, gc=cfg.gc, at=cfg.at, split=split, contact=contact, irreversibility=irr,
                 threshold=cfg.crack_set_threshold, k_res=cfg.k_res, tol_mech=tol, tol_pf=tol,
-                max_am=cfg.max_am)
+                max_am=cfg.max_am, nyquist="free" if cfg.nyquist == spff.NYQ_FREE else "zero")
     args.update(kw)
     return oracle.Problem(np.asarray(E, dtype=np.float64), **args)
 

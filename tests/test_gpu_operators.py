@@ -21,6 +21,36 @@ def _problem(nx, ny, precision, B=2):
     return spff.Problem(E, cfg)
 
 
+@pytest.mark.parametrize("nyquist", ["zero", "free"])
+@pytest.mark.parametrize("nx,ny,kind", [(16, 32, "lds"), (64, 64, "lds"), (256, 128, "reg"), (512, 512, "reg"),
+                                        (2048, 1024, "reg")])
+def test_projection_nyquist_treatments_match_oracle(nx, ny, kind, nyquist):
+    """Both treatments of the Nyquist modes on even grids, through the LDS
+    and the register column kernels (including the packed kx = 0 / nx/2
+    column), against the oracle's projection."""
+    import torch
+    print(f"projection {nx}x{ny} {kind} nyquist {nyquist}", flush=True)
+    cfg = cfg_for(nx, ny, "fp32", nyquist=spff.NYQ_FREE if nyquist == "free" else spff.NYQ_ZERO)
+    E = torch.ones((2, ny, nx), dtype=torch.float32, device=device())
+    p = spff.Problem(E, cfg)
+    b = len(p.plan_buckets()) - 1
+    plan = p.get_plan(b)
+    if kind == "lds":
+        p.set_plan(b, dict(plan, col_kind=spff.FFT_LDS, cols=1, col_threads=256))
+    else:
+        assert plan["col_kind"] == spff.FFT_REG
+    rng = np.random.default_rng(nx + ny)
+    x3 = rng.standard_normal((2, 3, ny, nx)).astype(np.float32)
+    out = p.apply_operator(spff.OP_PROJECT, torch.from_numpy(x3).to(device())).double().cpu().numpy()
+    for i in range(2):
+        want = tensor_to_planes(osp.project(planes_to_tensor(x3[i].astype(np.float64)), nyquist))
+        assert rel_l2(out[i], want) < 2e-6
+    other = tensor_to_planes(osp.project(planes_to_tensor(x3[0].astype(np.float64)),
+                                         "zero" if nyquist == "free" else "free"))
+    assert rel_l2(out[0], other) > 1e-3
+    p.close()
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("nx,ny", SHAPES)
 def test_projection_matches_oracle(nx, ny, precision):

@@ -43,11 +43,11 @@ SIGMA_M = 64.55 / ELL       # 64.55 G_c / l
 STIFF = SIGMA_M / EPS_M     # sigma_M / eps_M = lambda + 2 mu at E0
 
 
-def _run(phi0):
+def _run(phi0, nyquist=spff.NYQ_ZERO):
     import torch
     cfg = spff.default_config(nx=N, ny=N, at=1, split=spff.SPLIT_SPECTRAL, contact=spff.SPLIT_NONE,
                               irreversibility=spff.IRR_DAMAGE, ell=ELL, gc=1.0, nu=0.2, tol_mech=1e-6,
-                              tol_pf=1e-6, use_graph=1, ticks_per_sync=16)
+                              tol_pf=1e-6, use_graph=1, ticks_per_sync=16, nyquist=nyquist)
     p = spff.Problem(torch_E(np.full((N, N), E0), "fp32"), cfg, phi_init=torch.as_tensor(phi0, device="cuda:0"))
     hist = []
     for k in range(1, 120):
@@ -63,17 +63,28 @@ def _run(phi0):
 
 
 def _final_checks(hist, phi):
+    """Broken sample, a crack near the centre row through the whole periodic
+    width, no damage away from it; returns F_f / (G_c l) and the relative L1
+    distance of phi from the analytical crack profile centred, column by
+    column, on the crack (the crack may step by a few pixels where the two
+    tips of a void's crack meet across the periodic boundary)."""
     assert hist[-1]["C_bar"] < 0.01 * E0
     c = N // 2
-    # a straight crack along the centre row through the whole periodic width
-    assert (phi[c - 1:c + 2].max(axis=0) >= 0.95).all()
+    band = int(np.ceil(2 * ELL))
+    assert (phi[c - band:c + band + 1].max(axis=0) >= 0.95).all()
     d = np.abs(np.arange(N) - c)
-    band = np.minimum(d, N - d) > 2 * ELL + 1
-    assert phi[band].max() < 1e-3
+    far = np.minimum(d, N - d) > 4 * ELL
+    assert phi[far].max() < 1e-3
     ff = hist[-1]["F_f"] / ELL
     assert 95.0 <= ff <= 115.0, ff
-    ana = np.broadcast_to(opf.optimal_profile(np.minimum(d, N - d), 1, ELL)[:, None], (N, N))
-    err = np.abs(phi - ana).sum() / ana.sum()
+    err = tot = 0.0
+    for x in range(N):
+        r = int(np.argmax(phi[:, x]))
+        dd = np.abs(np.arange(N) - r)
+        ana = opf.optimal_profile(np.minimum(dd, N - dd), 1, ELL)
+        err += np.abs(phi[:, x] - ana).sum()
+        tot += ana.sum()
+    err /= tot
     assert err < 0.3, err
     return ff, err
 
@@ -143,3 +154,29 @@ def test_homogeneous_tension_near_equilibrium(ic):
     assert eps_min_after < 0.7 * eps_peak
     if ic == "void":
         assert peak == pytest.approx(0.77, rel=0.05)
+
+
+@pytest.mark.parametrize("ic", ["crack", "void"])
+def test_homogeneous_tension_free_nyquist_matches_printed_results(ic):
+    """With the Nyquist modes of the strain fluctuation left free (the even
+    grid then behaves like the paper's odd ones), alternating minimisation
+    reproduces the printed figures of Sec. 4.1.1: stiffness before fracture
+    0.65 sigma_M/eps_M (crack) and nearly 1 (void), peak stress 0.16 and
+    0.77 sigma_M, a final crack with the analytical profile (printed L1
+    errors 5.6% and 6.6%) and about G_c per unit length of crack (printed
+    F_f 103.0 G_c l for the void; 100 is ideal)."""
+    phi0 = si.centre_crack(N, N, ELL, 50 * ELL) if ic == "crack" else si.round_void(N, N, ELL)
+    hist, phi = _run(phi0, spff.NYQ_FREE)
+    c0 = hist[0]["C_bar"] / STIFF
+    peak = max(s["sigma_bar"][1] for s in hist) / SIGMA_M
+    ff, err = _final_checks(hist, phi)
+    print(f"free Nyquist, {ic} IC: C0 {c0:.3f} sigma_M/eps_M, peak {peak:.3f} sigma_M, steps {len(hist)}, "
+          f"F_f {ff:.2f} G_c l, L1 {err:.3f}")
+    if ic == "crack":
+        assert c0 == pytest.approx(0.65, rel=0.05)
+        assert peak == pytest.approx(0.16, rel=0.1)
+    else:
+        assert c0 == pytest.approx(1.0, abs=0.02)
+        assert peak == pytest.approx(0.77, rel=0.05)
+    assert err < 0.1
+    assert 95.0 <= ff <= 110.0
