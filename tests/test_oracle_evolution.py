@@ -378,3 +378,25 @@ def test_homogeneous_tension_stiffness_on_odd_grid(ic, want, rel):
     st = p.load_step((0.0, 1e-4, 0.0))
     lam, mu = cm.lame(E0, 0.2)
     assert st["C_bar"] / (lam + 2 * mu) == pytest.approx(want, rel=rel)
+
+
+def test_free_nyquist_even_grid_behaves_like_odd_grid():
+    """The cracked homogeneous domain of Sec. 4.1.1 (centred 50 l crack):
+    on an even grid with free Nyquist modes the pre-fracture stiffness is
+    the odd grid's (the paper's discretisation), while the default even-grid
+    treatment stiffens it by more than 10% (a pixel-wide crack cannot open
+    freely without the Nyquist strain modes)."""
+    def stiffness(n, nyquist):
+        ell = n / 100.0
+        E0 = 1e4 / ell
+        phi0 = si.centre_crack(n, n, ell, 50 * ell).astype(np.float64)
+        p = oracle.Problem(np.full((n, n), E0), nu=0.2, ell=ell, gc=1.0, at=1, split="spectral", contact="none",
+                           irreversibility="damage", tol_mech=1e-8, tol_pf=1e-8, phi_init=phi0, nyquist=nyquist)
+        st = p.load_step((0.0, 1e-4, 0.0))
+        lam, mu = cm.lame(E0, 0.2)
+        return st["C_bar"] / (lam + 2 * mu)
+    odd = stiffness(127, "zero")
+    free = stiffness(128, "free")
+    zero = stiffness(128, "zero")
+    assert free == pytest.approx(odd, rel=0.02)
+    assert zero > 1.1 * odd
