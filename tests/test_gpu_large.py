@@ -152,3 +152,28 @@ def test_large_crop_256_against_oracle(c5):
             assert stats[0]["phi_max"] > 0.0 and stats[0]["am_iters"] == ost["am"]
             assert abs(stats[0]["F_f"] - ost["F_f"]) <= TOL * (ost["F_e"] + ost["F_f"])
     p.close()
+
+
+@pytest.mark.parametrize("at,split", [(1, "none"), (1, "spectral"), (2, "none"), (2, "spectral")])
+def test_plain_256_step_parity(at, split):
+    """The plain single-instance workload (256^2, E = max(1+0.1z, 0.5), corr
+    8 px, seed 2000, l = 2 px, crack set) in each of its four model
+    variants: the load step at 60% of the ramp's strength strain against
+    the FP64 oracle from the same (GPU) state, FP32 contract."""
+    n = 256
+    E = si.young_modulus(n, 8.0, 0.1, 2000)
+    ramp = si.uniaxial_ramp(200, 0.2, 2.0)
+    cfg3 = cfg_for(n, at=at, split=split, max_am=3)
+    o = oracle_for(E, cfg3, max_am=3)
+    # step 79 from the GPU state on both sides (AM capped at 3)
+    q = spff.Problem(torch_E(E, "fp32"), cfg3)
+    st, _ = q.run_sequence(ramp[:79])
+    assert st >= 0
+    set_oracle_from_gpu(o, q)
+    _, stats = q.load_step(ramp[79])
+    ost = o.load_step(ramp[79])
+    cmp = compare(gpu_fields(q), oracle_fields(o), "fp32")
+    print(at, split, cmp, stats[0]["cg_iters"], ost["cg"], stats[0]["bccg_iters"], ost["bccg"])
+    tot = ost["F_e"] + ost["F_f"]
+    assert abs(stats[0]["F_e"] - ost["F_e"]) <= TOL * tot
+    q.close()
