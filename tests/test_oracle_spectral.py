@@ -118,6 +118,76 @@ def test_laplacian_nyquist_checkerboard_kept():
     np.testing.assert_allclose(sp.laplacian(f), -2 * np.pi ** 2 * f, atol=1e-11)
 
 
+def _plane_wave_displacement(ny, nx, kx, ky, ax, ay, phase):
+    """u = (ax sin(t), ay cos(t)), t = 2 pi (kx x / nx + ky y / ny) + phase,
+    and its symmetric gradient written out by hand from the continuum
+    derivatives d/dx t = 2 pi kx / nx, d/dy t = 2 pi ky / ny (exact on the
+    grid for a wave below the Nyquist index).  Returns u (ny, nx, 2) and eps
+    (ny, nx, 2, 2), vector index order (x, y)."""
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    t = 2 * np.pi * (kx * x / nx + ky * y / ny) + phase
+    gx, gy = 2 * np.pi * kx / nx, 2 * np.pi * ky / ny
+    u = np.stack([ax * np.sin(t), ay * np.cos(t)], axis=-1)
+    dux_dx, dux_dy = ax * gx * np.cos(t), ax * gy * np.cos(t)
+    duy_dx, duy_dy = -ay * gx * np.sin(t), -ay * gy * np.sin(t)
+    eps = np.zeros((ny, nx, 2, 2))
+    eps[..., 0, 0] = dux_dx
+    eps[..., 1, 1] = duy_dy
+    eps[..., 0, 1] = eps[..., 1, 0] = 0.5 * (dux_dy + duy_dx)
+    return u, eps
+
+
+WAVES = [(1, 0, 1.0, 0.0, 0.0), (0, 1, 0.0, 1.0, 0.0), (0, 1, 1.0, 0.0, 0.0), (1, 0, 0.0, 1.0, 0.0),
+         (2, 3, 0.7, -1.3, 0.4), (-3, 1, -0.5, 0.9, 1.1), (1, -2, 1.2, 0.3, -0.6)]
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (9, 7), (12, 10), (16, 16)])
+@pytest.mark.parametrize("wave", WAVES)
+def test_symmetric_gradient_plane_waves(shape, wave):
+    """sym(grad u) of a single plane-wave displacement equals the hand-written
+    derivative (Sec. 3.1.1: compatible strains are symmetric gradients).
+    Covers pure extension in x and y, pure shear (eps_xy = d u_x / dy / 2),
+    and oblique waves with both components."""
+    ny, nx = shape
+    u, eps = _plane_wave_displacement(ny, nx, *wave)
+    np.testing.assert_allclose(sp.symmetric_gradient(u), eps, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (9, 7), (12, 10), (16, 16)])
+@pytest.mark.parametrize("wave", WAVES)
+def test_displacement_from_strain_plane_waves(shape, wave):
+    """The displacement recovered from a plane-wave strain is the plane-wave
+    displacement itself (zero mean), e.g. eps_xx = (2 pi / N) cos(2 pi x / N)
+    gives u = (sin(2 pi x / N), 0): checked against the hand-written wave, not
+    against ``symmetric_gradient``."""
+    ny, nx = shape
+    u, eps = _plane_wave_displacement(ny, nx, *wave)
+    np.testing.assert_allclose(sp.displacement_from_strain(eps), u, atol=1e-12)
+
+
+def test_displacement_from_strain_superposition_and_mean():
+    """Linear in the strain, and a constant offset of u is not recoverable:
+    the result is the zero-mean fluctuation of the sum of several waves."""
+    ny, nx = 10, 12
+    us, es = zip(*[_plane_wave_displacement(ny, nx, *w) for w in WAVES[4:]])
+    u = sum(us) + np.array([0.3, -0.2])
+    eps = sum(es)
+    np.testing.assert_allclose(sp.displacement_from_strain(eps), u - u.mean(axis=(0, 1)), atol=1e-12)
+
+
+def test_symmetric_gradient_of_nyquist_waves_vanishes():
+    """Even grids: cos(pi x) and cos(pi y) sampled on the grid are (-1)^x,
+    (-1)^y, whose continuum derivative -pi sin(pi x) vanishes at every grid
+    point; the gradient (Nyquist component zero) gives zero strain, and the
+    displacement recovered from zero strain is zero."""
+    y, x = np.meshgrid(np.arange(8), np.arange(8), indexing="ij")
+    for wave in ((-1.0) ** x, (-1.0) ** y, (-1.0) ** (x + y)):
+        for c in range(2):
+            u = np.zeros((8, 8, 2))
+            u[..., c] = wave
+            np.testing.assert_allclose(sp.symmetric_gradient(u), 0.0, atol=1e-13)
+
+
 @pytest.mark.parametrize("shape", [(8, 8), (9, 7), (6, 10)])
 def test_displacement_recovery_roundtrip(shape):
     rng = np.random.default_rng(4)
