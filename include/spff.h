@@ -18,7 +18,7 @@
  *
  * Conventions shared by every entry point
  *   - Grid: ny rows by nx columns, unit spacing, row-major [y][x] arrays.
- *     nx and ny are powers of two, 8 <= n <= 4096.
+ *     nx and ny are powers of two, 8 <= n <= 2048.
  *   - Tensors are stored as three planes (xx, yy, xy) of tensor components
  *     (the shear plane holds eps_xy, not the engineering strain).
  *   - "real" is float for precision SPFF_FP32 (fields stored and transformed
@@ -91,13 +91,18 @@ enum {
   SPFF_FIELD_STRAIN = 1u << 2,   /* total strain eps_bar + eps*, 3 planes */
   SPFF_FIELD_STRESS = 1u << 3,   /* stress sigma(eps, phi), 3 planes */
   SPFF_FIELD_PSI_PLUS = 1u << 4, /* crack driving energy psi0+(eps), 1 plane */
-  SPFF_FIELD_EPS_STAR = 1u << 5  /* strain fluctuation eps*, 3 planes */
+  SPFF_FIELD_EPS_STAR = 1u << 5, /* strain fluctuation eps*, 3 planes */
+  SPFF_FIELD_DISP = 1u << 6      /* periodic displacement fluctuation u*, 2 planes (x, y): the
+                                    zero-mean field with sym(grad u*) = eps* (Sec. 3.1.1 solves
+                                    for the strain; u* is recovered mode by mode, and is zero on
+                                    modes whose gradient wavevector vanishes); the total
+                                    displacement is eps_bar . x + u* */
 };
 
 /* Problem configuration (Sec. 2.1, 3.1, 3.2.1; defaults from
  * spff_default_config). */
 typedef struct spff_config {
-  int32_t nx, ny;          /* grid, powers of two in [8, 4096] */
+  int32_t nx, ny;          /* grid, powers of two in [8, 2048] */
   int32_t at;              /* SPFF_AT1 (w = phi, c_w = 8/3) or SPFF_AT2 (w = phi^2, c_w = 2) */
   int32_t split;           /* crack driving force model: SPFF_SPLIT_NONE (isotropic), _SPECTRAL, _VOLDEV */
   int32_t irreversibility; /* SPFF_IRR_CRACK_SET or SPFF_IRR_DAMAGE */
@@ -275,9 +280,15 @@ spff_status spff_set_state(spff_problem* p, const void* src_dev, const double* e
  *   SPFF_OP_NEG_LAPLACIAN out = -lap_N in, the collocation Laplacian of
  *                         Sec. 3.1.2 (true |2 pi q|^2 at Nyquist); in/out
  *                         real[nbatch][ny][nx]
+ *   SPFF_OP_DISPLACEMENT  out = u*: the zero-mean periodic displacement
+ *                         whose symmetric gradient is the compatible part of
+ *                         in (the displacement of SPFF_FIELD_DISP); in
+ *                         real[nbatch][3][ny][nx] (xx, yy, xy), out
+ *                         real[nbatch][2][ny][nx] (x, y)
  * in and out are device buffers owned by the caller and may alias.
- * Synchronises the stream. */
-enum { SPFF_OP_PROJECT = 0, SPFF_OP_NEG_LAPLACIAN = 1 };
+ * Synchronises the stream.  Errors: SPFF_E_INVALID (unknown op, NULL
+ * buffers), SPFF_E_BUSY (a step is running), SPFF_E_DEVICE. */
+enum { SPFF_OP_PROJECT = 0, SPFF_OP_NEG_LAPLACIAN = 1, SPFF_OP_DISPLACEMENT = 2 };
 spff_status spff_apply_operator(spff_problem* p, int32_t op, const void* in_dev, void* out_dev);
 
 /* Kernel profiling.  A tick is four kernels: row-forward FFT, column FFT,

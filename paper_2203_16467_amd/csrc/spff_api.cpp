@@ -692,6 +692,42 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// One diagnostic tick (PH_X_PROJ, PH_X_LAP or PH_X_DISP) over the slots
+// `slots`: copies pin planes from src(s) into the slot's theta planes, runs
+// the tick with the plan of the slot count's bucket, copies pout planes of
+// rm to dst(s), and restores the control blocks (step statistics stay
+// readable).  Every listed slot must be idle.
+template <typename Src, typename Dst>
+spff_status run_diag(spff_problem* p, int phase, const std::vector<int32_t>& slots, int pin, int pout, Src src,
+                     Dst dst) {
+  const size_t rb = p->rsize * p->n();
+  for (int s : slots)
+    if (p->host_ctl[s].phase != PH_IDLE) return fail(SPFF_E_BUSY, "slot %d is not idle", s);
+  if (slots.empty()) return SPFF_OK;
+  for (int s : slots)
+    HIP_TRY(hipMemcpyAsync(p->slot(s) + p->L.theta, src(s), pin * rb, hipMemcpyDeviceToDevice, p->stream));
+  std::vector<SlotCtl> saved(p->host_ctl, p->host_ctl + p->S);
+  for (int s : slots) p->host_ctl[s].phase = phase;
+  HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * p->S, hipMemcpyHostToDevice, p->stream));
+  const int b = bucket_for(p, (int)slots.size());
+  spff_status lst = set_list(p, slots, b);
+  if (lst != SPFF_OK) return lst;
+  const bool prof = p->prof_on;
+  p->prof_on = false;
+  hipError_t e = enqueue_ticks(p, 1, p->stream, b);
+  p->prof_on = prof;
+  if (e != hipSuccess) return fail(SPFF_E_DEVICE, "operator launch failed: %s", hipGetErrorString(e));
+  for (int s : slots)
+    HIP_TRY(hipMemcpyAsync(dst(s), p->slot(s) + p->L.rm, pout * rb, hipMemcpyDeviceToDevice, p->stream));
+  // the pinned mirror is the source of the pending upload above: wait before
+  // reusing it, then restore the control blocks
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  std::copy(saved.begin(), saved.end(), p->host_ctl);
+  HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * p->S, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return SPFF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -998,18 +1034,27 @@ spff_status spff_load_step(spff_problem* p, const double eps_bar[3], spff_step_s
 spff_status spff_get_fields(spff_problem* p, int32_t index, uint32_t mask, void* const* dst) {
   if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
   if (index < -1 || index >= p->S) return fail(SPFF_E_INVALID, "index out of range");
-  if (mask & ~0x3Fu) return fail(SPFF_E_INVALID, "unknown field bits");
+  if (mask & ~0x7Fu) return fail(SPFF_E_INVALID, "unknown field bits");
   if (mask && !dst) return fail(SPFF_E_INVALID, "dst is NULL");
   const size_t n = p->n(), rb = p->rsize * n;
   const int s0 = index < 0 ? 0 : index, s1 = index < 0 ? p->S : index + 1;
   int k = 0;
-  void* out[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  for (int b = 0; b < 6; ++b)
+  void* out[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int b = 0; b < 7; ++b)
     if (mask & (1u << b)) {
       if (!dst[k]) return fail(SPFF_E_INVALID, "dst[%d] is NULL", k);
       out[b] = dst[k++];
     }
-  const size_t planes[6] = {1, 1, 3, 3, 1, 3};
+  const size_t planes[7] = {1, 1, 3, 3, 1, 3, 2};
+  if (out[6]) {
+    // displacement u* of eps*: one diagnostic tick over the selected slots
+    std::vector<int32_t> sl;
+    for (int s = s0; s < s1; ++s) sl.push_back(s);
+    spff_status st = run_diag(
+        p, PH_X_DISP, sl, 3, 2, [&](int s) { return static_cast<const unsigned char*>(p->slot(s) + p->L.eps); },
+        [&](int s) { return static_cast<unsigned char*>(out[6]) + (size_t)(s - s0) * 2 * rb; });
+    if (st != SPFF_OK) return st;
+  }
   for (int s = s0; s < s1; ++s) {
     const int j = s - s0;
     unsigned char* b = p->slot(s);
@@ -1078,38 +1123,16 @@ spff_status spff_set_state(spff_problem* p, const void* src_dev, const double* e
 
 spff_status spff_apply_operator(spff_problem* p, int32_t op, const void* in_dev, void* out_dev) {
   if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
-  if (op != SPFF_OP_PROJECT && op != SPFF_OP_NEG_LAPLACIAN) return fail(SPFF_E_INVALID, "unknown operator");
+  if (op != SPFF_OP_PROJECT && op != SPFF_OP_NEG_LAPLACIAN && op != SPFF_OP_DISPLACEMENT)
+    return fail(SPFF_E_INVALID, "unknown operator");
   if (!in_dev || !out_dev) return fail(SPFF_E_INVALID, "in/out is NULL");
-  const int planes = op == SPFF_OP_PROJECT ? 3 : 1;
-  const size_t rb = p->rsize * p->n();
-  for (int s = 0; s < p->S; ++s) {
-    if (p->host_ctl[s].phase != PH_IDLE) return fail(SPFF_E_BUSY, "slot %d is not idle", s);
-    HIP_TRY(hipMemcpyAsync(p->slot(s) + p->L.theta, static_cast<const unsigned char*>(in_dev) + s * planes * rb,
-                           planes * rb, hipMemcpyDeviceToDevice, p->stream));
-  }
-  std::vector<SlotCtl> saved(p->host_ctl, p->host_ctl + p->S);
-  for (int s = 0; s < p->S; ++s) p->host_ctl[s].phase = op == SPFF_OP_PROJECT ? PH_X_PROJ : PH_X_LAP;
-  HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * p->S, hipMemcpyHostToDevice, p->stream));
+  const int pin = op == SPFF_OP_NEG_LAPLACIAN ? 1 : 3;
+  const int pout = op == SPFF_OP_NEG_LAPLACIAN ? 1 : (op == SPFF_OP_DISPLACEMENT ? 2 : 3);
+  const int phase = op == SPFF_OP_PROJECT ? PH_X_PROJ : (op == SPFF_OP_DISPLACEMENT ? PH_X_DISP : PH_X_LAP);
   std::vector<int32_t> all(p->S);
   for (int s = 0; s < p->S; ++s) all[s] = s;
-  const int ball = (int)p->bucket_size.size() - 1;
-  spff_status lst = set_list(p, all, ball);
-  if (lst != SPFF_OK) return lst;
-  const bool prof = p->prof_on;
-  p->prof_on = false;
-  hipError_t e = enqueue_ticks(p, 1, p->stream, ball);
-  p->prof_on = prof;
-  if (e != hipSuccess) return fail(SPFF_E_DEVICE, "operator launch failed: %s", hipGetErrorString(e));
-  for (int s = 0; s < p->S; ++s)
-    HIP_TRY(hipMemcpyAsync(static_cast<unsigned char*>(out_dev) + s * planes * rb, p->slot(s) + p->L.rm,
-                           planes * rb, hipMemcpyDeviceToDevice, p->stream));
-  // the pinned mirror is the source of the pending upload above: wait before
-  // reusing it, then restore the control blocks (step statistics stay readable)
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  std::copy(saved.begin(), saved.end(), p->host_ctl);
-  HIP_TRY(hipMemcpyAsync(p->d_ctl(), p->host_ctl, sizeof(SlotCtl) * p->S, hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  return SPFF_OK;
+  return run_diag(p, phase, all, pin, pout, [&](int s) { return static_cast<const unsigned char*>(in_dev) + (size_t)s * pin * p->rsize * p->n(); },
+                  [&](int s) { return static_cast<unsigned char*>(out_dev) + (size_t)s * pout * p->rsize * p->n(); });
 }
 
 spff_status spff_profile_enable(spff_problem* p, int32_t enable) {

@@ -36,6 +36,7 @@ enum Phase : int32_t {
   PH_X_PROJ = 8,  // diagnostic: rm = G[theta] (3 planes)
   PH_X_LAP = 9,   // diagnostic: rm[0] = -lap theta[0]
   PH_TD_RESTORE = 10,  // time-discretized evolution: phi <- phi_n before a retry with dt/2
+  PH_X_DISP = 11,      // diagnostic: rm[0..1] = displacement u* of the strain field in theta (3 planes)
 };
 
 // ctl.flags bits

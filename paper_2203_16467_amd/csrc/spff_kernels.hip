@@ -32,6 +32,7 @@ __device__ __forceinline__ int phase_comps_row(int phase) {
     case PH_M_RES:
     case PH_M_CG:
     case PH_X_PROJ:
+    case PH_X_DISP:
       return 3;
     case PH_PF_ASM:
     case PH_PF_PQ:
@@ -330,6 +331,7 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       break;
     }
     case PH_X_PROJ:
+    case PH_X_DISP:
     case PH_X_LAP: {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -370,6 +372,7 @@ __device__ __forceinline__ void row_prologue_n(const RowCtx<real>& X, const Slot
     SPFF_PRO_CASE(PH_TD_RESTORE)
     SPFF_PRO_CASE(PH_STATS)
     SPFF_PRO_CASE(PH_X_PROJ)
+    SPFF_PRO_CASE(PH_X_DISP)
     SPFF_PRO_CASE(PH_X_LAP)
     default:
 #pragma unroll
@@ -478,6 +481,42 @@ __device__ __forceinline__ void project3_mode(real* a, real fx, real fy, bool ny
   project3(a, fx, fy);
 }
 
+// Displacement at one mode.  The strain is the unknown of the mechanics
+// problem (Sec. 3.1.1); the periodic displacement u* is recovered from the
+// compatible eps* by inverting eps^ = sym(i u^ (x) xi) at each mode:
+//   u^ = -i [ 2 eps^ xi / |xi|^2 - xi (xi . eps^ . xi) / |xi|^4 ],
+// xi = 2 pi (fx, fy) the gradient wavevector (Nyquist components zero), and
+// u^ = 0 where xi = 0 (the mean, and modes that are Nyquist in every
+// direction).  v[0..2] = (xx, yy, xy) in; v[0..1] = (x, y) out, v[2] = 0;
+// scale carries the 1/(nx ny) of the inverse transform.
+template <typename real>
+__device__ __forceinline__ void disp_part(const real* a, real gx, real gy, real* u) {
+  const real n2 = gx * gx + gy * gy;
+  if (n2 == real(0)) {
+    u[0] = u[1] = real(0);
+    return;
+  }
+  const real inv = real(1) / n2;
+  const real ex = a[0] * gx + a[2] * gy, ey = a[2] * gx + a[1] * gy;
+  const real s = (gx * ex + gy * ey) * inv;
+  u[0] = (real(2) * ex - gx * s) * inv;
+  u[1] = (real(2) * ey - gy * s) * inv;
+}
+
+template <typename real>
+__device__ __forceinline__ void disp3(cplx<real>* v, real fx, real fy, real scale) {
+  using C = cplx<real>;
+  const real gx = real(TWO_PI) * fx, gy = real(TWO_PI) * fy;
+  const real re[3] = {v[0].x, v[1].x, v[2].x}, im[3] = {v[0].y, v[1].y, v[2].y};
+  real ur[2], ui[2];
+  disp_part(re, gx, gy, ur);
+  disp_part(im, gx, gy, ui);
+  // -i (ur + i ui) = ui - i ur
+  v[0] = mk<C>(ui[0] * scale, -ur[0] * scale);
+  v[1] = mk<C>(ui[1] * scale, -ur[1] * scale);
+  v[2] = mk<C>(real(0), real(0));
+}
+
 template <typename real>
 __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                                  const SlotParam* __restrict__ prms,
@@ -490,13 +529,17 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
   const int s = list[blockIdx.y], g = blockIdx.x;
   if (s < 0) return;
   const int phase = ctls[s].phase;
-  int ncomp, mode;  // mode 0: projection, 1: Laplacian, 2: Parseval reduction
+  int ncomp, mode;  // mode 0: projection, 1: Laplacian, 2: Parseval reduction, 3: displacement
   switch (phase) {
     case PH_M_RES:
     case PH_M_CG:
     case PH_X_PROJ:
       ncomp = 3;
       mode = 0;
+      break;
+    case PH_X_DISP:
+      ncomp = 3;
+      mode = 3;
       break;
     case PH_X_LAP:
       ncomp = 1;
@@ -547,7 +590,12 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
     const real fy_grad = (2 * ky == ny) ? real(0) : fy_true;
     if (kx > 0) {
       const real fx = real(kx) / real(nx);
-      if (mode == 0) {
+      if (mode == 3) {
+        C a[3] = {buf[(0 * W + w) * stride + ky], buf[(1 * W + w) * stride + ky], buf[(2 * W + w) * stride + ky]};
+        disp3(a, fx, fy_grad, inv_n);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) buf[(c * W + w) * stride + ky] = a[c];
+      } else if (mode == 0) {
         C* a0 = buf + (0 * W + w) * stride + ky;
         C* a1 = buf + (1 * W + w) * stride + ky;
         C* a2 = buf + (2 * W + w) * stride + ky;
@@ -573,7 +621,24 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
       const bool self = (km == ky);
       // split packed column into A (kx = 0 column) and B (kx = nx/2 column)
       const real fxN_true = real(0.5);
-      if (mode == 0) {
+      if (mode == 3) {
+        C Aa[3], Bb[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C cp = buf[(c * W + w) * stride + ky];
+          const C cm = cconj(buf[(c * W + w) * stride + km]);
+          Aa[c] = cscale(cadd(cp, cm), real(0.5));
+          Bb[c] = cscale(cmulni(csub(cp, cm)), real(0.5));
+        }
+        // kx = 0 and kx = nx/2 (x-component of the gradient wavevector zero)
+        disp3(Aa, real(0), fy_grad, inv_n);
+        disp3(Bb, real(0), fy_grad, inv_n);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          buf[(c * W + w) * stride + ky] = cadd(Aa[c], cmuli(Bb[c]));
+          if (!self) buf[(c * W + w) * stride + km] = cadd(cconj(Aa[c]), cmuli(cconj(Bb[c])));
+        }
+      } else if (mode == 0) {
         C Aa[3], Bb[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -646,13 +711,17 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
   const int s = list[blockIdx.y], g = blockIdx.x;
   if (s < 0) return;
   const int phase = ctls[s].phase;
-  int ncomp, mode;  // mode 0: projection, 1: Laplacian, 2: Parseval reduction
+  int ncomp, mode;  // mode 0: projection, 1: Laplacian, 2: Parseval reduction, 3: displacement
   switch (phase) {
     case PH_M_RES:
     case PH_M_CG:
     case PH_X_PROJ:
       ncomp = 3;
       mode = 0;
+      break;
+    case PH_X_DISP:
+      ncomp = 3;
+      mode = 3;
       break;
     case PH_X_LAP:
     case PH_PF_ASM:
@@ -702,7 +771,12 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
       const int kys = ky < N / 2 ? ky : ky - N;
       const real fy_true = real(kys) / real(N);
       const real fy_grad = (2 * ky == N) ? real(0) : fy_true;
-      if (mode == 0) {
+      if (mode == 3) {
+        C a[3] = {v[0][m], v[1][m], v[2][m]};
+        disp3(a, fx, fy_grad, inv_n);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c][m] = a[c];
+      } else if (mode == 0) {
         real re[3] = {v[0][m].x, v[1][m].x, v[2][m].x}, im[3] = {v[0][m].y, v[1][m].y, v[2][m].y};
         project3_mode(re, fx, fy_grad, 2 * ky == N, nyq_free);
         project3_mode(im, fx, fy_grad, 2 * ky == N, nyq_free);
@@ -743,7 +817,19 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
       const int kys = ky < N / 2 ? ky : ky - N;
       const real fy_true = real(kys) / real(N);
       const real fy_grad = (2 * ky == N) ? real(0) : fy_true;
-      if (mode == 0) {
+      if (mode == 3) {
+        C Aa[3], Bb[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C cp = v[c][m], cm = cconj(Pn[c][m]);
+          Aa[c] = cscale(cadd(cp, cm), real(0.5));
+          Bb[c] = cscale(cmulni(csub(cp, cm)), real(0.5));
+        }
+        disp3(Aa, real(0), fy_grad, inv_n);
+        disp3(Bb, real(0), fy_grad, inv_n);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c][m] = cadd(Aa[c], cmuli(Bb[c]));
+      } else if (mode == 0) {
         real ar[3], ai[3], br[3], bi[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -861,6 +947,7 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
       break;
     }
     case PH_X_PROJ:
+    case PH_X_DISP:
     case PH_X_LAP: {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
@@ -890,6 +977,7 @@ __device__ __forceinline__ void row_epilogue_n(const RowCtx<real>& X, const Slot
     SPFF_EPI_CASE(PH_PF_ASM)
     SPFF_EPI_CASE(PH_PF_R)
     SPFF_EPI_CASE(PH_X_PROJ)
+    SPFF_EPI_CASE(PH_X_DISP)
     SPFF_EPI_CASE(PH_X_LAP)
     default:
       break;
@@ -1034,6 +1122,7 @@ __device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, con
     case PH_M_RES:
     case PH_M_CG:
     case PH_X_PROJ:
+    case PH_X_DISP:
       ncomp = 3;
       break;
     case PH_PF_ASM:
@@ -1140,6 +1229,7 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
     case PH_M_RES:
     case PH_M_CG:
     case PH_X_PROJ:
+    case PH_X_DISP:
       ncomp = 3;
       break;
     case PH_PF_ASM:
@@ -1531,6 +1621,7 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
       nphase = PH_PF_ASM;
       break;
     case PH_X_PROJ:
+    case PH_X_DISP:
     case PH_X_LAP:
       nphase = PH_IDLE;
       break;

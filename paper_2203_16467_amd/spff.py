@@ -26,12 +26,13 @@ EVOL_AM, EVOL_TIME, EVOL_NEAR_EQ = 0, 1, 2
 NYQ_ZERO, NYQ_FREE = 0, 1
 IRR_CRACK_SET, IRR_DAMAGE = 0, 1
 FP32, FP64 = 0, 1
-OP_PROJECT, OP_NEG_LAPLACIAN = 0, 1
-FIELD_PHI, FIELD_PHI_REF, FIELD_STRAIN, FIELD_STRESS, FIELD_PSI_PLUS, FIELD_EPS_STAR = (1, 2, 4, 8, 16, 32)
+OP_PROJECT, OP_NEG_LAPLACIAN, OP_DISPLACEMENT = 0, 1, 2
+FIELD_PHI, FIELD_PHI_REF, FIELD_STRAIN, FIELD_STRESS, FIELD_PSI_PLUS, FIELD_EPS_STAR, FIELD_DISP = (
+    1, 2, 4, 8, 16, 32, 64)
 FIELD_PLANES = {FIELD_PHI: 1, FIELD_PHI_REF: 1, FIELD_STRAIN: 3, FIELD_STRESS: 3, FIELD_PSI_PLUS: 1,
-                FIELD_EPS_STAR: 3}
+                FIELD_EPS_STAR: 3, FIELD_DISP: 2}
 FIELD_NAMES = {FIELD_PHI: "phi", FIELD_PHI_REF: "phi_ref", FIELD_STRAIN: "strain", FIELD_STRESS: "stress",
-               FIELD_PSI_PLUS: "psi_plus", FIELD_EPS_STAR: "eps_star"}
+               FIELD_PSI_PLUS: "psi_plus", FIELD_EPS_STAR: "eps_star", FIELD_DISP: "disp"}
 
 
 class SpffLibraryError(RuntimeError):
@@ -353,10 +354,17 @@ class Problem:
         return outs
 
     def apply_operator(self, op, x):
-        """spff_apply_operator: G (op=OP_PROJECT, x [B,3,ny,nx]) or -lap_N
-        (op=OP_NEG_LAPLACIAN, x [B,ny,nx]); returns a new tensor."""
+        """spff_apply_operator: G (op=OP_PROJECT, x [B,3,ny,nx]), -lap_N
+        (op=OP_NEG_LAPLACIAN, x [B,ny,nx]) or the displacement of a strain
+        field (op=OP_DISPLACEMENT, x [B,3,ny,nx] -> [B,2,ny,nx]); returns a
+        new tensor."""
         x = x.to(device=self.device, dtype=self.dtype).contiguous()
-        out = _torch().empty_like(x)
+        if op == OP_DISPLACEMENT:
+            if x.dim() != 4 or x.shape[1] != 3:
+                raise ValueError("displacement operator needs x of shape [B, 3, ny, nx]")
+            out = _torch().empty((x.shape[0], 2) + tuple(x.shape[2:]), dtype=self.dtype, device=self.device)
+        else:
+            out = _torch().empty_like(x)
         _check(lib().spff_apply_operator(self.handle, int(op), ctypes.c_void_p(x.data_ptr()),
                                          ctypes.c_void_p(out.data_ptr())))
         return out

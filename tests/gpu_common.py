@@ -66,7 +66,7 @@ def rel_l2(a, b):
 
 def gpu_fields(prob, index=0):
     mask = spff.FIELD_PHI | spff.FIELD_PHI_REF | spff.FIELD_STRAIN | spff.FIELD_STRESS | spff.FIELD_PSI_PLUS | \
-        spff.FIELD_EPS_STAR
+        spff.FIELD_EPS_STAR | spff.FIELD_DISP
     f = prob.get_fields(mask, index=index)
     return {k: v.double().cpu().numpy() for k, v in f.items()}
 
@@ -74,7 +74,7 @@ def gpu_fields(prob, index=0):
 def oracle_fields(o):
     return {"phi": o.phi.copy(), "phi_ref": o.phi_ref.copy(), "strain": tensor_to_planes(o.strain()),
             "stress": tensor_to_planes(o.stress()), "psi_plus": o.psi_plus(),
-            "eps_star": tensor_to_planes(o.eps_star)}
+            "eps_star": tensor_to_planes(o.eps_star), "disp": np.moveaxis(o.displacement(), -1, 0)}
 
 
 def set_oracle_from_gpu(o, prob, index=0):

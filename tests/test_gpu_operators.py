@@ -155,3 +155,35 @@ def test_invalid_plans_rejected():
         p.set_plan(5, base)
     assert p.get_plan(0) == base
     p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("nx,ny,kind", [(8, 8, "lds"), (16, 32, "lds"), (64, 64, "lds"), (256, 128, "reg"),
+                                        (512, 512, "reg"), (512, 512, "lds"), (2048, 1024, "reg"),
+                                        (2048, 2048, "lds")])
+def test_displacement_operator_matches_oracle(nx, ny, kind, precision):
+    """u* from a strain field (the SPFF_FIELD_DISP recovery) through the LDS
+    and register column kernels, including the packed kx = 0 / nx/2 column,
+    against the oracle's displacement recovery (itself pinned to hand-written
+    plane waves).  The input is an arbitrary symmetric field: the operator
+    returns the displacement of its compatible part."""
+    import torch
+    if precision == "fp64" and kind == "reg":
+        pytest.skip("register kernels are FP32 only")
+    print(f"displacement {nx}x{ny} {kind} {precision}", flush=True)
+    p = _problem(nx, ny, precision)
+    b = len(p.plan_buckets()) - 1
+    plan = p.get_plan(b)
+    if kind == "lds":
+        p.set_plan(b, dict(plan, col_kind=spff.FFT_LDS, cols=1, col_threads=256))
+    else:
+        assert plan["col_kind"] == spff.FFT_REG
+    rng = np.random.default_rng(nx * 3 + ny)
+    x = rng.standard_normal((p.B, 3, ny, nx)).astype(np.float64 if precision == "fp64" else np.float32)
+    out = p.apply_operator(spff.OP_DISPLACEMENT, torch.from_numpy(x).to(device())).double().cpu().numpy()
+    assert out.shape == (p.B, 2, ny, nx)
+    tol = 1e-12 if precision == "fp64" else 5e-6
+    for i in range(p.B):
+        want = np.moveaxis(osp.displacement_from_strain(planes_to_tensor(x[i].astype(np.float64))), -1, 0)
+        assert rel_l2(out[i], want) < tol, rel_l2(out[i], want)
+    p.close()

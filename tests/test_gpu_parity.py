@@ -1,7 +1,7 @@
 """GPU solver parity against the FP64 oracle (same seeded inputs).
 
 Contract for the FP32-bulk path (fields FP32, reductions FP64): strain /
-stress / eps* relative L2 <= 1e-4, phi max-abs <= 1e-3, crack set {phi > 0.9}
+stress / eps* / displacement u* relative L2 <= 1e-4, phi max-abs <= 1e-3, crack set {phi > 0.9}
 differing in <= 0.5% of pixels, energies relative <= 1e-4.  The FP64 path is
 held to 1e-7 (solver tolerances 1e-10 on both sides; what remains is the
 different operation order of the two FFT implementations and reductions).
@@ -37,12 +37,12 @@ def tol_fields(precision):
     return 1e-7 if precision == "fp64" else 1e-4
 
 
-def compare(gf, of, precision, phi_tol=None, what=("strain", "stress", "eps_star", "psi_plus")):
+def compare(gf, of, precision, phi_tol=None, what=("strain", "stress", "eps_star", "disp", "psi_plus")):
     t = tol_fields(precision)
     out = {}
     for k in what:
         scale = max(np.abs(of[k]).max(), 1e-30)
-        if k == "eps_star" and scale < 1e-12:
+        if k in ("eps_star", "disp") and scale < 1e-12:
             err = float(np.abs(gf[k] - of[k]).max())
             assert err < 1e-6, (k, err)
         else:
