@@ -1501,11 +1501,12 @@ spff_status spff_server_progress(spff_server* sv, int32_t max_rounds, int32_t* c
       any = true;
     }
     if (!any) break;
-    // 2. collect finished requests
-    const double t = now_ms();
+    // 2. collect finished requests; a request completes when the host has
+    // seen the end of its class's tick block
     for (SrvClass& C : sv->classes) {
       if (!C.inflight) continue;
       HIP_TRY(hipEventSynchronize(C.done_ev));
+      const double t = now_ms();
       C.inflight = false;
       spff_problem* e = C.eng;
       for (int s = 0; s < e->S; ++s) {

@@ -121,10 +121,15 @@ def test_poisson_driver_smoke():
     for kw, E in _problems()[:4]:
         pid = sv.register(spff.default_config(**kw), torch.as_tensor(E, device=device()))
         ramps[pid] = si.uniaxial_ramp(20, 0.2, 2.0)
-    rate, lat, wall, _ = serving.run_closed(sv, ramps, 2)
-    assert rate > 0 and len(lat) == 8
-    thr, lat2, offered = serving.run_poisson(sv, ramps, 2, rate=0.5 * rate, n_requests=12, seed=1)
-    assert len(lat2) == 12 and thr > 0
+    cursor = {pid: 2 for pid in ramps}
+    rate, lat, wall, _ = serving.run_closed(sv, ramps, cursor, 2)
+    assert rate > 0 and len(lat) == 8 and all(c == 4 for c in cursor.values())
+    thr, lat2, offered, res, cens = serving.run_poisson(sv, ramps, cursor, rate=0.5 * rate, n_requests=12,
+                                                        seed=1)
+    assert cens == 0
+    assert len(lat2) == 12 and thr > 0 and sum(cursor.values()) == 16 + 12
+    # latency from arrival includes the server's own submit-to-completion time
+    assert all(l >= r["wall_ms"] - 1e-6 for l, r in zip(lat2, res))
     sv.close()
 
 
