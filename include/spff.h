@@ -418,6 +418,39 @@ spff_status spff_server_info(const spff_server* sv, int32_t* nclasses, int32_t* 
 
 spff_status spff_server_destroy(spff_server* sv);
 
+/* ---------------------------------------------------------------------------
+ * Allocation-free load step, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  One load step (Algorithm 2 at macroscopic strain eps_bar,
+ * as spff_load_step) of one problem whose state lives in caller buffers;
+ * every solver scratch array (control block, parameters, FFT twiddles,
+ * partial sums, CG / BCCG vectors, half spectra) lives in a static device
+ * array of SPFF_STATIC_SCRATCH_BYTES owned by the library: one per device,
+ * allocated with the library's code on that device and held until the
+ * process ends.  The call allocates no device or pinned memory and builds
+ * no graph (use_graph is ignored); it launches kernels, copies and a memset
+ * on `stream` and synchronises it.
+ *   cfg:       as spff_create_problem; evolution must be SPFF_EVOL_AM.  The
+ *              scratch a grid needs is about 12 real planes plus partial
+ *              sums: FP32 up to 1024 x 1024, FP64 up to 1024 x 512 fit.
+ *   E_dev:     device, real[ny][nx], Young's modulus (> 0, finite).
+ *   state_dev: device, real[5][ny][nx] = (eps*[3], phi, phi_ref), the
+ *              layout of spff_get_state for one problem; read as the state
+ *              before the step and overwritten with the state after it.
+ *              phi and phi_ref must lie in [0, 1].
+ *   eps_bar:   host, double[3] (xx, yy, xy).
+ *   stats:     host, one spff_step_stats, or NULL.
+ * Errors: SPFF_E_INVALID (configuration, NULL pointers, E or phi out of
+ * range, a grid whose scratch exceeds SPFF_STATIC_SCRATCH_BYTES -- checked
+ * before any device work), SPFF_E_DEVICE.  The scratch keeps the last
+ * call's contents; every value a step reads is written first in that step.
+ * All calls on one device share its scratch: calls that overlap on one
+ * device (other threads, other streams) race and must be serialised by the
+ * caller. */
+#define SPFF_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+spff_status spff_load_step_static(const spff_config* cfg, const void* E_dev, void* state_dev,
+                                  const double eps_bar[3], spff_step_stats* stats, void* stream);
+
 /* Thread-local message for the last non-OK status ("" if none). */
 const char* spff_last_error(void);
 

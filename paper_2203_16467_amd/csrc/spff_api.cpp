@@ -634,7 +634,7 @@ spff_status slot_status(const SlotCtl& c) {
   return SPFF_OK;
 }
 
-void fill_stats(const spff_problem* p, const SlotCtl& c, spff_step_stats& o, double wall_ms) {
+void fill_stats(size_t npx, const SlotCtl& c, spff_step_stats& o, double wall_ms) {
   std::memset(&o, 0, sizeof(o));
   o.status = slot_status(c);
   o.am_iters = c.am;
@@ -660,7 +660,7 @@ void fill_stats(const spff_problem* p, const SlotCtl& c, spff_step_stats& o, dou
     if (std::fabs(c.eps_bar[k]) > std::fabs(c.eps_bar[kmax])) kmax = k;
   o.C_bar = c.eps_bar[kmax] != 0.0 ? c.sbar[kmax] / c.eps_bar[kmax] : NAN;
   o.phi_max = c.phi_max;
-  o.phi_mean = c.phi_sum / (double)p->n();
+  o.phi_mean = c.phi_sum / (double)npx;
   o.crack_px = (int64_t)std::llround(c.crack_px);
   o.wall_ms = wall_ms;
 }
@@ -994,7 +994,7 @@ static spff_status run_queue(spff_problem* p, int32_t nsteps, const double* eps_
         if (ss > 0 && worst == SPFF_OK) worst = ss;
         if (ss < 0) failed = true;
         const double ms = (double)(r.t_end - r.t_start) / p->clock_khz;
-        if (stats) fill_stats(p, c, stats[(size_t)s * nsteps + next[s] + j], ms);
+        if (stats) fill_stats(p->n(), c, stats[(size_t)s * nsteps + next[s] + j], ms);
         for (int m = 0; m < 3; ++m) p->last_eps_bar[3 * s + m] = r.eps_bar[m];
         p->last_advance[s] = r.advance;
       }
@@ -1233,6 +1233,126 @@ spff_status spff_destroy_problem(spff_problem* p) {
   if (p->host_list) (void)hipHostFree(p->host_list);
   delete p;
   return SPFF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One load step of one problem for spff_load_step_static: the state planes
+// are the caller's, every other array is carved out of the static scratch
+// with the single-slot scratch-only layout.  Host staging lives on this
+// stack frame and is consumed before the function returns (the stream is
+// synchronised after each group of uploads).
+template <typename real>
+spff_status static_step(const spff_config* cfg, const Layout& L, const LaunchGeom& G, unsigned char* ws,
+                        const void* E_dev, void* state_dev, const double* eb, spff_step_stats* stats,
+                        hipStream_t st) {
+  using C = typename HostCplx<real>::type;
+  const double t0 = now_ms();
+  const size_t n = (size_t)cfg->nx * cfg->ny;
+  SlotPtr<real> F{};
+  F.E = static_cast<const real*>(E_dev);
+  F.eps = static_cast<real*>(state_dev);
+  F.phi = F.eps + 3 * n;
+  F.phi_ref = F.eps + 4 * n;
+  unsigned char* slot = ws + L.slot0;
+  F.theta = reinterpret_cast<real*>(slot + L.theta);
+  F.rm = reinterpret_cast<real*>(slot + L.rm);
+  F.pm = reinterpret_cast<real*>(slot + L.pm);
+  F.spec = slot + L.spec;
+  const SlotParam P = make_param(cfg);
+  SlotCtl ctl;
+  std::memset(&ctl, 0, sizeof(ctl));
+  for (int k = 0; k < 3; ++k) ctl.eps_bar[k] = eb[k];
+  ctl.phase = PH_M_RES;
+  ctl.flags = FL_FIRST_OF_STEP;
+  ctl.dt = cfg->dt_max;
+  ctl.eta_dt = cfg->eta_over_dt;
+  ctl.gamma = 1.0;
+  const int32_t list0 = 0;
+  C tw[2048];
+  auto twiddles = [&](int m) {
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < m; ++k) {
+      const double a = -two_pi * (double)k / (double)m;
+      tw[k].x = (real)std::cos(a);
+      tw[k].y = (real)std::sin(a);
+    }
+  };
+  SlotCtl* d_ctl = reinterpret_cast<SlotCtl*>(ws + L.ctl);
+  SlotParam* d_prm = reinterpret_cast<SlotParam*>(ws + L.prm);
+  SlotPtr<real>* d_ptr = reinterpret_cast<SlotPtr<real>*>(ws + L.ptr);
+  int32_t* d_list = reinterpret_cast<int32_t*>(ws + L.list);
+  unsigned int* d_bad = reinterpret_cast<unsigned int*>(ws + L.bad);
+  C* twx = reinterpret_cast<C*>(ws + L.twx);
+  C* twy = reinterpret_cast<C*>(ws + L.twy);
+  HIP_TRY(hipMemcpyAsync(d_ptr, &F, sizeof(F), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_prm, &P, sizeof(P), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_list, &list0, sizeof(list0), hipMemcpyHostToDevice, st));
+  twiddles(cfg->nx);
+  HIP_TRY(hipMemcpyAsync(twx, tw, sizeof(C) * cfg->nx, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  twiddles(cfg->ny);
+  HIP_TRY(hipMemcpyAsync(twy, tw, sizeof(C) * cfg->ny, hipMemcpyHostToDevice, st));
+  // inputs: E > 0 and finite, phi and phi_ref in [0, 1]
+  HIP_TRY(hipMemsetAsync(d_bad, 0, 2 * sizeof(unsigned int), st));
+  HIP_TRY(launch_validate<real>(F.E, n, 0.0, -1e300, 1e300, d_bad, st));
+  HIP_TRY(launch_validate<real>(F.phi, 2 * n, -1e300, 0.0, 1.0, d_bad + 1, st));
+  unsigned int bad[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (bad[0]) return fail(SPFF_E_INVALID, "E has %u non-positive or non-finite entries", bad[0]);
+  if (bad[1]) return fail(SPFF_E_INVALID, "phi / phi_ref have %u entries outside [0, 1]", bad[1]);
+  double* prow = reinterpret_cast<double*>(ws + L.prow);
+  double* pcol = reinterpret_cast<double*>(ws + L.pcol);
+  double* pinv = reinterpret_cast<double*>(ws + L.pinv);
+  const int K = cfg->ticks_per_sync;
+  for (;;) {
+    for (int i = 0; i < K; ++i) {
+      hipError_t e = launch_tick<real>(G, d_list, d_ptr, d_prm, d_ctl, twx, twy, prow, pcol, pinv, nullptr, nullptr,
+                                       nullptr, nullptr, nullptr, st);
+      if (e != hipSuccess) return fail(SPFF_E_DEVICE, "tick launch failed: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemcpyAsync(&ctl, d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctl.phase == PH_IDLE) break;
+  }
+  if (stats) fill_stats(n, ctl, *stats, now_ms() - t0);
+  const spff_status ss = slot_status(ctl);
+  if (ss < 0) g_last_error = "a reduction produced NaN or Inf";
+  return ss;
+}
+
+}  // namespace
+
+extern "C" {
+
+spff_status spff_load_step_static(const spff_config* cfg, const void* E_dev, void* state_dev,
+                                  const double eps_bar[3], spff_step_stats* stats, void* stream) {
+  spff_status st = check_config(cfg);
+  if (st != SPFF_OK) return st;
+  if (!E_dev || !state_dev || !eps_bar) return fail(SPFF_E_INVALID, "E_dev, state_dev and eps_bar must not be NULL");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(eps_bar[k])) return fail(SPFF_E_INVALID, "eps_bar must be finite");
+  if (cfg->evolution != SPFF_EVOL_AM)
+    return fail(SPFF_E_INVALID, "spff_load_step_static runs alternating minimisation (SPFF_EVOL_AM) only");
+  const size_t rsize = cfg->precision == SPFF_FP64 ? 8 : 4;
+  const Layout L = layout(cfg, 1, rsize, true);
+  if (L.total > SPFF_STATIC_SCRATCH_BYTES)
+    return fail(SPFF_E_INVALID, "a %d x %d %s problem needs %zu bytes of scratch; the static scratch holds %zu",
+                cfg->nx, cfg->ny, rsize == 8 ? "FP64" : "FP32", L.total, (size_t)SPFF_STATIC_SCRATCH_BYTES);
+  const spff_plan pl = auto_plan(cfg, 1, 2 * rsize);
+  const LaunchGeom G = geom_from_plan(cfg, 1, 2 * rsize, pl);
+  if (G.lds_row > LDS_MAX || G.lds_col > LDS_MAX) return fail(SPFF_E_INVALID, "grid too large for LDS tiles");
+  void* ws = nullptr;
+  hipError_t e = static_scratch(&ws);
+  if (e != hipSuccess) return fail(SPFF_E_DEVICE, "static scratch address: %s", hipGetErrorString(e));
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  return cfg->precision == SPFF_FP64 ? static_step<double>(cfg, L, G, w, E_dev, state_dev, eps_bar, stats, hs)
+                                     : static_step<float>(cfg, L, G, w, E_dev, state_dev, eps_bar, stats, hs);
 }
 
 const char* spff_last_error(void) { return g_last_error.c_str(); }
@@ -1514,7 +1634,7 @@ spff_status spff_server_progress(spff_server* sv, int32_t max_rounds, int32_t* c
         if (id < 0 || e->host_ctl[s].phase != PH_IDLE) continue;
         SrvProblem& P = sv->probs[id];
         spff_step_stats o;
-        fill_stats(e, e->host_ctl[s], o, t - P.t_submit);
+        fill_stats(e->n(), e->host_ctl[s], o, t - P.t_submit);
         P.dt = e->host_ctl[s].dt;
         P.ne_flag = e->host_ctl[s].ne_flag;
         sv->done[P.ticket] = o;

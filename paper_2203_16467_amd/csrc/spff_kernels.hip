@@ -14,8 +14,10 @@
 // components; a column kernel work-group owns W consecutive kx columns.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
+#include "spff.h"
 #include "spff_device.hpp"
 #include "spff_engine.hpp"
 #include "spff_launch.hpp"
@@ -2092,5 +2094,34 @@ template hipError_t launch_fields<float>(const SlotPtr<float>*, const SlotParam*
                                          float*, float*, float*, hipStream_t);
 template hipError_t launch_fields<double>(const SlotPtr<double>*, const SlotParam*, const SlotCtl*, int, int,
                                           double*, double*, double*, hipStream_t);
+
+
+// ===========================================================================
+// Library-owned scratch of the allocation-free entry point
+// (spff_load_step_static): one array per device, held until the process
+// ends, shared by every call on that device.  In host code the array's name
+// is not a device address; static_scratch() returns the address of the
+// current device's copy, taken once per device with that device current.
+// ===========================================================================
+static __device__ __align__(256) unsigned char scratch[SPFF_STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void** out) {
+  constexpr int MAX_DEVICES = 64;
+  static std::mutex mu;
+  static void* addr[MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = ptr;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
 
 }  // namespace spff

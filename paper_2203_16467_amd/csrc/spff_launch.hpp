@@ -39,4 +39,8 @@ template <typename real>
 hipError_t launch_fields(const SlotPtr<real>* ptrs, const SlotParam* prms, const SlotCtl* ctls, int slot, int n,
                          real* strain, real* stress_out, real* psi, hipStream_t st);
 
+// Address of the current device's copy of the library-owned scratch array
+// (SPFF_STATIC_SCRATCH_BYTES bytes, 256-byte aligned).
+hipError_t static_scratch(void** out);
+
 }  // namespace spff

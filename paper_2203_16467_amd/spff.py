@@ -157,6 +157,8 @@ _SIGS = {
     "spff_plan_buckets": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "spff_get_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Plan)]),
     "spff_set_plan": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Plan)]),
+    "spff_load_step_static": (ctypes.c_int, [ctypes.POINTER(Config), _P, _P, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(StepStats), _P]),
     "spff_last_error": (ctypes.c_char_p, []),
     "spff_version": (ctypes.c_char_p, []),
 }
@@ -421,6 +423,31 @@ class Problem:
             eb = np.ascontiguousarray(np.broadcast_to(np.asarray(eps_bar, np.float64), (self.B, 3)))
             ebp = eb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         _check(lib().spff_set_state(self.handle, ctypes.c_void_p(state.data_ptr()), ebp))
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def load_step_static(cfg, E, state, eps_bar, stream=None):
+    """spff_load_step_static: one load step of one problem whose state
+    (device tensor [5, ny, nx] = eps*[3], phi, phi_ref, of the config's real
+    type, contiguous) is updated in place; all solver scratch is the
+    library's static device array (no allocation by the library or here).
+    Returns (status, stats dict)."""
+    dt = _real_dtype(cfg)
+    if not (E.is_cuda and state.is_cuda) or E.dtype != dt or state.dtype != dt:
+        raise ValueError("E and state must be device tensors of the configuration's real type")
+    if tuple(E.shape[-2:]) != (cfg.ny, cfg.nx) or tuple(state.shape) != (5, cfg.ny, cfg.nx):
+        raise ValueError("E must be [ny, nx] and state [5, ny, nx]")
+    if not (E.is_contiguous() and state.is_contiguous()):
+        raise ValueError("E and state must be contiguous")
+    eb = (ctypes.c_double * 3)(*[float(v) for v in eps_bar])
+    out = StepStats()
+    st = lib().spff_load_step_static(ctypes.byref(cfg), ctypes.c_void_p(E.data_ptr()),
+                                     ctypes.c_void_p(state.data_ptr()), eb, ctypes.byref(out),
+                                     _stream_ptr(stream))
+    _check(st)
+    return st, out.to_dict()
 
 
 class Server:

@@ -159,3 +159,24 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_static_step_rejects_before_any_device_work():
+    """spff_load_step_static checks its configuration and the size of the
+    scratch the grid needs against the static array before it touches a
+    device (dummy pointers are never dereferenced)."""
+    L = spff.lib()
+    eb = (ctypes.c_double * 3)(0.0, 0.01, 0.0)
+    dummy = ctypes.c_void_p(256)
+    for kw in (dict(nx=2048, ny=2048), dict(nx=1024, ny=1024, precision=spff.FP64),
+               dict(nx=64, ny=64, evolution=spff.EVOL_TIME), dict(nx=100, ny=64)):
+        cfg = spff.default_config(**kw)
+        st = L.spff_load_step_static(ctypes.byref(cfg), dummy, dummy, eb, None, None)
+        assert st == spff.E_INVALID, kw
+    cfg = spff.default_config(nx=2048, ny=2048)
+    L.spff_load_step_static(ctypes.byref(cfg), dummy, dummy, eb, None, None)
+    assert "static scratch" in spff.last_error()
+    cfg = spff.default_config(nx=64, ny=64)
+    assert L.spff_load_step_static(ctypes.byref(cfg), None, dummy, eb, None, None) == spff.E_INVALID
+    bad = (ctypes.c_double * 3)(0.0, float("nan"), 0.0)
+    assert L.spff_load_step_static(ctypes.byref(cfg), dummy, dummy, bad, None, None) == spff.E_INVALID
