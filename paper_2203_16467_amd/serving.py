@@ -23,11 +23,13 @@ def _has_next(ramps, cursor, pid):
     return cursor[pid] < len(ramps[pid])
 
 
-def run_closed(server, ramps, cursor, steps_per_problem):
+def run_closed(server, ramps, cursor, steps_per_problem, deadline=None):
     """Saturation run: the next `steps_per_problem` load steps of every
     problem (fewer where its ramp ends) are submitted at once, in ramp order
-    per problem.  Returns (requests/s, latencies ms, wall s, per-request
-    stats dicts)."""
+    per problem.  `deadline` (a time.perf_counter() value) stops the run;
+    requests still running then stay queued in the server.  Returns
+    (completed requests/s, latencies ms, wall s, per-request stats dicts,
+    tickets still running)."""
     inflight, lat, results = {}, [], []
     t0 = time.perf_counter()
     for pid in ramps:
@@ -37,7 +39,7 @@ def run_closed(server, ramps, cursor, steps_per_problem):
             t = server.submit(pid, ramps[pid][cursor[pid]])
             cursor[pid] += 1
             inflight[t] = (pid, (time.perf_counter() - t0) * 1e3)
-    while inflight:
+    while inflight and (deadline is None or time.perf_counter() < deadline):
         server.progress(1)
         for t, (pid, wait_ms) in list(inflight.items()):
             st = server.poll(t)
@@ -46,7 +48,7 @@ def run_closed(server, ramps, cursor, steps_per_problem):
                 results.append(dict(st, pid=pid, ticket=t))
                 del inflight[t]
     wall = time.perf_counter() - t0
-    return len(lat) / wall, lat, wall, results
+    return len(lat) / wall, lat, wall, results, sorted(inflight)
 
 
 def run_poisson(server, ramps, cursor, rate, n_requests, seed=0, warmup=0, arrivals=None, deadline=None):

@@ -122,7 +122,8 @@ def test_poisson_driver_smoke():
         pid = sv.register(spff.default_config(**kw), torch.as_tensor(E, device=device()))
         ramps[pid] = si.uniaxial_ramp(20, 0.2, 2.0)
     cursor = {pid: 2 for pid in ramps}
-    rate, lat, wall, _ = serving.run_closed(sv, ramps, cursor, 2)
+    rate, lat, wall, _, left = serving.run_closed(sv, ramps, cursor, 2)
+    assert left == []
     assert rate > 0 and len(lat) == 8 and all(c == 4 for c in cursor.values())
     thr, lat2, offered, res, cens = serving.run_poisson(sv, ramps, cursor, rate=0.5 * rate, n_requests=12,
                                                         seed=1)
@@ -185,3 +186,81 @@ def test_evolution_state_is_kept_per_problem(mode):
     else:
         assert any(s["gamma"] < 1.0 for h in hist.values() for s in h)
     sv.close()
+
+
+def _onset_step(kw, E, ramp, chunk=40):
+    """First load step whose phase field leaves zero (AT1: onset of damage),
+    running the problem alone with alternating minimisation capped as in kw."""
+    import torch
+    p = spff.Problem(torch.as_tensor(E, device=device()), spff.default_config(**kw))
+    try:
+        for c0 in range(0, len(ramp), chunk):
+            _, stats = p.run_sequence(ramp[c0:c0 + chunk])
+            for k, s in enumerate(stats[0]):
+                if s["phi_max"] > 0.0:
+                    return c0 + k
+    finally:
+        p.close()
+    return None
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_served_nucleation_step_large_grids(n):
+    """The serving workload's large grids (C4 recipe: E = max(1 + 0.1 z,
+    0.5), corr 8 px, AT1, strain-spectral split) at the load step where the
+    phase field first leaves zero: a problem served in a mix with a smaller
+    one (requests walking its ramp from the start) ends that step bit for bit
+    where the same problem run alone does, and the alone step matches the
+    FP64 oracle started from the same state (FP32 contract).  Alternating
+    minimisation is capped at 2 iterations on every side (the uncapped
+    onset of a crack runs hundreds of iterations, a path FP32 and FP64 need
+    not share iteration by iteration; the oracle at 1024^2 takes minutes per
+    uncapped step)."""
+    import torch
+    ramp = si.uniaxial_ramp(200, 0.2, 2.0)
+    E = si.young_modulus(n, 8.0, 0.1, 4000 + n // 256)
+    kw = dict(nx=n, ny=n, at=1, max_am=2, **PLAN)
+    k = _onset_step(kw, E, ramp)
+    assert k is not None and k > 20
+    print(f"{n}^2: onset at load step {k}", flush=True)
+    # alone: to step k - 1, snapshot, step k
+    p = spff.Problem(torch.as_tensor(E, device=device()), spff.default_config(**kw))
+    p.run_sequence(ramp[:k])
+    before, eb = p.get_state()
+    _, alone = p.load_step(ramp[k])
+    after, _ = p.get_state()
+    assert alone[0]["phi_max"] > 0.0 and alone[0]["bccg_iters"] > 0
+    # served in a mix with a small AT2 problem
+    sv = spff.Server(arena_bytes=int(24 * n * n * 4 + (64 << 20)), ticks_per_sync=4, use_graph=1)
+    small = sv.register(spff.default_config(nx=128, ny=128, at=2, **PLAN),
+                        torch.as_tensor(si.young_modulus(128, 8.0, 0.1, 4100), device=device()))
+    pid = sv.register(spff.default_config(**kw), torch.as_tensor(E, device=device()))
+    tks = [sv.submit(pid, ramp[j]) for j in range(k + 1)]
+    for j in range(2 * k):
+        sv.submit(small, ramp[j % 120])
+    while sv.progress(8)[1] > 0:
+        pass
+    served = [sv.poll(t) for t in tks][-1]
+    f = sv.get_fields(pid, spff.FIELD_PHI | spff.FIELD_PHI_REF | spff.FIELD_EPS_STAR)
+    got = torch.cat([f["eps_star"], f["phi"], f["phi_ref"]]).cpu()
+    assert torch.equal(got, after[0].cpu())
+    for key in ("am_iters", "cg_iters", "bccg_iters", "F_e", "F_f"):
+        assert served[key] == alone[0][key], key
+    sv.close()
+    # alone against the oracle from the same state
+    from gpu_common import oracle_for, planes_to_tensor, gpu_fields, oracle_fields
+    from oracle import constitutive as ocm
+    from test_gpu_parity import compare
+    cfg = spff.default_config(**kw)
+    o = oracle_for(E, cfg, tol=1e-8, max_am=2)
+    s = before[0].double().cpu().numpy()
+    o.set_state({"eps_star": planes_to_tensor(s[0:3]), "phi": s[3], "phi_ref": s[4],
+                 "eps_bar": ocm.sym_tensor(*eb[0])})
+    ost = o.load_step(ramp[k])
+    cmp = compare(gpu_fields(p), oracle_fields(o), "fp32")
+    print(n, k, cmp, alone[0]["am_iters"], ost["am"], alone[0]["bccg_iters"], ost["bccg"], flush=True)
+    assert alone[0]["am_iters"] == ost["am"]
+    tot = ost["F_e"] + ost["F_f"]
+    assert abs(alone[0]["F_e"] - ost["F_e"]) <= 1e-4 * tot
+    assert abs(alone[0]["F_f"] - ost["F_f"]) <= 1e-4 * tot
+    p.close()

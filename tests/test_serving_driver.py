@@ -79,7 +79,7 @@ def test_closed_and_poisson_walk_the_ramps(monkeypatch):
     sv = FakeServer(clock, block=0.01)
     ramps = _ramps(3, 5)
     cursor = {pid: 0 for pid in ramps}
-    serving.run_closed(sv, ramps, cursor, 2)
+    assert serving.run_closed(sv, ramps, cursor, 2)[4] == []
     assert cursor == {0: 2, 1: 2, 2: 2}
     serving.run_poisson(sv, ramps, cursor, rate=100.0, n_requests=9, seed=1)
     assert sum(cursor.values()) == 15 and all(c == 5 for c in cursor.values())
