@@ -264,8 +264,9 @@ spff_status spff_get_fields(spff_problem* p, int32_t index, uint32_t mask, void*
 
 /* State = (eps*[3], phi, phi_ref) planes: real[nbatch][5][ny][nx] on the
  * device, plus the macroscopic strain of the last step (host double[nbatch][3],
- * may be NULL).  get copies out, set copies in (no validation of values
- * beyond finiteness is made). */
+ * may be NULL).  get copies out, set copies in; set checks that every value
+ * (and eps_bar) is finite and fails with SPFF_E_INVALID, state unchanged,
+ * otherwise (no other validation of values is made). */
 size_t spff_state_bytes(const spff_problem* p);
 spff_status spff_get_state(spff_problem* p, void* dst_dev, double* eps_bar_host);
 spff_status spff_set_state(spff_problem* p, const void* src_dev, const double* eps_bar_host);
@@ -323,9 +324,10 @@ spff_status spff_profile_read(spff_problem* p, spff_profile* out);
  * sums (so results by rounding only), never the arithmetic.
  *   row_kind / col_kind: SPFF_FFT_LDS -- Stockham radix-4/2 passes through
  *     LDS, one point pair per thread (any size); SPFF_FFT_REG -- radix-8
- *     Stockham on registers, 8 points per lane (16 for 1024-point
- *     transforms), wavefront-local LDS exchanges (FP32 only; rows:
- *     128 <= nx <= 2048, columns: ny in {128, 256, 512, 1024});
+ *     Stockham on registers, 8 points per lane (16 for 1024- and
+ *     2048-point transforms), wavefront-local LDS exchanges (a 2048-point
+ *     column spans the two wavefronts of its work-group) (FP32 only; rows:
+ *     128 <= nx <= 2048, columns: ny in {128, 256, 512, 1024, 2048});
  *     SPFF_FFT_REG4 (rows only) -- 4 points per lane and radix-4 passes
  *     (twice the lanes per row, for launches with few problems;
  *     128 <= nx <= 512).
@@ -335,8 +337,8 @@ spff_status spff_profile_read(spff_problem* p, spff_profile* out);
  *     (64, 128 or 256, times 8 covering the transform); for the register
  *     kinds derived as rows * (lanes per row: nx/16, nx/32 for nx = 2048,
  *     nx/8 for SPFF_FFT_REG4) and cols * (lanes per column: ny/8, ny/16
- *     for ny = 1024), which must be a power of two in [64, 256] -- filled
- *     in on return. */
+ *     for ny >= 1024), which must be a power of two in [64, 256] (cols = 1
+ *     for ny = 2048) -- filled in on return. */
 enum { SPFF_FFT_LDS = 1, SPFF_FFT_REG = 2, SPFF_FFT_REG4 = 3 };
 typedef struct spff_plan {
   int32_t row_kind, rows, row_threads;

@@ -68,9 +68,10 @@ def col_candidates(cfg):
         for T in (128, 256):
             if T * 8 >= cfg.ny and 3 * W * (cfg.ny + 1) * csize <= LDS_BYTES // 2:
                 out.append((spff.FFT_LDS, W, T))
-    if cfg.precision == spff.FP32 and cfg.ny in (128, 256, 512, 1024):
+    if cfg.precision == spff.FP32 and cfg.ny in (128, 256, 512, 1024, 2048):
         L = cfg.ny // (8 if cfg.ny <= 512 else 16)
-        for W in _pow2_range(max(1, 64 // L), THREADS // L):
+        # a 2048-point column (128 lanes) is alone in its work-group
+        for W in _pow2_range(max(1, 64 // L), 1 if L > 64 else THREADS // L):
             if W <= M:
                 out.append((spff.FFT_REG, W, W * L))
     return out

@@ -123,11 +123,17 @@ bool reg_rows_ok(const spff_config* c, int kind = SPFF_FFT_REG) {
   return c->precision == SPFF_FP32 && M >= 64 && M <= (kind == SPFF_FFT_REG4 ? 256 : 1024);
 }
 bool reg_cols_ok(const spff_config* c) {
-  return c->precision == SPFF_FP32 && (c->ny == 128 || c->ny == 256 || c->ny == 512 || c->ny == 1024);
+  return c->precision == SPFF_FP32 &&
+         (c->ny == 128 || c->ny == 256 || c->ny == 512 || c->ny == 1024 || c->ny == 2048);
 }
 // points per lane of the register kinds: 8 up to 512-point transforms, 16
-// for 1024 (a group never exceeds one wavefront); REG4 rows: 4
+// for 1024 and 2048 (a 2048-point column takes two wavefronts, alone in its
+// work-group); REG4 rows: 4
 int reg_points(int n) { return n > 512 ? 16 : 8; }
+// columns per work-group of the register column kind: at least one
+// wavefront, at most THREADS lanes; a column wider than a wavefront alone
+int reg_cols_min(int Lc) { return Lc >= 64 ? 1 : 64 / Lc; }
+int reg_cols_max(int Lc) { return Lc > 64 ? 1 : THREADS / Lc; }
 
 spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
   spff_plan pl{};
@@ -157,7 +163,7 @@ spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
   // that the partial sums (hence the results) do not depend on the batch
   if (reg_cols_ok(c)) {
     const int Lc = c->ny / reg_points(c->ny);
-    const int wmin = 64 / Lc, wmax = THREADS / Lc;
+    const int wmin = reg_cols_min(Lc), wmax = reg_cols_max(Lc);
     if (wmin <= M) {
       int Wr = wmin;
       if (c->plan_cols > 0) {
@@ -233,11 +239,11 @@ spff_status check_plan(const spff_config* c, spff_plan* pl, size_t csize) {
   }
   if (pl->col_kind == SPFF_FFT_REG) {
     if (!reg_cols_ok(c))
-      return fail(SPFF_E_INVALID, "register column FFT needs FP32 and ny in {128, 256, 512, 1024}");
+      return fail(SPFF_E_INVALID, "register column FFT needs FP32 and ny in {128, ..., 2048}");
     const int Lc = c->ny / reg_points(c->ny);
-    if (!pow2(pl->cols) || pl->cols * Lc < 64 || pl->cols * Lc > THREADS || pl->cols > M)
-      return fail(SPFF_E_INVALID, "register column FFT: cols * lanes per column must be a power of two in [64, %d]",
-                  THREADS);
+    if (!pow2(pl->cols) || pl->cols < reg_cols_min(Lc) || pl->cols > reg_cols_max(Lc) || pl->cols > M)
+      return fail(SPFF_E_INVALID, "register column FFT: cols * lanes per column must be a power of two in [64, %d] "
+                                  "(one column per work-group for 2048 points)", THREADS);
     pl->col_threads = pl->cols * Lc;
   } else if (pl->col_kind == SPFF_FFT_LDS) {
     if (!pow2(pl->cols) || pl->cols > M) return fail(SPFF_E_INVALID, "cols must be a power of two <= nx/2");
@@ -1102,7 +1108,27 @@ spff_status spff_get_state(spff_problem* p, void* dst_dev, double* eps_bar_host)
 spff_status spff_set_state(spff_problem* p, const void* src_dev, const double* eps_bar_host) {
   if (!p) return fail(SPFF_E_INVALID, "problem is NULL");
   if (!src_dev) return fail(SPFF_E_INVALID, "src is NULL");
+  if (eps_bar_host)
+    for (int k = 0; k < 3 * p->S; ++k)
+      if (!std::isfinite(eps_bar_host[k])) return fail(SPFF_E_INVALID, "eps_bar must be finite");
   const size_t rb = p->rsize * p->n();
+  // every value finite (checked before anything is copied: an error leaves
+  // the state unchanged)
+  {
+    unsigned int* bad = reinterpret_cast<unsigned int*>(p->ws + p->L.bad);
+    const size_t cnt = (size_t)p->S * 5 * p->n();
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned int), p->stream));
+    hipError_t e = p->cfg.precision == SPFF_FP64
+                       ? launch_validate<double>(static_cast<const double*>(src_dev), cnt, -1e300, -1e300, 1e300,
+                                                 bad, p->stream)
+                       : launch_validate<float>(static_cast<const float*>(src_dev), cnt, -1e300, -1e300, 1e300, bad,
+                                                p->stream);
+    if (e != hipSuccess) return fail(SPFF_E_DEVICE, "validation launch failed: %s", hipGetErrorString(e));
+    unsigned int hbad = 0;
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    if (hbad) return fail(SPFF_E_INVALID, "state has %u non-finite entries", hbad);
+  }
   for (int s = 0; s < p->S; ++s) {
     const unsigned char* d = static_cast<const unsigned char*>(src_dev) + (size_t)s * 5 * rb;
     unsigned char* b = p->slot(s);

@@ -192,8 +192,11 @@ __device__ void fft_lds(cplx<real>* buf, int M, int ntrans, int stride, const cp
 // the last pass, whose outputs j + s N/RD are the lane's own slots.  So a
 // forward transform ends, and an inverse one starts, in the load layout: a
 // per-mode operator in between needs no data movement, and global loads and
-// stores of x[l + m L] are coalesced across lanes.  Groups never span
-// wavefronts (L <= 64), so an exchange is ordered by wave_sync() alone.
+// stores of x[l + m L] are coalesced across lanes.  A group of L <= 64 lanes
+// lies in one wavefront, so an exchange is ordered by wave_sync() alone; a
+// group of L = 128 lanes (2048-point columns) spans the two wavefronts of
+// its work-group, which then holds that one group only, and an exchange is
+// ordered by a work-group barrier.
 // tw holds the (N twmul)-th roots of unity exp(-2 pi i e / (N twmul)); the
 // inverse (INV) uses conjugates and is unnormalised.
 // ---------------------------------------------------------------------------
@@ -201,6 +204,16 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Barrier of a group of L lanes exchanging through LDS (see above).
+template <int L>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (L <= 64) {
+    wave_sync();
+  } else {
+    __syncthreads();
+  }
 }
 
 // LDS index of element i of an exchange area (one pad slot per 8 elements,
@@ -273,10 +286,10 @@ __device__ __forceinline__ void reg_pass(cplx<real> (&v)[E], cplx<real>* x, int 
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = o[m];
   } else {
-    wave_sync();
+    group_sync<L>();
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = x[xpad(lane + m * L)];
-    wave_sync();
+    group_sync<L>();
   }
 }
 

@@ -706,8 +706,11 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
                                             const cplx<real>* __restrict__ twy, double* __restrict__ part, int nx,
                                             int ngc, int nyq_free) {
   using C = cplx<real>;
-  // eight points per lane up to 512-point columns, sixteen for 1024
-  constexpr int E = N <= 512 ? 8 : N / 64, L = N / E;
+  // eight points per lane up to 512-point columns, sixteen for 1024 (one
+  // wavefront per column) and 2048 (two wavefronts: the work-group holds
+  // this one column, so every barrier below is reached by all its threads)
+  constexpr int E = N <= 512 ? 8 : 16, L = N / E;
+  static_assert(L <= 64 || N == 2048, "groups wider than a wavefront are 2048-point columns");
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_COL];
   const int s = list[blockIdx.y], g = blockIdx.x;
@@ -802,10 +805,21 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (c < ncomp) {
+        if constexpr (L <= 64) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-          const real px = __shfl(v[c][i].x, src, L), py = __shfl(v[c][i].y, src, L);
-          Pn[c][E - 1 - i] = mk<C>(px, py);
+          for (int i = 0; i < E; ++i) {
+            const real px = __shfl(v[c][i].x, src, L), py = __shfl(v[c][i].y, src, L);
+            Pn[c][E - 1 - i] = mk<C>(px, py);
+          }
+        } else {
+          // the partner lane may sit in the other wavefront: exchange
+          // through the column's LDS area (free between transforms)
+#pragma unroll
+          for (int i = 0; i < E; ++i) x[xpad(lane + i * L)] = v[c][i];
+          group_sync<L>();
+#pragma unroll
+          for (int i = 0; i < E; ++i) Pn[c][E - 1 - i] = x[xpad(src + i * L)];
+          group_sync<L>();
         }
         if (lane == 0) {
 #pragma unroll
@@ -2018,8 +2032,12 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
         hipLaunchKernelGGL((k_colr<real, 512>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
                            twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
         break;
-      default:
+      case 1024:
         hipLaunchKernelGGL((k_colr<real, 1024>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
+                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
+        break;
+      default:
+        hipLaunchKernelGGL((k_colr<real, 2048>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
                            twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
         break;
       }

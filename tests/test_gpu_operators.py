@@ -23,7 +23,7 @@ def _problem(nx, ny, precision, B=2):
 
 @pytest.mark.parametrize("nyquist", ["zero", "free"])
 @pytest.mark.parametrize("nx,ny,kind", [(16, 32, "lds"), (64, 64, "lds"), (256, 128, "reg"), (512, 512, "reg"),
-                                        (2048, 1024, "reg")])
+                                        (2048, 1024, "reg"), (256, 2048, "reg")])
 def test_projection_nyquist_treatments_match_oracle(nx, ny, kind, nyquist):
     """Both treatments of the Nyquist modes on even grids, through the LDS
     and the register column kernels (including the packed kx = 0 / nx/2
@@ -106,7 +106,7 @@ def _check_ops(p, x3, x1, tol=2e-6):
 
 
 @pytest.mark.parametrize("nx,ny", [(128, 128), (256, 512), (512, 256), (1024, 128), (64, 512), (2048, 1024),
-                                   (128, 1024)])
+                                   (128, 1024), (128, 2048), (2048, 2048)])
 def test_every_plan_candidate_gives_the_operators(nx, ny):
     """Every launch plan the autotuner may install (LDS and register FFT
     kinds, all work-group shapes) computes the same operators."""
@@ -134,7 +134,7 @@ def test_every_plan_candidate_gives_the_operators(nx, ny):
         assert ("row", spff.FFT_REG) in kinds
     if 128 <= nx <= 512:
         assert ("row", spff.FFT_REG4) in kinds
-    if ny in (128, 256, 512, 1024):
+    if ny in (128, 256, 512, 1024, 2048):
         assert ("col", spff.FFT_REG) in kinds
     p.close()
 
@@ -160,7 +160,7 @@ def test_invalid_plans_rejected():
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("nx,ny,kind", [(8, 8, "lds"), (16, 32, "lds"), (64, 64, "lds"), (256, 128, "reg"),
                                         (512, 512, "reg"), (512, 512, "lds"), (2048, 1024, "reg"),
-                                        (2048, 2048, "lds")])
+                                        (2048, 2048, "lds"), (2048, 2048, "reg")])
 def test_displacement_operator_matches_oracle(nx, ny, kind, precision):
     """u* from a strain field (the SPFF_FIELD_DISP recovery) through the LDS
     and register column kernels, including the packed kx = 0 / nx/2 column,

@@ -125,8 +125,8 @@ def test_at2_step_parity(precision, split):
         ost = o.load_step(ramp[s])
         cmp = compare(gpu_fields(p), oracle_fields(o), precision)
         print(s, cmp, stats[0]["am_iters"], ost["am"], stats[0]["bccg_iters"], ost["bccg"])
-        assert stats[0]["F_f"] == pytest.approx(ost["F_f"], rel=10 * tol_fields(precision))
-        assert stats[0]["F_e"] == pytest.approx(ost["F_e"], rel=10 * tol_fields(precision))
+        assert stats[0]["F_f"] == pytest.approx(ost["F_f"], rel=tol_fields(precision))
+        assert stats[0]["F_e"] == pytest.approx(ost["F_e"], rel=tol_fields(precision))
     p.close()
 
 
@@ -214,8 +214,8 @@ def _elastic_and_nucleation_parity(E, ramp, cfg, precision):
     print(k, cmp, stats[0]["am_iters"], ost["am"])
     assert stats[0]["am_iters"] == ost["am"]
     tot = ost["F_e"] + ost["F_f"]
-    assert abs(stats[0]["F_e"] - ost["F_e"]) <= 10 * tol_fields(precision) * tot
-    assert abs(stats[0]["F_f"] - ost["F_f"]) <= 10 * tol_fields(precision) * tot
+    assert abs(stats[0]["F_e"] - ost["F_e"]) <= tol_fields(precision) * tot
+    assert abs(stats[0]["F_f"] - ost["F_f"]) <= tol_fields(precision) * tot
     p.close()
     q.close()
 
@@ -629,3 +629,46 @@ def test_run_evolution_across_device_queue_chunks():
         assert np.array_equal(fa[key], fb[key]), key
     a.close()
     b.close()
+
+
+def test_nonfinite_reductions_are_reported():
+    """SPFF_E_NONFINITE, forced from the host: a macroscopic strain beyond the
+    FP32 range (finite as the double the caller passes, infinite once the
+    step converts it to the working precision) makes the first stress
+    reduction of that problem's step non-finite.  Its step stops at once
+    with SPFF_E_NONFINITE; the other problem of the batch finishes its own
+    step normally."""
+    import ctypes
+
+    from paper_2203_16467_amd.spff import StepStats, lib
+    E, ramp = _c1_inputs(32)
+    cfg = cfg_for(32)
+    p = spff.Problem(torch_E(E, "fp32", B=2), cfg)
+    p.load_step(ramp[3])
+    eb = np.array([ramp[4], (0.0, 1e39, 0.0)], dtype=np.float64)
+    stats = (StepStats * 2)()
+    r = lib().spff_load_step_batch(p.handle, eb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), stats)
+    assert r == spff.E_NONFINITE
+    assert stats[0].status == spff.OK and np.isfinite(stats[0].F_e) and stats[0].sigma_bar[1] > 0.0
+    assert stats[1].status == spff.E_NONFINITE
+    with pytest.raises(spff.SpffError) as ei:
+        p.load_step(eb)
+    assert ei.value.status == spff.E_NONFINITE
+    p.close()
+
+
+def test_set_state_rejects_nonfinite_values():
+    """spff_set_state refuses a state with a NaN (SPFF_E_INVALID) and leaves
+    the problem's state as it was."""
+    E, ramp = _c1_inputs(32)
+    p = spff.Problem(torch_E(E, "fp32", B=2), cfg_for(32))
+    p.load_step(ramp[3])
+    st, eb = p.get_state()
+    bad = st.clone()
+    bad[1, 0, 7, 9] = float("nan")
+    with pytest.raises(spff.SpffError) as ei:
+        p.set_state(bad, eb)
+    assert ei.value.status == spff.E_INVALID
+    again, _ = p.get_state()
+    assert bool((again == st).all())
+    p.close()
