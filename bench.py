@@ -107,11 +107,14 @@ def iters(stats):
 
 
 def kernel_figures(pr):
-    """Per-kernel launch time from the device-clock timers: a launch's
-    work-group activity plus half of the dead time to the next kernel (its
-    drain and write-back belong to it, the next dispatch does not); a
-    profiler's kernel-trace duration lies between activity and span."""
-    kt = {k: 0.5 * (pr["kernel_ms"][k] + pr["kernel_span_ms"][k]) for k in KERNELS}
+    """Per-kernel launch time from the device-clock timers: a launch's span,
+    from its first work-group's start to the next kernel's first start (its
+    work-group activity plus its drain and end-of-kernel write-back, plus the
+    next dispatch).  A profiler's kernel-trace duration lies between the
+    activity and the span, within 2% of the span on the benchmark's window
+    (the dispatch itself is short), so the span is the launch time used, a
+    slight overestimate."""
+    kt = {k: pr["kernel_span_ms"][k] for k in KERNELS}
     dom = max(KERNELS, key=lambda k: kt[k])
     nl = max(pr["launches"][dom], 1)
     ms = kt[dom]
@@ -142,7 +145,25 @@ def batched_leg(args):
     autotune.apply(p, plans)
     s0 = args.start - args.warmup
     t = time.time()
-    if s0 > 0:
+    steady = None
+    a0, a1 = args.all_active
+    if s0 >= a1 > a0 >= 0:
+        # the kernels at full occupancy: every realization active (elastic
+        # steps before any nucleates), timed on the way to the window
+        p.run_sequence(ramp[:a0])
+        p.profile_enable(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, sst = p.run_sequence(ramp[a0:a1])
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t1
+        pr = p.profile_read()
+        p.profile_enable(False)
+        cg1, pf1 = iters(sst)
+        steady = {"steps": f"{a0}..{a1 - 1}", "seconds": dt1, "value": (cg1 + pf1) * n * n / dt1,
+                  "cg_iters": cg1, "bccg_iters": pf1, "prof": pr}
+        p.run_sequence(ramp[a1:s0])
+    elif s0 > 0:
         p.run_sequence(ramp[:s0])
     log(f"prepared {B}x{n}^2 to load step {s0} in {time.time() - t:.1f}s")
     if args.warmup > 0:
@@ -174,7 +195,7 @@ def batched_leg(args):
             "cpu_states": cpu_states, "cpu_eps": ramp[min(args.start + args.steps, 199)],
             "cpu_step": min(args.start + args.steps, 199), "ramp": ramp, "n": n, "B": B, "tuned": tuned,
             "am_iters": int(sum(am)), "am_max_step": int(max(s["am_iters"] for row in stats for s in row)),
-            "steps_capped": capped}
+            "steps_capped": capped, "steady": steady}
 
 
 # ---------------------------------------------------------------------------
@@ -337,11 +358,14 @@ def serving_leg(args, budget):
     irreversibility bound is phi >= 0 alone, so that state is the one the
     ramp itself reaches (AT1 stays at phi = 0 before the onset of damage);
     positions late in the range put AT2 problems a few requests before
-    crack nucleation.  A closed-loop run (one request per problem) gives the
-    saturation rate of this mix, then Poisson arrivals at fractions of it
-    give throughput and p50/p99 latency from arrival.  Each load level gets
-    an equal share of the remaining budget; requests still running when
-    its share ends are censored (counted with their age, a lower bound)."""
+    crack nucleation.  A closed-loop run (serve_closed_steps requests per
+    problem) gives the saturation rate of this mix and the latency under
+    saturation; Poisson arrivals at fractions of that rate then give
+    throughput and p50/p99 latency from arrival.  Requests of the closed
+    loop still running after a tenth of the budget run on under the open
+    loop as a backlog.  Each load level gets an equal share of the remaining
+    budget; requests still running when its share ends are censored
+    (counted with their age, a lower bound)."""
     import numpy as np
     import torch
 
@@ -364,24 +388,25 @@ def serving_leg(args, budget):
     pos = np.asarray(starts)
     log(f"serving: {len(ramps)} problems joining at ramp steps {pos.min()}..{pos.max()}")
     sat, lat0, wall0, res0, running = serving.run_closed(sv, ramps, cursor, args.serve_closed_steps,
-                                                          deadline=time.perf_counter() + 0.25 * budget)
+                                                          deadline=time.perf_counter() + 0.3 * budget)
     info = sv.info()
     log(f"serving: saturation {sat:.1f} req/s ({len(lat0)} requests in {wall0:.1f}s, {len(running)} still "
         f"running), {info['slots']} slots in {info['classes']} classes")
+    lat0 = np.asarray(lat0)
     out = {"workload": None, "join_steps": {"min": int(pos.min()), "median": int(np.median(pos)),
                                             "max": int(pos.max())},
-           "saturation_req_per_s": sat, "saturation_requests": len(lat0), "slots": info["slots"],
-           "classes": info["classes"], "loads": []}
-    # requests of the saturation run that are still running finish before
-    # the open-loop levels start (at most a fifth of the budget)
-    drain_end = time.perf_counter() + 0.15 * budget
+           "saturation_req_per_s": sat, "saturation_requests": int(lat0.size),
+           "saturation_p50_ms": float(np.percentile(lat0, 50)) if lat0.size else None,
+           "saturation_p99_ms": float(np.percentile(lat0, 99)) if lat0.size else None,
+           "saturation_max_am_iters": int(max((r["am_iters"] for r in res0), default=0)),
+           "slots": info["slots"], "classes": info["classes"], "loads": []}
+    # requests of the saturation run still running get a tenth of the budget
+    # to finish; any left run on under the open-loop levels (a backlog)
+    drain_end = time.perf_counter() + 0.1 * budget
     while running and time.perf_counter() < drain_end:
         sv.progress(1)
         running = [t for t in running if sv.poll(t) is None]
-    if running:
-        log(f"serving: {len(running)} saturation requests still running; open-loop levels skipped")
-        out["saturation_still_running"] = len(running)
-        sat = 0.0
+    out["backlog_from_saturation_run"] = len(running)
     for k, f in enumerate(args.serve_loads if sat > 0 else []):
         share = (t_end - time.time()) / (len(args.serve_loads) - k)
         if share < 10:
@@ -429,10 +454,10 @@ def large_leg(args, budget):
     split, l = 1 px, crack set, 500-step uniaxial ramp to 1.5 eps_M.  Load
     steps before `large_start` run untimed; then single load steps are timed
     with the kernel timers on, through at most `large_pf_steps` steps with
-    phase-field work (from the onset of damage), or until the budget is
-    spent; a step after the onset is started only with about a minute of
-    the budget left (unstable crack growth on this grid can run the
-    alternating minimisation to its cap)."""
+    phase-field work (by default the onset of damage itself, load step 212;
+    the next step is unstable crack growth across the 2048 px cell, which
+    runs the alternating minimisation for minutes), or until the budget is
+    spent."""
     import torch
 
     import spff_inputs as si
@@ -583,12 +608,12 @@ def kernel_source_hash():
 
 
 def measured_traffic(role, window):
-    """HBM bytes per launch of the dominant kernel role from the committed
-    rocprofv3 --pmc record (FETCH_SIZE and WRITE_SIZE in KiB per dispatch,
-    each scaled by the factor the same counter reads for a copy kernel of
-    known size), or None if the record is missing, covers another kernel
-    role or window, or was taken on kernel sources other than the ones built
-    here."""
+    """HBM-side bytes per launch of a kernel role from the committed
+    rocprofv3 --pmc record: read bytes from the L2's read requests counted
+    by size (TCC_EA0_RDREQ_32B/64B/128B) and write bytes (WRITE_SIZE), per
+    dispatch of the role in the record's window.  None if the record is
+    missing, covers another window, or was taken on kernel sources other
+    than the ones built here."""
     if not os.path.exists(PMC_RECORD):
         return None
     rec = {}
@@ -600,11 +625,11 @@ def measured_traffic(role, window):
     try:
         if rec.get("kernel_source_sha256") != kernel_source_hash() or rec.get("window") != window:
             return None
-        fetch = float(rec[f"{role}.fetch_kib_per_dispatch"]) * float(rec["fetch_scale"])
-        write = float(rec[f"{role}.write_kib_per_dispatch"]) * float(rec["write_scale"])
+        read = float(rec[f"{role}.read_kib_per_dispatch"])
+        write = float(rec[f"{role}.write_kib_per_dispatch"])
     except (KeyError, ValueError):
         return None
-    return (fetch + write) * 1024.0
+    return (read + write) * 1024.0
 
 
 LEGS = ("cpu_baseline", "plain", "serving", "large", "variants")
@@ -626,6 +651,8 @@ def main():
                          "first wave of crack nucleation: eight realizations nucleate, three run the "
                          "alternating minimisation to its cap)")
     ap.add_argument("--budget", type=float, default=420.0, help="wall-clock seconds for the whole run")
+    ap.add_argument("--all-active", type=int, nargs=2, default=[40, 45],
+                    help="load steps [a, b) timed on the way to the window with every realization active")
     ap.add_argument("--legs", nargs="*", default=list(LEGS), help=f"secondary legs to run, in order: {LEGS}")
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--batch", type=int, default=64)
@@ -644,14 +671,16 @@ def main():
     ap.add_argument("--serve-problems", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 0.95])
-    ap.add_argument("--serve-closed-steps", type=int, default=3,
+    ap.add_argument("--serve-closed-steps", type=int, default=2,
                     help="load steps per problem of the closed-loop saturation run")
     ap.add_argument("--serve-start-lo", type=int, default=0)
     ap.add_argument("--serve-start-hi", type=int, default=90)
     ap.add_argument("--serve-arena-gb", type=float, default=8.0)
     ap.add_argument("--serve-scratch-gb", type=float, default=1.0)
     ap.add_argument("--large-start", type=int, default=170)
-    ap.add_argument("--large-pf-steps", type=int, default=3)
+    ap.add_argument("--large-pf-steps", type=int, default=1,
+                    help="load steps with phase-field work timed in the large leg (the step after the onset of "
+                         "damage of this instance is unstable crack growth that runs for minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs one process on one MI355X "
@@ -696,11 +725,32 @@ def main():
                       "kernel_alg_bytes": res["prof"]["alg_bytes"],
                       "alg_GBs_all_fft_kernels": all_b / (all_ms * 1e-3) / 1e9 if all_ms > 0 else None},
         "autotune": res["tuned"],
+        "kernel_source_sha256": kernel_source_hash(),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kf["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": kf["achieved_GBs"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, window), "alg_bytes_per_launch": kf["alg_bytes_per_launch"],
                      "avg_launch_us": kf["avg_launch_us"]},
     }
+    if res["steady"] is not None:
+        sd = res["steady"]
+        sk = kernel_figures(sd["prof"])
+        out["all_active"] = {
+            "steps": sd["steps"], "seconds": sd["seconds"], "value": sd["value"], "unit": "grid-pt-iters/s",
+            "cg_iters": sd["cg_iters"], "bccg_iters": sd["bccg_iters"],
+            "note": "every realization active (elastic load steps before any nucleates), same launch plans; "
+                    "the kernels at full occupancy",
+            "roofline": {"bound": "hbm", "kernel": sk["dominant"], "achieved": sk["achieved_GBs"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sk["achieved_GBs"] / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(sk["dominant"], sd["steps"]),
+                         "alg_bytes_per_launch": sk["alg_bytes_per_launch"], "avg_launch_us": sk["avg_launch_us"]},
+            "kernel_GBs": {q: sd["prof"]["alg_bytes"][q] / (sk["kernel_ms"][q] * 1e-3) / 1e9
+                           for q in KERNELS if sk["kernel_ms"][q] > 0},
+            "kernel_alg_MB_per_launch": {q: sd["prof"]["alg_bytes"][q] / max(sd["prof"]["launches"][q], 1) / 1e6
+                                         for q in KERNELS},
+            "kernel_traffic_MB_per_launch": {q: (measured_traffic(q, sd["steps"]) or 0.0) / 1e6 or None
+                                             for q in KERNELS}}
+        log(f"all active {sd['steps']}: {sd['value']:.3e} grid-pt-iters/s; {sk['dominant']} "
+            f"{sk['achieved_GBs']:.0f} GB/s")
     log(f"headline {value:.3e} grid-pt-iters/s; {dom} {kf['achieved_GBs']:.0f} GB/s")
     skipped = []
     for leg in args.legs:

@@ -25,8 +25,8 @@ def test_window_outside_the_ramp_is_refused():
 def _record(path, sha, window):
     with open(path, "w") as f:
         f.write("# test record\n")
-        f.write(f"kernel_source_sha256: {sha}\nwindow: {window}\nfetch_scale: 2.0\nwrite_scale: 1.0\n")
-        f.write("rowfwd.fetch_kib_per_dispatch: 100.0\nrowfwd.write_kib_per_dispatch: 50.0\n")
+        f.write(f"kernel_source_sha256: {sha}\nwindow: {window}\n")
+        f.write("rowfwd.read_kib_per_dispatch: 200.0\nrowfwd.write_kib_per_dispatch: 50.0\n")
 
 
 def test_traffic_is_reported_only_for_the_measured_sources_and_window(tmp_path, monkeypatch):
@@ -38,7 +38,7 @@ def test_traffic_is_reported_only_for_the_measured_sources_and_window(tmp_path, 
     monkeypatch.setattr(bench, "PMC_RECORD", str(rec))
     assert bench.measured_traffic("rowfwd", "82..101") is None  # no record
     _record(rec, bench.kernel_source_hash(), "82..101")
-    assert bench.measured_traffic("rowfwd", "82..101") == (100.0 * 2.0 + 50.0) * 1024.0
+    assert bench.measured_traffic("rowfwd", "82..101") == (200.0 + 50.0) * 1024.0
     assert bench.measured_traffic("rowfwd", "88..107") is None  # another window
     assert bench.measured_traffic("col", "82..101") is None     # another kernel
     _record(rec, "0" * 64, "82..101")
