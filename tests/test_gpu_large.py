@@ -139,18 +139,20 @@ def test_batched_512_nucleation_window_parity():
     p.close()
 
 
-def test_batched_512_nucleation_uncapped_fp32_against_fp64():
+def test_batched_512_nucleation_full_step_fp32_against_fp64():
     """The first nucleating step of the batched workload (realization 47,
-    load step 95) run to its alternating-minimisation stop, FP32 against
-    FP64 from the same state (the FP32 state promoted).  The crack runs
-    across the cell and the iteration takes hundreds of steps (about 900 in
-    FP32, 600 in FP64): the two precisions reach different approximate
-    fixed points of Algorithm 2, each with ||d phi||_1 below Tol_AM, so the
-    comparison is the crack-set metric of the parity contract (the paper's
-    crack paths themselves are path-sensitive), plus the fracture energy and
-    the phase field's mean.  The elastic energy left in the broken cell is
-    not determined to better than the alternating-minimisation tolerance
-    and is not compared."""
+    load step 95) run as the benchmark runs it (alternating minimisation up
+    to its cap of 1000 iterations), FP32 against FP64 from the same state
+    (the FP32 state promoted).  The crack runs across the cell and the
+    iteration takes hundreds of steps: from this state FP32 stops after about
+    900 iterations and FP64 is still at ||d phi||_1 ~ 0.06 at the cap (from
+    the state the batched run reaches, 917 and 627), so the two precisions
+    end at different approximate fixed points of Algorithm 2 and the
+    comparison is the crack-set metric of the parity contract (crack paths
+    are path-sensitive), plus the fracture energy and the phase field's
+    mean.  The elastic energy left in the broken cell is not determined to
+    better than the alternating-minimisation tolerance and is not
+    compared."""
     n, i = 512, 47
     E = si.young_modulus(n, 16.0, 0.2, 3000 + i)
     ramp = si.uniaxial_ramp(200, 0.2, 2.0)
@@ -167,11 +169,16 @@ def test_batched_512_nucleation_uncapped_fp32_against_fp64():
     print("AM", a["am_iters"], b["am_iters"], "crack px", a["crack_px"], b["crack_px"], "F_f", a["F_f"], b["F_f"],
           "dphi", a["dphi_l1"], b["dphi_l1"], flush=True)
     tol_am = 1e-3 * 2.0 ** 2
-    assert a["dphi_l1"] < tol_am and b["dphi_l1"] < tol_am  # both reached the stop, not the cap
+    assert a["am_iters"] > 100 and b["am_iters"] > 100
+    # each run either reached the stop or is close to it at the cap
+    for s in (a, b):
+        assert s["dphi_l1"] < tol_am or (s["am_iters"] == 1000 and s["dphi_l1"] < 0.1), s
     assert a["crack_px"] > 500 and b["crack_px"] > 500
     phi32 = p32.get_fields(spff.FIELD_PHI, 0)["phi"].double().cpu().numpy()
     phi64 = p64.get_fields(spff.FIELD_PHI, 0)["phi"].double().cpu().numpy()
-    assert crack_xor_fraction(phi32, phi64) <= 0.005
+    xor = crack_xor_fraction(phi32, phi64)
+    print("crack-set xor", xor, "phi mean", a["phi_mean"], b["phi_mean"], flush=True)
+    assert xor <= 0.005
     assert abs(a["F_f"] - b["F_f"]) <= 1e-2 * b["F_f"]
     assert abs(a["phi_mean"] - b["phi_mean"]) <= 1e-2 * b["phi_mean"]
     p32.close()
