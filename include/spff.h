@@ -292,20 +292,23 @@ spff_status spff_set_state(spff_problem* p, const void* src_dev, const double* e
 enum { SPFF_OP_PROJECT = 0, SPFF_OP_NEG_LAPLACIAN = 1, SPFF_OP_DISPLACEMENT = 2 };
 spff_status spff_apply_operator(spff_problem* p, int32_t op, const void* in_dev, void* out_dev);
 
-/* Kernel profiling.  A tick is four kernels: row-forward FFT, column FFT,
- * row-inverse FFT and the controller.  While enabled, every work-group of
- * the three FFT kernels stamps its first and last device wall-clock reading,
- * and the controller of the same tick accumulates per FFT kernel
+/* Kernel profiling.  A tick is three kernels: row-forward FFT (which first
+ * runs the controller step of the previous tick), column FFT and
+ * row-inverse FFT; a block of ticks ends with a closing controller kernel.
+ * While enabled, every work-group of the three FFT kernels stamps its first
+ * and last device wall-clock reading, and an extra work-group of the next
+ * tick's column kernel (the closing kernel, for a block's last tick)
+ * accumulates per FFT kernel
  *   kernel_ms       its activity: first work-group start to last end;
  *   kernel_span_ms  its span: first start to the first start of the next
- *                   kernel of the tick (activity plus the dead time of its
- *                   drain, end-of-kernel write-back and the next dispatch);
+ *                   kernel (activity plus the dead time of its drain,
+ *                   end-of-kernel write-back and the next dispatch);
  * a profiler's kernel trace, which also counts dispatch and write-back,
  * falls between the two.  Works inside captured graphs, without host
- * events; the controller itself is not timed (index 3 stays zero).  The
- * controller also accumulates each kernel's algorithmic HBM bytes for the
- * phase every problem executed (inputs read once, outputs written once, half
- * spectra round-tripped).  Enabling resets the totals. */
+ * events; index 3 stays zero.  The controller step also accumulates each
+ * kernel's algorithmic HBM bytes for the phase every problem executed
+ * (inputs read once, outputs written once, half spectra round-tripped).
+ * Enabling resets the totals. */
 typedef struct spff_profile {
   double kernel_ms[4];       /* summed activity per kernel */
   int64_t launches[4];       /* launches per kernel */

@@ -52,7 +52,9 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 inline bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 struct Layout {
-  size_t ctl, prm, ptr, twx, twy, prow, pcol, pinv, list, bad, prof, seq, rec, kt, ktsum;
+  // ctl: two control blocks per slot (ticks alternate; the host uses the
+  // first); prow: two halves of row-forward partials (ticks alternate)
+  size_t ctl, prm, ptr, twx, twy, prow, prow1, pcol, pinv, list, bad, prof, seq, rec, kt, ktsum;
   size_t slot0, slot_bytes;
   // offsets inside a slot
   size_t E, phi, phi_ref, eps, theta, rm, pm, spec;
@@ -291,20 +293,21 @@ Layout layout(const spff_config* c, int S, size_t rsize, bool scratch_only = fal
     off = align_up(off + bytes);
     return o;
   };
-  L.ctl = take(sizeof(SlotCtl) * S);
+  L.ctl = take(2 * sizeof(SlotCtl) * S);
   L.prm = take(sizeof(SlotParam) * S);
   L.ptr = take(sizeof(SlotPtr<double>) * S);
   L.twx = take(2 * rsize * c->nx);
   L.twy = take(2 * rsize * c->ny);
   // partial sums sized for the finest launch plan (one row / column per group)
   L.prow = take(sizeof(double) * S * c->ny * NP_ROW);
+  L.prow1 = take(sizeof(double) * S * c->ny * NP_ROW);
   L.pcol = take(sizeof(double) * S * (c->nx / 2) * NP_COL);
   L.pinv = take(sizeof(double) * S * c->ny * NP_INV);
   L.list = take(sizeof(int32_t) * S);
   L.bad = take(64);
   L.prof = take(sizeof(double) * 3 * S);
   L.seq = take(sizeof(SlotSeq) * S);
-  L.kt = take(sizeof(KTime) * 3);
+  L.kt = take(sizeof(KTime) * 6);
   L.ktsum = take(sizeof(unsigned long long) * 8);
   L.rec = take(sizeof(StepRec) * SEQ_MAX * S);
   L.slot0 = off;
@@ -376,32 +379,51 @@ struct spff_problem {
 namespace {
 
 template <typename real>
-hipError_t enqueue_tick(spff_problem* p, hipStream_t st, int b) {
+TickBufs<real> tick_bufs(const spff_problem* p) {
   using C = typename HostCplx<real>::type;
-  return launch_tick<real>(p->geoms[b], p->d_list(), reinterpret_cast<const SlotPtr<real>*>(p->d_ptr()),
-                           p->d_prm(), p->d_ctl(),
-                           reinterpret_cast<const C*>(p->ws + p->L.twx),
-                           reinterpret_cast<const C*>(p->ws + p->L.twy),
-                           reinterpret_cast<double*>(p->ws + p->L.prow),
-                           reinterpret_cast<double*>(p->ws + p->L.pcol),
-                           reinterpret_cast<double*>(p->ws + p->L.pinv), p->prof_on ? p->d_prof() : nullptr,
-                           p->d_seq(), p->d_rec(), p->prof_on ? p->d_kt() : nullptr,
-                           p->prof_on ? p->d_ktsum() : nullptr, st);
+  TickBufs<real> B;
+  B.list = p->d_list();
+  B.ptrs = reinterpret_cast<const SlotPtr<real>*>(p->d_ptr());
+  B.prms = p->d_prm();
+  B.ctl[0] = p->d_ctl();
+  B.ctl[1] = p->d_ctl() + p->S;
+  B.twx = reinterpret_cast<const C*>(p->ws + p->L.twx);
+  B.twy = reinterpret_cast<const C*>(p->ws + p->L.twy);
+  B.prow[0] = reinterpret_cast<double*>(p->ws + p->L.prow);
+  B.prow[1] = reinterpret_cast<double*>(p->ws + p->L.prow1);
+  B.pcol = reinterpret_cast<double*>(p->ws + p->L.pcol);
+  B.pinv = reinterpret_cast<double*>(p->ws + p->L.pinv);
+  B.prof = p->prof_on ? p->d_prof() : nullptr;
+  B.seqs = p->d_seq();
+  B.recs = p->d_rec();
+  B.kt = p->prof_on ? p->d_kt() : nullptr;
+  B.ktsum = p->prof_on ? p->d_ktsum() : nullptr;
+  return B;
+}
+
+// k ticks and the closing controller step (leaves the control blocks in
+// the host-visible buffer)
+template <typename real>
+hipError_t enqueue_block(spff_problem* p, int k, hipStream_t st, int b) {
+  const TickBufs<real> B = tick_bufs<real>(p);
+  for (int i = 0; i < k; ++i) {
+    hipError_t e = launch_tick<real>(p->geoms[b], B, i, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_close<real>(p->geoms[b], B, k, st);
 }
 
 hipError_t enqueue_ticks(spff_problem* p, int k, hipStream_t st, int b) {
-  for (int i = 0; i < k; ++i) {
-    hipError_t e = p->cfg.precision == SPFF_FP64 ? enqueue_tick<double>(p, st, b) : enqueue_tick<float>(p, st, b);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return p->cfg.precision == SPFF_FP64 ? enqueue_block<double>(p, k, st, b) : enqueue_block<float>(p, k, st, b);
 }
 
 // After a synchronised block of k ticks: count the launches (the kernel
-// times are accumulated on the device).
+// times are accumulated on the device): k of each FFT kernel, one closing
+// controller launch.
 void collect_profile(spff_problem* p, int k) {
   if (!p->prof_on) return;
-  for (int j = 0; j < 4; ++j) p->launches[j] += k;
+  for (int j = 0; j < 3; ++j) p->launches[j] += k;
+  p->launches[3] += 1;
   p->prof_ticks += k;
 }
 
@@ -1173,12 +1195,12 @@ spff_status spff_profile_enable(spff_problem* p, int32_t enable) {
   p->prof_on = enable != 0;
   for (int j = 0; j < 4; ++j) p->launches[j] = 0;
   p->prof_ticks = 0;
-  std::vector<KTime> init(3);
+  std::vector<KTime> init(6);
   for (KTime& k : init) {
     std::fill(std::begin(k.start), std::end(k.start), ~0ull);
     std::fill(std::begin(k.end), std::end(k.end), 0ull);
   }
-  HIP_TRY(hipMemcpyAsync(p->d_kt(), init.data(), sizeof(KTime) * 3, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->d_kt(), init.data(), sizeof(KTime) * 6, hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipMemsetAsync(p->d_ktsum(), 0, sizeof(unsigned long long) * 8, p->stream));
   HIP_TRY(hipMemsetAsync(p->d_prof(), 0, sizeof(double) * 3 * p->S, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -1331,16 +1353,26 @@ spff_status static_step(const spff_config* cfg, const Layout& L, const LaunchGeo
   HIP_TRY(hipStreamSynchronize(st));
   if (bad[0]) return fail(SPFF_E_INVALID, "E has %u non-positive or non-finite entries", bad[0]);
   if (bad[1]) return fail(SPFF_E_INVALID, "phi / phi_ref have %u entries outside [0, 1]", bad[1]);
-  double* prow = reinterpret_cast<double*>(ws + L.prow);
-  double* pcol = reinterpret_cast<double*>(ws + L.pcol);
-  double* pinv = reinterpret_cast<double*>(ws + L.pinv);
+  TickBufs<real> B{};
+  B.list = d_list;
+  B.ptrs = d_ptr;
+  B.prms = d_prm;
+  B.ctl[0] = d_ctl;
+  B.ctl[1] = d_ctl + 1;
+  B.twx = twx;
+  B.twy = twy;
+  B.prow[0] = reinterpret_cast<double*>(ws + L.prow);
+  B.prow[1] = reinterpret_cast<double*>(ws + L.prow1);
+  B.pcol = reinterpret_cast<double*>(ws + L.pcol);
+  B.pinv = reinterpret_cast<double*>(ws + L.pinv);
   const int K = cfg->ticks_per_sync;
   for (;;) {
     for (int i = 0; i < K; ++i) {
-      hipError_t e = launch_tick<real>(G, d_list, d_ptr, d_prm, d_ctl, twx, twy, prow, pcol, pinv, nullptr, nullptr,
-                                       nullptr, nullptr, nullptr, st);
+      hipError_t e = launch_tick<real>(G, B, i, st);
       if (e != hipSuccess) return fail(SPFF_E_DEVICE, "tick launch failed: %s", hipGetErrorString(e));
     }
+    hipError_t e = launch_close<real>(G, B, K, st);
+    if (e != hipSuccess) return fail(SPFF_E_DEVICE, "tick launch failed: %s", hipGetErrorString(e));
     HIP_TRY(hipMemcpyAsync(&ctl, d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (ctl.phase == PH_IDLE) break;

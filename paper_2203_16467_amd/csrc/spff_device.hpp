@@ -433,22 +433,52 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NP], double* re
   }
 }
 
-// Sum (or max) of `count` contiguous partials p[0..count) by one wavefront in
-// a fixed order (lane-strided running sums, then a butterfly); every lane
-// returns the same value.  Used identically by the controller and by kernels
-// that need a scalar of the same tick.  The loads of a lane are independent
-// and are issued before the dependent adds.
+// Sums (or maxima: bit j of max_mask) of NA arrays of partials, array j
+// being p[j][0..cnt[j]), by one wavefront in a fixed order: lane l runs
+// through p[j][l], p[j][l + 64], ... in index order, then a butterfly; every
+// lane returns the same values.  Used identically by the controller and by
+// kernels that need a scalar of the same tick.  The partials are loaded 512
+// at a time (eight per lane) for all NA arrays before any of them is summed,
+// so the arrays of one controller step cost one memory round trip per 512
+// work-groups rather than one per array and per 256.
+template <int NA>
+__device__ __forceinline__ void wave_reduce_partials_n(const double* const (&p)[NA], const int (&cnt)[NA],
+                                                       double (&out)[NA], unsigned max_mask = 0u) {
+  const int lane = threadIdx.x & 63;
+  double s[NA];
+  int cmax = 0;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    s[j] = ((max_mask >> j) & 1u) ? -1.0e300 : 0.0;
+    cmax = cnt[j] > cmax ? cnt[j] : cmax;
+  }
+  for (int base = 0; base < cmax; base += 512) {
+    double a[NA][8];
+#pragma unroll
+    for (int j = 0; j < NA; ++j)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int i = base + lane + 64 * k;
+        a[j][k] = i < cnt[j] ? p[j][i] : 0.0;
+      }
+#pragma unroll
+    for (int j = 0; j < NA; ++j)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (base + lane + 64 * k < cnt[j]) s[j] = ((max_mask >> j) & 1u) ? fmax(s[j], a[j][k]) : s[j] + a[j][k];
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < NA; ++j) out[j] = ((max_mask >> j) & 1u) ? wave_max(s[j]) : wave_sum(s[j]);
+}
+
 __device__ __forceinline__ double wave_reduce_partials(const double* __restrict__ p, int count,
                                                        bool is_max = false) {
-  const int lane = threadIdx.x & 63;
-  double s = is_max ? -1.0e300 : 0.0;
-  int i = lane;
-  for (; i + 192 < count; i += 256) {
-    const double a = p[i], b = p[i + 64], c = p[i + 128], d = p[i + 192];
-    s = is_max ? fmax(fmax(fmax(fmax(s, a), b), c), d) : (((s + a) + b) + c) + d;
-  }
-  for (; i < count; i += 64) s = is_max ? fmax(s, p[i]) : s + p[i];
-  return is_max ? wave_max(s) : wave_sum(s);
+  const double* const ps[1] = {p};
+  const int cs[1] = {count};
+  double o[1];
+  wave_reduce_partials_n<1>(ps, cs, o, is_max ? 1u : 0u);
+  return o[0];
 }
 
 // ---------------------------------------------------------------------------

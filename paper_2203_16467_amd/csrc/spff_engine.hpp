@@ -14,11 +14,18 @@
 //
 // The host advances all slots together in "ticks": one tick launches the
 // row-forward, column and row-inverse FFT kernels (each does the part of the
-// current phase that belongs to it, or nothing) and the controller kernel,
-// which reduces the partial sums of the tick in a fixed order, computes the
-// FP64 scalars (alpha, beta, norms) and moves the slot to its next phase.
+// current phase that belongs to it, or nothing).  The controller step of a
+// tick -- reduce the tick's partial sums in a fixed order, compute the FP64
+// scalars (alpha, beta, norms) and move the slot to its next phase -- runs
+// at the start of the next tick's row-forward kernel, redundantly in every
+// work-group of the slot (same inputs, same order: same result), and for
+// the last tick of a block in a closing kernel.  The control block is
+// double-buffered across ticks: the row-forward kernel of tick i reads
+// block (i & 1), the group of row block 0 writes the advanced one to block
+// ((i + 1) & 1), which the column and row-inverse kernels of tick i read.
 // Ticks contain no host round trip, so blocks of ticks can be replayed as a
-// captured HIP graph; the host polls phases between blocks.
+// captured HIP graph; the host polls phases between blocks (the closing
+// kernel leaves the current block in buffer 0).
 #pragma once
 #include <stdint.h>
 
@@ -82,7 +89,8 @@ struct SlotCtl {
   int32_t phase, flags;
   int32_t am, newton, cg, bccg;     // counters of the current load step
   int32_t cg_newton, pf_it;         // CG iterations of the current Newton step, BCCG of the current solve
-  int32_t newton_solve, pad0;       // Newton steps of the current mechanics solve
+  int32_t newton_solve;             // Newton steps of the current mechanics solve
+  int32_t pending;                  // the controller step of the last tick is still to run
   uint64_t t_start;                 // device wall clock at the start of the step
   int32_t ticks, status;
   double eps_bar[3];
@@ -91,7 +99,8 @@ struct SlotCtl {
   // phase field
   double pf_ref, pf_target, pf_res, rr_pf, alpha_pf, beta_pf, pq, rp;
   double pf_bnorm, pf_best, mech_floor, pf_floor;
-  int32_t pf_best_it, pad1;
+  int32_t pf_best_it;
+  int32_t seq_pos;                  // position in the device-side load-step queue
   // alternating minimisation
   double dphi;
   // viscous term of the running phase-field solve; time-discretized
@@ -148,10 +157,12 @@ struct StepRec {
 // lowers one of KT_LINES `start` words to its first clock reading and raises
 // one of KT_LINES `end` words to its last (hashed by work-group, one word per
 // 128-byte line, so that thousands of groups do not contend on one address).
-// The controller of the same tick folds, per FFT kernel, its activity
-// (last end - first start) and its span (first start to the next kernel's
-// first start: activity plus the dead time of its drain, write-back and the
-// next dispatch), and resets the words.
+// Ticks alternate between two sets of three (one per FFT kernel).  An extra
+// work-group of the next tick's column kernel (or the closing kernel, for
+// the last tick of a block) folds, per FFT kernel, its activity (last end -
+// first start) and its span (first start to the next kernel's first start:
+// activity plus the dead time of its drain, write-back and the next
+// dispatch), and resets the words.
 constexpr int KT_LINES = 64;
 constexpr int KT_STRIDE = 16;  // 64-bit words per line
 struct KTime {

@@ -1,6 +1,9 @@
-// Solver kernels for gfx950.  One tick = k_rowfwd -> k_col -> k_rowinv ->
-// k_ctrl over all slots of a handle; every kernel looks up the phase of its
-// slot and does that phase's share of the work (or returns).
+// Solver kernels for gfx950.  One tick = k_rowfwd -> k_col -> k_rowinv over
+// all listed slots of a handle; the row-forward kernel first advances each
+// slot's control block by the controller step of the previous tick, and a
+// block of ticks ends with k_close (the controller step of its last tick).
+// Every kernel looks up the phase of its slot and does that phase's share of
+// the work (or returns).
 //
 // Data layout (per slot, real = float or double):
 //   real planes [ny][nx]; tensors as 3 planes (xx, yy, xy)
@@ -91,22 +94,60 @@ __device__ __forceinline__ void row_coords(int ngr, int& g, int& si) {
   g = L & (ngr - 1);
 }
 
+// Field and spectrum accesses go through global-address-space pointers: the
+// slot's field pointers are read from the pointer table, so the compiler
+// cannot tell they address device memory and would use flat instructions,
+// whose completion it can only wait for all at once (a flat access may be an
+// LDS access).  Global loads complete in order and are waited for one by
+// one, so the loads of a prologue overlap the arithmetic on the first ones.
+#define SPFF_GLOBAL __attribute__((address_space(1)))
+
 template <typename real>
 struct V2 {
   real a, b;
 };
 
 template <typename real>
+struct Pair;
+template <>
+struct Pair<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <typename real>
 __device__ __forceinline__ V2<real> ld2(const real* p) {
-  using C = cplx<real>;
-  const C v = *reinterpret_cast<const C*>(p);
+  using T = typename Pair<real>::type;
+  const T v = *(const SPFF_GLOBAL T*)(p);
   return {v.x, v.y};
 }
 template <typename real>
 __device__ __forceinline__ void st2(real* p, real a, real b) {
-  using C = cplx<real>;
-  *reinterpret_cast<C*>(p) = mk<C>(a, b);
+  using T = typename Pair<real>::type;
+  T v;
+  v.x = a;
+  v.y = b;
+  *(SPFF_GLOBAL T*)(p) = v;
 }
+// one complex value of a spectrum
+template <typename real>
+__device__ __forceinline__ cplx<real> ldc(const cplx<real>* p) {
+  using T = typename Pair<real>::type;
+  const T v = *(const SPFF_GLOBAL T*)(p);
+  return mk<cplx<real>>(v.x, v.y);
+}
+template <typename real>
+__device__ __forceinline__ void stc(cplx<real>* p, const cplx<real>& c) {
+  using T = typename Pair<real>::type;
+  T v;
+  v.x = c.x;
+  v.y = c.y;
+  *(SPFF_GLOBAL T*)(p) = v;
+}
+__device__ __forceinline__ unsigned char ldb(const unsigned char* p) { return *(const SPFF_GLOBAL unsigned char*)(p); }
+__device__ __forceinline__ void stb(unsigned char* p, unsigned char v) { *(SPFF_GLOBAL unsigned char*)(p) = v; }
 
 template <typename real>
 __device__ __forceinline__ real lower_bound(real pref, const SlotParam& P) {
@@ -278,8 +319,8 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
         p = {-r.a + bt * po.a, -r.b + bt * po.b};
       }
       const unsigned char* mask = reinterpret_cast<const unsigned char*>(pmp + n);
-      if (mask[o]) p.a = real(0);
-      if (mask[o + 1]) p.b = real(0);
+      if (ldb(mask + o)) p.a = real(0);
+      if (ldb(mask + o + 1)) p.b = real(0);
       st2(pmp + o, p.a, p.b);
       acc[0] += double(d.a) * double(p.a) * double(p.a) + double(d.b) * double(p.b) * double(p.b);
       acc[1] += double(r.a) * double(p.a) + double(r.b) * double(p.b);
@@ -385,6 +426,60 @@ __device__ __forceinline__ void row_prologue_n(const RowCtx<real>& X, const Slot
 #undef SPFF_PRO_CASE
 }
 
+// Inputs of the controller step that a row-forward kernel runs for the
+// previous tick (and the closing kernel for the last tick of a block).
+struct CtrlArgs {
+  const SlotCtl* ctl_in;  // control blocks as the previous tick left them
+  SlotCtl* ctl_out;       // advanced blocks, read by this tick's other kernels
+  const double* prow;     // partial sums of the previous tick
+  const double* pcol;
+  const double* pinv;
+  double* prof;
+  SlotSeq* seqs;
+  StepRec* recs;
+  int ngc;
+};
+
+template <typename real>
+__device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict__ ptrs,
+                                          const SlotParam* __restrict__ prms, SlotCtl& C, bool writer,
+                                          const double* __restrict__ prow, const double* __restrict__ pcol,
+                                          const double* __restrict__ pinv, double* __restrict__ prof,
+                                          SlotSeq* __restrict__ seqs, StepRec* __restrict__ recs, int nx, int ny,
+                                          int ngr, int ngc);
+
+// Control block of slot s for this tick, in `lc` (LDS): a copy of the input
+// block, advanced by the controller step of the previous tick if that is
+// still pending.  Every work-group of the slot computes the same block (the
+// same inputs reduced in the same order); the one that owns row block 0
+// (`writer`) publishes it to ctl_out and records the step.  The input block
+// is not written, so groups that start late read what the early ones read.
+// Every thread of the group calls this (it synchronises the group).
+template <typename real>
+__device__ __forceinline__ void tick_control(int s, bool writer, const CtrlArgs& A,
+                                             const SlotPtr<real>* __restrict__ ptrs,
+                                             const SlotParam* __restrict__ prms, int nx, int ny, int ngr,
+                                             SlotCtl& lc) {
+  constexpr int NW = (int)(sizeof(SlotCtl) / sizeof(int));
+  static_assert(sizeof(SlotCtl) % sizeof(int) == 0, "the control block is copied as words");
+  const int* src = reinterpret_cast<const int*>(A.ctl_in + s);
+  int* dst = reinterpret_cast<int*>(&lc);
+  for (int i = threadIdx.x; i < NW; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    if (lc.pending)
+      ctrl_slot<real>(s, ptrs, prms, lc, writer, A.prow, A.pcol, A.pinv, A.prof, A.seqs, A.recs, nx, ny, ngr,
+                      A.ngc);
+    // the slot's controller step after this tick is pending if it works
+    if (threadIdx.x == 0) lc.pending = lc.phase != PH_IDLE ? 1 : 0;
+  }
+  __syncthreads();
+  if (writer) {
+    int* out = reinterpret_cast<int*>(A.ctl_out + s);
+    for (int i = threadIdx.x; i < NW; i += blockDim.x) out[i] = dst[i];
+  }
+}
+
 // ===========================================================================
 // Row-forward kernel: prologue (per phase) -> R2C row FFTs -> transposed
 // store of the half spectra; FP64 partial sums per work-group.
@@ -392,18 +487,19 @@ __device__ __forceinline__ void row_prologue_n(const RowCtx<real>& X, const Slot
 template <typename real>
 __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
                                                     const SlotPtr<real>* __restrict__ ptrs,
-                                                    const SlotParam* __restrict__ prms,
-                                                    const SlotCtl* __restrict__ ctls,
+                                                    const SlotParam* __restrict__ prms, const CtrlArgs A,
                                                     const cplx<real>* __restrict__ twx, double* __restrict__ part,
                                                     int nx, int ny, int R, int ngr) {
   using C = cplx<real>;
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_ROW];
+  __shared__ SlotCtl lctl;
   int g, si;
   row_coords(ngr, g, si);
   const int s = list[si];
   if (s < 0) return;
-  const SlotCtl& ctl = ctls[s];
+  tick_control<real>(s, g == 0, A, ptrs, prms, nx, ny, ngr, lctl);
+  const SlotCtl& ctl = lctl;
   const int phase = ctl.phase;
   const int ncomp = phase_comps_row(phase);
   if (phase != PH_AM_CHK && phase != PH_TD_RESTORE && ncomp == 0) return;
@@ -445,7 +541,7 @@ __device__ __forceinline__ void k_rowfwd_body(const int* __restrict__ list,
       const int r = idx & (R - 1);
       const int rest = idx >> logR;
       const int kx = rest & (M - 1), c = rest >> logM;
-      spec[(size_t)(rest) * ny + y0 + r] = buf[(c * R + r) * stride + kx];
+      stc<real>(spec + (size_t)(rest) * ny + y0 + r, buf[(c * R + r) * stride + kx]);
     }
   }
   block_reduce_store<NP_ROW>(acc, red, part + (size_t)s * NP_ROW * ngr + g, ngr, nacc_rowfwd(phase),
@@ -575,7 +671,7 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
   for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
     const int y = idx & (ny - 1), rest = idx >> logny;
     const int w = rest & (W - 1), c = rest >> logW;
-    buf[rest * stride + y] = spec[(size_t)(c * M + kx0 + w) * ny + y];
+    buf[rest * stride + y] = ldc<real>(spec + (size_t)(c * M + kx0 + w) * ny + y);
   }
   __syncthreads();
   fft_lds<real, false, MAXE>(buf, ny, ncomp * W, stride, twy, 1);
@@ -687,7 +783,7 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
       const int y = idx & (ny - 1), rest = idx >> logny;
       const int w = rest & (W - 1), c = rest >> logW;
-      spec[(size_t)(c * M + kx0 + w) * ny + y] = buf[rest * stride + y];
+      stc<real>(spec + (size_t)(c * M + kx0 + w) * ny + y, buf[rest * stride + y]);
     }
   }
   block_reduce_store<NP_COL>(acc, red, part + (size_t)s * NP_COL * ngc + g, ngc, mode == 2 ? 1 : 0);
@@ -760,7 +856,7 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
     if (c < ncomp) {
       const C* src = spec + (size_t)(c * M + kx) * N + lane;
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[c][m] = src[m * L];
+      for (int m = 0; m < E; ++m) v[c][m] = ldc<real>(src + m * L);
     }
   }
 #pragma unroll
@@ -889,7 +985,7 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
         reg_fft<real, true, N, E>(v[c], x, lane, twy, 1);
         C* dst = spec + (size_t)(c * M + kx) * N + lane;
 #pragma unroll
-        for (int m = 0; m < E; ++m) dst[m * L] = v[c][m];
+        for (int m = 0; m < E; ++m) stc<real>(dst + m * L, v[c][m]);
       }
     }
   }
@@ -955,8 +1051,8 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
       }
       st2(rmp + o, r0, r1);
       unsigned char* mask = reinterpret_cast<unsigned char*>(pmp + n);
-      mask[o] = a0 ? 1 : 0;
-      mask[o + 1] = a1 ? 1 : 0;
+      stb(mask + o, a0 ? 1 : 0);
+      stb(mask + o + 1, a1 ? 1 : 0);
       acc[0] += double(r0) * r0 + double(r1) * r1;
       acc[2] += double(ph.a) * ph.a + double(ph.b) * ph.b;
       acc[3] += double(d.a * ph.a) * double(d.a * ph.a) + double(d.b * ph.b) * double(d.b * ph.b);
@@ -1039,18 +1135,20 @@ __device__ __forceinline__ void partner_bins(const cplx<real> (&v)[E], cplx<real
 
 template <typename real, int M, int E>
 __device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
-                                               const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
+                                               const SlotParam* __restrict__ prms, const CtrlArgs A,
                                                const cplx<real>* __restrict__ twx, double* __restrict__ part,
                                                int ny, int ngr) {
   using C = cplx<real>;
   constexpr int L = M / E, nx = 2 * M;
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_ROW];
+  __shared__ SlotCtl lctl;
   int g, si;
   row_coords(ngr, g, si);
   const int s = list[si];
   if (s < 0) return;
-  const SlotCtl& ctl = ctls[s];
+  tick_control<real>(s, g == 0, A, ptrs, prms, nx, ny, ngr, lctl);
+  const SlotCtl& ctl = lctl;
   const int phase = ctl.phase;
   const int ncomp = phase_comps_row(phase);
   if (phase != PH_AM_CHK && phase != PH_TD_RESTORE && ncomp == 0) return;
@@ -1108,7 +1206,7 @@ __device__ __forceinline__ void k_rowfwdr_body(const int* __restrict__ list, con
         // transposed store: spec[c][kx][y0 + r], r fastest
         for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
           const int r = idx & (R - 1), k = idx >> logR;
-          spec[(size_t)(c * M + k) * ny + y0 + r] = tile[RowLds<M>::tile_index(k, r, R)];
+          stc<real>(spec + (size_t)(c * M + k) * ny + y0 + r, tile[RowLds<M>::tile_index(k, r, R)]);
         }
       }
     }
@@ -1181,7 +1279,7 @@ __device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, con
       if (c > 0) __syncthreads();  // the previous component's tile reads are done
       for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
         const int r = idx & (R - 1), k = idx >> logR;
-        tile[RowLds<M>::tile_index(k, r, R)] = spec[(size_t)(c * M + k) * ny + y0 + r];
+        tile[RowLds<M>::tile_index(k, r, R)] = ldc<real>(spec + (size_t)(c * M + k) * ny + y0 + r);
       }
       __syncthreads();
 #pragma unroll
@@ -1284,7 +1382,7 @@ __device__ __forceinline__ void k_rowinv_body(const int* __restrict__ list,
     const int r = idx & (R - 1);
     const int rest = idx >> logR;
     const int kx = rest & (M - 1), c = rest >> logM;
-    buf[(c * R + r) * stride + kx] = spec[(size_t)rest * ny + y0 + r];
+    buf[(c * R + r) * stride + kx] = ldc<real>(spec + (size_t)rest * ny + y0 + r);
   }
   __syncthreads();
   c2r_pre<real>(buf, M, ncomp * R, stride, twx);
@@ -1409,22 +1507,27 @@ __device__ bool ne_gamma(const SlotPtr<real>& F, const SlotParam& P, const SlotC
   return true;
 }
 
+// The controller step of slot s after a tick: one wavefront reads the
+// tick's partial sums and the control block C, lane 0 writes the advanced
+// block back into C.  `writer`: this wavefront also records the step's
+// statistics (byte counters, finished load steps, the queue position); the
+// other wavefronts that run the same step on their own copy of C (every
+// row-forward work-group of the slot) only advance their copy.
 template <typename real>
 __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict__ ptrs,
-                                          const SlotParam* __restrict__ prms, SlotCtl* __restrict__ ctls,
-                                       const double* __restrict__ prow, const double* __restrict__ pcol,
-                                       const double* __restrict__ pinv, double* __restrict__ prof,
-                                       SlotSeq* __restrict__ seqs, StepRec* __restrict__ recs, int nx, int ny,
-                                       int ngr, int ngc) {
+                                          const SlotParam* __restrict__ prms, SlotCtl& C, bool writer,
+                                          const double* __restrict__ prow, const double* __restrict__ pcol,
+                                          const double* __restrict__ pinv, double* __restrict__ prof,
+                                          SlotSeq* __restrict__ seqs, StepRec* __restrict__ recs, int nx, int ny,
+                                          int ngr, int ngc) {
   const double* pr = prow + (size_t)s * NP_ROW * ngr;
   const double* pc = pcol + (size_t)s * NP_COL * ngc;
   const double* pi = pinv + (size_t)s * NP_INV * ngr;
-  SlotCtl& C = ctls[s];
   const int phase = C.phase;
   if (phase == PH_IDLE) return;
   if (threadIdx.x == 0 && C.ticks == 0 && C.t_start == 0) C.t_start = wall_clock64();
   const SlotParam& P = prms[s];
-  if (prof && threadIdx.x == 0) {
+  if (prof && writer && threadIdx.x == 0) {
     double b[3];
     phase_bytes(phase, C.flags, P.contact, double(sizeof(real)), b);
     const double npx = double(nx) * double(ny);
@@ -1462,9 +1565,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
   };
   switch (phase) {
     case PH_M_RES: {
-      const double sh2 = wave_reduce_partials(pr, ngr);
-      const double sg2 = wave_reduce_partials(pr + 1 * ngr, ngr);
-      const double r2 = wave_reduce_partials(pi, ngr);
+      double o[3];
+      wave_reduce_partials_n<3>({pr, pr + 1 * ngr, pi}, {ngr, ngr, ngr}, o);
+      const double sh2 = o[0], sg2 = o[1], r2 = o[2];
       bad = !isfinite(sh2) || !isfinite(r2) || !isfinite(sg2);
       mech_res = sqrt(r2);
       // G[sigma] cannot be evaluated more accurately than the rounding of
@@ -1495,8 +1598,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
       break;
     }
     case PH_M_CG: {
-      const double pcp = wave_reduce_partials(pr, ngr);
-      const double r2 = wave_reduce_partials(pi, ngr);
+      double o[2];
+      wave_reduce_partials_n<2>({pr, pi}, {ngr, ngr}, o);
+      const double pcp = o[0], r2 = o[1];
       bad = !isfinite(pcp) || !isfinite(r2);
       alpha_m = (pcp > 0.0) ? rr / pcp : 0.0;
       ++cg;
@@ -1519,8 +1623,10 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
         // Algorithm 4: -F_phi(phi_n, eps_n) and the crack driving force
         // -h'(phi_n) psi0+ were evaluated by this assembly
         flags &= ~FL_NE_CHECK;
-        fmax_ne = wave_reduce_partials(pi + 1 * ngr, ngr, true);
-        const double dmax = wave_reduce_partials(pr + 1 * ngr, ngr, true);
+        double o[2];
+        wave_reduce_partials_n<2>({pi + 1 * ngr, pr + 1 * ngr}, {ngr, ngr}, o, 3u);
+        fmax_ne = o[0];
+        const double dmax = o[1];
         if (fmax_ne > P.fphi_max && dmax > P.drive_thr) ne_flag = 1;
         if (fmax_ne > P.fphi_max && ne_flag &&
             ne_gamma<real>(ptrs[s], P, C, fmax_ne, pi + 1 * ngr, nx, ny, ngr, &gamma)) {
@@ -1530,10 +1636,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
           break;
         }
       }
-      const double b2 = wave_reduce_partials(pr, ngr);
-      const double r2 = wave_reduce_partials(pi, ngr);
-      const double x2 = wave_reduce_partials(pi + 2 * ngr, ngr);
-      const double dx2 = wave_reduce_partials(pi + 3 * ngr, ngr);
+      double o[4];
+      wave_reduce_partials_n<4>({pr, pi, pi + 2 * ngr, pi + 3 * ngr}, {ngr, ngr, ngr, ngr}, o);
+      const double b2 = o[0], r2 = o[1], x2 = o[2], dx2 = o[3];
       bad = !isfinite(b2) || !isfinite(r2);
       pf_res = sqrt(r2);
       pf_bnorm = sqrt(b2);
@@ -1554,9 +1659,12 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
       break;
     }
     case PH_PF_PQ: {
-      v[0] = wave_reduce_partials(pr, ngr);            // sum d p^2
-      v[1] = wave_reduce_partials(pr + 1 * ngr, ngr);  // sum r p
-      v[2] = wave_reduce_partials(pc, ngc);            // sum L |p^|^2
+      // sum d p^2, sum r p, sum L |p^|^2
+      double o[3];
+      wave_reduce_partials_n<3>({pr, pr + 1 * ngr, pc}, {ngr, ngr, ngc}, o);
+      v[0] = o[0];
+      v[1] = o[1];
+      v[2] = o[2];
       bad = !isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2]);
       pq = v[0] + P.kappa * inv_n * v[2];
       rp = v[1];
@@ -1571,10 +1679,9 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
       break;
     }
     case PH_PF_R: {
-      const double r2 = wave_reduce_partials(pi, ngr);
-      const double rro = wave_reduce_partials(pi + 1 * ngr, ngr);
-      const double x2 = wave_reduce_partials(pi + 2 * ngr, ngr);
-      const double dx2 = wave_reduce_partials(pi + 3 * ngr, ngr);
+      double o[4];
+      wave_reduce_partials_n<4>({pi, pi + 1 * ngr, pi + 2 * ngr, pi + 3 * ngr}, {ngr, ngr, ngr, ngr}, o);
+      const double r2 = o[0], rro = o[1], x2 = o[2], dx2 = o[3];
       bad = !isfinite(r2) || !isfinite(rro);
       beta_pf = (r2 - rro) / (alpha_pf * pq);
       rr_pf = r2;
@@ -1642,7 +1749,11 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
       nphase = PH_IDLE;
       break;
     case PH_STATS: {
-      for (int i = 0; i < 8; ++i) v[i] = wave_reduce_partials(pr + i * ngr, ngr, i == 3);
+      double o[4];
+      wave_reduce_partials_n<4>({pr, pr + 1 * ngr, pr + 2 * ngr, pr + 3 * ngr}, {ngr, ngr, ngr, ngr}, o, 8u);
+      for (int i = 0; i < 4; ++i) v[i] = o[i];
+      wave_reduce_partials_n<4>({pr + 4 * ngr, pr + 5 * ngr, pr + 6 * ngr, pr + 7 * ngr}, {ngr, ngr, ngr, ngr}, o);
+      for (int i = 0; i < 4; ++i) v[4 + i] = o[i];
       const double lg = wave_reduce_partials(pc, ngc);
       bad = false;
       for (int i = 0; i < 8; ++i) bad |= !isfinite(v[i]);
@@ -1669,10 +1780,11 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
   }
   // a load step just ended: record it and start the next one of the queue
   bool restart = false;
-  if (seqs && nphase == PH_IDLE && (phase == PH_STATS || bad) && !(flags & FL_INIT_SOLVE) && threadIdx.x == 0) {
-    SlotSeq& q = seqs[s];
-    if (q.pos < q.len) {
-      StepRec& r = recs[(size_t)s * SEQ_MAX + q.pos];
+  if (seqs && nphase == PH_IDLE && (phase == PH_STATS || bad) && !(flags & FL_INIT_SOLVE) && threadIdx.x == 0 &&
+      C.seq_pos < seqs[s].len) {
+    const int pos = C.seq_pos;
+    if (writer) {
+      StepRec& r = recs[(size_t)s * SEQ_MAX + pos];
       r.status = status;
       r.flags = flags;
       r.am = am;
@@ -1700,24 +1812,26 @@ __device__ __forceinline__ void ctrl_slot(int s, const SlotPtr<real>* __restrict
       r.phi_sum = C.phi_sum;
       r.phi_max = C.phi_max;
       r.crack_px = C.crack_px;
-      q.pos += 1;
-      if (q.pos < q.len && status >= 0) restart = true;
+      seqs[s].pos = pos + 1;
     }
+    C.seq_pos = pos + 1;
+    if (pos + 1 < seqs[s].len && status >= 0) restart = true;
   }
   if (restart) {
     // fresh control block for the next load step of the queue
     const SlotSeq& q = seqs[s];
+    const int pos = C.seq_pos;
     if (q.incr) {
       // evolution queue: the next step continues from this step's final
       // macroscopic strain, plus the increment if the algorithm advances
       const double a = advance ? 1.0 : 0.0;
-      C.eps_bar[0] += a * q.eps_bar[q.pos][0];
-      C.eps_bar[1] += a * q.eps_bar[q.pos][1];
-      C.eps_bar[2] += a * q.eps_bar[q.pos][2];
+      C.eps_bar[0] += a * q.eps_bar[pos][0];
+      C.eps_bar[1] += a * q.eps_bar[pos][1];
+      C.eps_bar[2] += a * q.eps_bar[pos][2];
     } else {
-      C.eps_bar[0] = q.eps_bar[q.pos][0];
-      C.eps_bar[1] = q.eps_bar[q.pos][1];
-      C.eps_bar[2] = q.eps_bar[q.pos][2];
+      C.eps_bar[0] = q.eps_bar[pos][0];
+      C.eps_bar[1] = q.eps_bar[pos][1];
+      C.eps_bar[2] = q.eps_bar[pos][2];
     }
     C.phase = PH_M_RES;
     C.flags = FL_FIRST_OF_STEP | (P.evolution == 2 ? FL_NE_CHECK : 0);
@@ -1801,14 +1915,72 @@ __device__ __forceinline__ void kt_end(KTime* kt) {
   }
 }
 
+// Folds the kernel times of one tick (kt[0..2]: row-forward, column,
+// row-inverse) into ktsum and resets the words for the tick after next; one
+// wavefront, lane l takes line l.  ktsum[j]: activity of kernel j (first
+// start to last end); ktsum[4 + j]: its span (first start to the first
+// start of the kernel after it; t_next for the row-inverse kernel).
+__device__ __forceinline__ void kt_fold(KTime* kt, unsigned long long t_next, unsigned long long* ktsum) {
+  const int l = threadIdx.x & 63;
+  unsigned long long st[3], en[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    unsigned long long a = kt[j].start[l * KT_STRIDE], b = kt[j].end[l * KT_STRIDE];
+    kt[j].start[l * KT_STRIDE] = ~0ull;
+    kt[j].end[l * KT_STRIDE] = 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long a2 = __shfl_xor(a, off, 64), b2 = __shfl_xor(b, off, 64);
+      a = a2 < a ? a2 : a;
+      b = b2 > b ? b2 : b;
+    }
+    st[j] = a;
+    en[j] = b;
+  }
+  if (l == 0) {
+    const unsigned long long nxt[3] = {st[1], st[2], t_next};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if (en[j] > st[j]) ktsum[j] += en[j] - st[j];
+      if (nxt[j] > st[j] && st[j] != ~0ull) ktsum[4 + j] += nxt[j] - st[j];
+    }
+  }
+}
+// First start stamped in kt (one wavefront).
+__device__ __forceinline__ unsigned long long kt_first_start(const KTime* kt) {
+  unsigned long long a = kt->start[(threadIdx.x & 63) * KT_STRIDE];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long a2 = __shfl_xor(a, off, 64);
+    a = a2 < a ? a2 : a;
+  }
+  return a;
+}
+
+// Timer bookkeeping of the column kernel: with timers on, the launch has one
+// extra row of work-groups; its group 0 folds the previous tick's times
+// (kt_prev, null for the first tick of a block) -- the previous tick ended
+// before this tick's row-forward kernel, whose first start (kt_row) closes
+// the previous row-inverse span -- and the other extra groups return.
+struct ColTimers {
+  KTime* kt;             // this column kernel's stamps
+  KTime* kt_prev;        // the previous tick's three kernels
+  const KTime* kt_row;   // this tick's row-forward kernel
+  unsigned long long* ktsum;
+};
+__device__ __forceinline__ bool col_timer_group(const ColTimers& T) {
+  if (!T.kt || blockIdx.y != gridDim.y - 1) return false;
+  if (T.kt_prev && blockIdx.x == 0 && threadIdx.x < 64) kt_fold(T.kt_prev, kt_first_start(T.kt_row), T.ktsum);
+  return true;
+}
+
 template <typename real>
 __global__ __launch_bounds__(THREADS) void k_rowfwd(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
-                                                    const SlotParam* __restrict__ prms,
-                                                    const SlotCtl* __restrict__ ctls,
+                                                    const SlotParam* __restrict__ prms, const CtrlArgs A,
                                                     const cplx<real>* __restrict__ twx, double* __restrict__ part,
                                                     int nx, int ny, int R, int ngr, KTime* kt) {
   kt_begin(kt);
-  k_rowfwd_body<real>(list, ptrs, prms, ctls, twx, part, nx, ny, R, ngr);
+  k_rowfwd_body<real>(list, ptrs, prms, A, twx, part, nx, ny, R, ngr);
   kt_end(kt);
 }
 
@@ -1817,10 +1989,11 @@ __global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, c
                                                  const SlotParam* __restrict__ prms,
                                                  const SlotCtl* __restrict__ ctls,
                                                  const cplx<real>* __restrict__ twy, double* __restrict__ part,
-                                                 int nx, int ny, int W, int ngc, int nyq_free, KTime* kt) {
-  kt_begin(kt);
+                                                 int nx, int ny, int W, int ngc, int nyq_free, const ColTimers T) {
+  if (col_timer_group(T)) return;
+  kt_begin(T.kt);
   k_col_body<real>(list, ptrs, prms, ctls, twy, part, nx, ny, W, ngc, nyq_free);
-  kt_end(kt);
+  kt_end(T.kt);
 }
 
 template <typename real, int N>
@@ -1828,21 +2001,21 @@ __global__ __launch_bounds__(THREADS) void k_colr(const int* __restrict__ list, 
                                                   const SlotParam* __restrict__ prms,
                                                   const SlotCtl* __restrict__ ctls,
                                                   const cplx<real>* __restrict__ twy, double* __restrict__ part,
-                                                  int nx, int ngc, int nyq_free, KTime* kt) {
-  kt_begin(kt);
+                                                  int nx, int ngc, int nyq_free, const ColTimers T) {
+  if (col_timer_group(T)) return;
+  kt_begin(T.kt);
   k_colr_body<real, N>(list, ptrs, prms, ctls, twy, part, nx, ngc, nyq_free);
-  kt_end(kt);
+  kt_end(T.kt);
 }
 
 template <typename real, int M, int E>
 __global__ __launch_bounds__(THREADS) void k_rowfwdr(const int* __restrict__ list,
                                                      const SlotPtr<real>* __restrict__ ptrs,
-                                                     const SlotParam* __restrict__ prms,
-                                                     const SlotCtl* __restrict__ ctls,
+                                                     const SlotParam* __restrict__ prms, const CtrlArgs A,
                                                      const cplx<real>* __restrict__ twx, double* __restrict__ part,
                                                      int ny, int ngr, KTime* kt) {
   kt_begin(kt);
-  k_rowfwdr_body<real, M, E>(list, ptrs, prms, ctls, twx, part, ny, ngr);
+  k_rowfwdr_body<real, M, E>(list, ptrs, prms, A, twx, part, ny, ngr);
   kt_end(kt);
 }
 
@@ -1872,56 +2045,40 @@ __global__ __launch_bounds__(THREADS) void k_rowinv(const int* __restrict__ list
   kt_end(kt);
 }
 
-// Controller: one wavefront per listed slot.  A separate launch rather than
-// a last-arriving-group step inside k_rowinv: publishing the partials across
-// the XCDs from every group would need a device-scope release per group (an
-// L2 write-back each), which costs far more than the kernel boundary.
+// Closing kernel of a block of ticks: the controller step of the last tick,
+// one work-group per listed slot, from A.ctl_in into A.ctl_out (buffer 0,
+// possibly the same block), so that the host reads every slot's current
+// block in buffer 0.  With timers on, the second wavefront of group 0 folds
+// the last tick's kernel times meanwhile.
 template <typename real>
-__global__ __launch_bounds__(128) void k_ctrl(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
-                                             const SlotParam* __restrict__ prms,
-                                             SlotCtl* __restrict__ ctls, const double* __restrict__ prow,
-                                             const double* __restrict__ pcol, const double* __restrict__ pinv,
-                                             double* __restrict__ prof, SlotSeq* __restrict__ seqs,
-                                             StepRec* __restrict__ recs, int nx, int ny, int ngr, int ngc,
-                                             KTime* kt, unsigned long long* __restrict__ ktsum) {
-  // Wavefront 0 of each work-group runs the controller of one slot; the
-  // second wavefront of the first work-group folds this tick's kernel times
-  // meanwhile (lane l takes line l of every kernel).  ktsum[j]: activity of
-  // kernel j (first start to last end); ktsum[4 + j]: its span (first start
-  // to the first start of kernel j + 1, this kernel's own start for the
-  // row-inverse kernel)
-  if (threadIdx.x >= 64) {
-    if (!kt || blockIdx.x != 0) return;
-    const int l = threadIdx.x - 64;
-    const unsigned long long t_ctrl = wall_clock64();
-    unsigned long long st[3], en[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      unsigned long long a = kt[j].start[l * KT_STRIDE], b = kt[j].end[l * KT_STRIDE];
-      kt[j].start[l * KT_STRIDE] = ~0ull;
-      kt[j].end[l * KT_STRIDE] = 0ull;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long a2 = __shfl_xor(a, off, 64), b2 = __shfl_xor(b, off, 64);
-        a = a2 < a ? a2 : a;
-        b = b2 > b ? b2 : b;
-      }
-      st[j] = a;
-      en[j] = b;
-    }
-    if (l == 0) {
-      const unsigned long long nxt[3] = {st[1], st[2], t_ctrl};
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        if (en[j] > st[j]) ktsum[j] += en[j] - st[j];
-        if (nxt[j] > st[j] && st[j] != ~0ull) ktsum[4 + j] += nxt[j] - st[j];
-      }
-    }
-    return;
-  }
+__global__ __launch_bounds__(128) void k_close(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
+                                              const SlotParam* __restrict__ prms, const CtrlArgs A, int nx, int ny,
+                                              int ngr, KTime* kt_last, unsigned long long* __restrict__ ktsum) {
+  constexpr int NW = (int)(sizeof(SlotCtl) / sizeof(int));
+  __shared__ SlotCtl lc;
+  const unsigned long long t_close = wall_clock64();
   const int s = list[blockIdx.x];
-  if (s < 0) return;
-  ctrl_slot<real>(s, ptrs, prms, ctls, prow, pcol, pinv, prof, seqs, recs, nx, ny, ngr, ngc);
+  int* w = reinterpret_cast<int*>(&lc);
+  if (s >= 0) {
+    const int* src = reinterpret_cast<const int*>(A.ctl_in + s);
+    for (int i = threadIdx.x; i < NW; i += blockDim.x) w[i] = src[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    if (s >= 0) {
+      if (lc.pending)
+        ctrl_slot<real>(s, ptrs, prms, lc, true, A.prow, A.pcol, A.pinv, A.prof, A.seqs, A.recs, nx, ny, ngr,
+                        A.ngc);
+      if (threadIdx.x == 0) lc.pending = 0;
+    }
+  } else if (kt_last && blockIdx.x == 0) {
+    kt_fold(kt_last, t_close, ktsum);
+  }
+  __syncthreads();
+  if (s >= 0) {
+    int* out = reinterpret_cast<int*>(A.ctl_out + s);
+    for (int i = threadIdx.x; i < NW; i += blockDim.x) out[i] = w[i];
+  }
 }
 
 // ===========================================================================
@@ -1978,20 +2135,45 @@ __global__ void k_fields(const SlotPtr<real>* __restrict__ ptrs, const SlotParam
 // ===========================================================================
 
 template <typename real>
-hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>* ptrs, const SlotParam* prms,
-                       SlotCtl* ctls, const typename HostCplx<real>::type* twx,
-                       const typename HostCplx<real>::type* twy, double* prow, double* pcol, double* pinv,
-                       double* prof, SlotSeq* seqs, StepRec* recs, KTime* kt, unsigned long long* ktsum,
-                       hipStream_t st) {
-  dim3 grow(G.ngr, G.S), gcol(G.ngc, G.S);
-  KTime* ktf = kt ? kt + 0 : nullptr;
-  KTime* kti = kt ? kt + 2 : nullptr;
+hipError_t launch_tick(const LaunchGeom& G, const TickBufs<real>& B, int i, hipStream_t st) {
+  // tick i reads control block (i & 1) and the partials of tick i - 1
+  // (row partials double-buffered: this tick's row-forward kernel writes the
+  // other half while its groups reduce the previous one)
+  const int cur = i & 1, nxt = cur ^ 1;
+  CtrlArgs A;
+  A.ctl_in = B.ctl[cur];
+  A.ctl_out = B.ctl[nxt];
+  A.prow = B.prow[nxt];
+  A.pcol = B.pcol;
+  A.pinv = B.pinv;
+  A.prof = B.prof;
+  A.seqs = B.seqs;
+  A.recs = B.recs;
+  A.ngc = G.ngc;
+  const int* list = B.list;
+  const SlotPtr<real>* ptrs = B.ptrs;
+  const SlotParam* prms = B.prms;
+  const SlotCtl* ctls = B.ctl[nxt];
+  const auto* twx = B.twx;
+  const auto* twy = B.twy;
+  double* prow = B.prow[cur];
+  double* pcol = B.pcol;
+  double* pinv = B.pinv;
+  KTime* ktset = B.kt ? B.kt + 3 * cur : nullptr;
+  KTime* ktf = ktset;
+  KTime* kti = ktset ? ktset + 2 : nullptr;
+  ColTimers T;
+  T.kt = ktset ? ktset + 1 : nullptr;
+  T.kt_prev = (B.kt && i > 0) ? B.kt + 3 * nxt : nullptr;
+  T.kt_row = ktf;
+  T.ktsum = B.ktsum;
+  dim3 grow(G.ngr, G.S), gcol(G.ngc, G.S + (B.kt ? 1 : 0));
   bool row_done = false;
   if constexpr (std::is_same<real, float>::value) {
     if (G.row_reg) {
       row_done = true;
 #define SPFF_ROWS_FWD(MM, EE)                                                                                   \
-  hipLaunchKernelGGL((k_rowfwdr<real, MM, EE>), grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, \
+  hipLaunchKernelGGL((k_rowfwdr<real, MM, EE>), grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, A, twx, \
                      prow, G.ny, G.ngr, ktf)
       if (G.row_reg == 2) {
         switch (G.nx) {
@@ -2012,40 +2194,28 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
     }
   }
   if (!row_done)
-    hipLaunchKernelGGL(k_rowfwd<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow,
+    hipLaunchKernelGGL(k_rowfwd<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, A, twx, prow,
                        G.nx, G.ny, G.R, G.ngr, ktf);
-  KTime* ktc = kt ? kt + 1 : nullptr;
   bool col_done = false;
   if constexpr (std::is_same<real, float>::value) {
     if (G.col_reg) {
       col_done = true;
+#define SPFF_COLS(NN)                                                                                           \
+  hipLaunchKernelGGL((k_colr<real, NN>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls, twy, \
+                     pcol, G.nx, G.ngc, G.nyq_free, T)
       switch (G.ny) {
-      case 128:
-        hipLaunchKernelGGL((k_colr<real, 128>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
-                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
-        break;
-      case 256:
-        hipLaunchKernelGGL((k_colr<real, 256>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
-                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
-        break;
-      case 512:
-        hipLaunchKernelGGL((k_colr<real, 512>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
-                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
-        break;
-      case 1024:
-        hipLaunchKernelGGL((k_colr<real, 1024>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
-                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
-        break;
-      default:
-        hipLaunchKernelGGL((k_colr<real, 2048>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls,
-                           twy, pcol, G.nx, G.ngc, G.nyq_free, ktc);
-        break;
+        case 128: SPFF_COLS(128); break;
+        case 256: SPFF_COLS(256); break;
+        case 512: SPFF_COLS(512); break;
+        case 1024: SPFF_COLS(1024); break;
+        default: SPFF_COLS(2048); break;
       }
+#undef SPFF_COLS
     }
   }
   if (!col_done)
     hipLaunchKernelGGL(k_col<real>, gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls, twy, pcol,
-                       G.nx, G.ny, G.W, G.ngc, G.nyq_free, ktc);
+                       G.nx, G.ny, G.W, G.ngc, G.nyq_free, T);
   if (row_done) {
     if constexpr (std::is_same<real, float>::value) {
 #define SPFF_ROWS_INV(MM, EE)                                                                                   \
@@ -2072,8 +2242,25 @@ hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>
     hipLaunchKernelGGL(k_rowinv<real>, grow, dim3(G.threads), G.lds_row, st, list, ptrs, prms, ctls, twx, prow,
                        pinv, G.nx, G.ny, G.R, G.ngr, kti);
   }
-  hipLaunchKernelGGL(k_ctrl<real>, dim3(G.S), dim3(128), 0, st, list, ptrs, prms, ctls, prow, pcol, pinv, prof,
-                     seqs, recs, G.nx, G.ny, G.ngr, G.ngc, kt, ktsum);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_close(const LaunchGeom& G, const TickBufs<real>& B, int k, hipStream_t st) {
+  // after ticks 0..k-1 the latest control blocks are in buffer (k & 1)
+  const int last = (k - 1) & 1;
+  CtrlArgs A;
+  A.ctl_in = B.ctl[k & 1];
+  A.ctl_out = B.ctl[0];
+  A.prow = B.prow[last];
+  A.pcol = B.pcol;
+  A.pinv = B.pinv;
+  A.prof = B.prof;
+  A.seqs = B.seqs;
+  A.recs = B.recs;
+  A.ngc = G.ngc;
+  hipLaunchKernelGGL(k_close<real>, dim3(G.S), dim3(128), 0, st, B.list, B.ptrs, B.prms, A, G.nx, G.ny, G.ngr,
+                     B.kt ? B.kt + 3 * last : nullptr, B.ktsum);
   return hipGetLastError();
 }
 
@@ -2098,12 +2285,10 @@ hipError_t launch_fields(const SlotPtr<real>* ptrs, const SlotParam* prms, const
   return hipGetLastError();
 }
 
-template hipError_t launch_tick<float>(const LaunchGeom&, const int*, const SlotPtr<float>*, const SlotParam*,
-                                       SlotCtl*, const float2*, const float2*, double*, double*, double*, double*,
-                                       SlotSeq*, StepRec*, KTime*, unsigned long long*, hipStream_t);
-template hipError_t launch_tick<double>(const LaunchGeom&, const int*, const SlotPtr<double>*, const SlotParam*,
-                                        SlotCtl*, const double2*, const double2*, double*, double*, double*,
-                                        double*, SlotSeq*, StepRec*, KTime*, unsigned long long*, hipStream_t);
+template hipError_t launch_tick<float>(const LaunchGeom&, const TickBufs<float>&, int, hipStream_t);
+template hipError_t launch_tick<double>(const LaunchGeom&, const TickBufs<double>&, int, hipStream_t);
+template hipError_t launch_close<float>(const LaunchGeom&, const TickBufs<float>&, int, hipStream_t);
+template hipError_t launch_close<double>(const LaunchGeom&, const TickBufs<double>&, int, hipStream_t);
 template hipError_t launch_validate<float>(const float*, size_t, double, double, double, unsigned int*,
                                            hipStream_t);
 template hipError_t launch_validate<double>(const double*, size_t, double, double, double, unsigned int*,

@@ -23,13 +23,35 @@ struct LaunchGeom {
   size_t lds_row, lds_col;
 };
 
-// One solver tick over the slots list[0..G.S) (entries < 0 are padding).
+// Device buffers of a handle's ticks.
 template <typename real>
-hipError_t launch_tick(const LaunchGeom& G, const int* list, const SlotPtr<real>* ptrs, const SlotParam* prms,
-                       SlotCtl* ctls, const typename HostCplx<real>::type* twx,
-                       const typename HostCplx<real>::type* twy, double* prow, double* pcol, double* pinv,
-                       double* prof, SlotSeq* seqs, StepRec* recs, KTime* kt, unsigned long long* ktsum,
-                       hipStream_t st);
+struct TickBufs {
+  const int* list;            // listed slots (G.S entries, < 0: padding)
+  const SlotPtr<real>* ptrs;  // per slot
+  const SlotParam* prms;
+  SlotCtl* ctl[2];            // control blocks; the host reads and writes ctl[0]
+  const typename HostCplx<real>::type* twx;
+  const typename HostCplx<real>::type* twy;
+  double* prow[2];            // row-forward partials, alternating by tick
+  double* pcol;
+  double* pinv;
+  double* prof;               // per-slot byte counters, or null
+  SlotSeq* seqs;              // device load-step queues, or null
+  StepRec* recs;
+  KTime* kt;                  // six kernel timers (two ticks x three kernels), or null
+  unsigned long long* ktsum;  // folded kernel times
+};
+
+// Tick i (0-based) of a block of ticks over the listed slots.  Tick 0 reads
+// ctl[0], whose blocks must have no controller step pending (as the host
+// and launch_close leave them).
+template <typename real>
+hipError_t launch_tick(const LaunchGeom& G, const TickBufs<real>& B, int i, hipStream_t st);
+
+// Closes a block of k ticks: the controller step of tick k - 1, leaving
+// every listed slot's control block in ctl[0].
+template <typename real>
+hipError_t launch_close(const LaunchGeom& G, const TickBufs<real>& B, int k, hipStream_t st);
 
 template <typename real>
 hipError_t launch_validate(const real* a, size_t n, double lo_excl, double lo_incl, double hi_incl,

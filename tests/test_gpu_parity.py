@@ -372,10 +372,12 @@ def test_profile_counters():
     p.run_sequence(ramp[3:6])
     prof = p.profile_read()
     ffts = ("rowfwd", "col", "rowinv")
-    assert prof["ticks"] > 0 and all(v == prof["ticks"] for v in prof["launches"].values())
+    assert prof["ticks"] > 0 and all(prof["launches"][k] == prof["ticks"] for k in ffts)
+    # one closing controller launch per block of ticks_per_sync ticks
+    assert prof["launches"]["ctrl"] * 4 == prof["ticks"]
     assert prof["alg_bytes"]["rowfwd"] > 0 and prof["alg_bytes"]["col"] > 0
     # device-clock execution times of the three FFT kernels (also inside the
-    # captured graphs); the controller is not timed
+    # captured graphs); the closing controller kernel is not timed
     assert all(prof["kernel_ms"][k] > 0 for k in ffts)
     assert prof["kernel_ms"]["ctrl"] == 0
     # per launch, a 64x64 tick kernel runs for well under a millisecond
