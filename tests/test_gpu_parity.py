@@ -295,6 +295,30 @@ def test_graph_replay_matches_eager():
         assert np.array_equal(fa[k], fb[k]), k
 
 
+def test_block_lengths_give_identical_results():
+    """The controller step of a tick runs in the next tick's row-forward
+    kernel (the control blocks alternate between two buffers) and a closing
+    kernel runs the last one of each block of ticks_per_sync ticks: odd and
+    even block lengths, launched eagerly or as captured graphs, with the
+    load steps queued on the device, give bit-identical steps for one
+    problem."""
+    E, ramp = _c1_inputs()
+    runs = []
+    for K, graph in ((1, 0), (3, 0), (3, 1), (4, 1), (5, 1)):
+        p = spff.Problem(torch_E(E, "fp32"), cfg_for(64, at=2, use_graph=graph, ticks_per_sync=K))
+        st, stats = p.run_sequence(ramp[6:11])
+        assert st >= 0
+        steps = [(s["cg_iters"], s["bccg_iters"], s["am_iters"], s["ticks"], s["F_e"], s["F_f"]) for s in stats[0]]
+        runs.append((K, graph, steps, gpu_fields(p)))
+        p.close()
+    K0, g0, steps0, f0 = runs[0]
+    assert sum(s[1] for s in steps0) > 0  # the phase field works in these steps
+    for K, graph, steps, f in runs[1:]:
+        assert steps == steps0, (K, graph)
+        for k in f0:
+            assert np.array_equal(f[k], f0[k]), (K, graph, k)
+
+
 def test_state_roundtrip():
     E, ramp = _c1_inputs()
     cfg = cfg_for(64, at=2)
