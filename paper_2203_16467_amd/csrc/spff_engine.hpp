@@ -83,8 +83,9 @@ struct SlotParam {
   int32_t max_cg, max_newton, max_bccg, max_am;
 };
 
-// Per-slot control block (written by the controller kernel; the host writes
-// it only while the slot is idle).
+// Per-slot control block (advanced by the controller step on the device; the
+// host writes it, in the buffer the closing kernel leaves it in, only while
+// the slot is idle).
 struct SlotCtl {
   int32_t phase, flags;
   int32_t am, newton, cg, bccg;     // counters of the current load step
@@ -132,7 +133,7 @@ struct SlotPtr {
   void* spec;    // complex [3][nx/2][ny]  (half spectrum, transposed)
 };
 
-// Device-side load-step queue of a slot: the controller starts step pos+1
+// Device-side load-step queue of a slot: the controller step starts step pos+1
 // as soon as step pos has finished, without a host round trip, and records
 // the finished step's statistics in the slot's StepRec array.
 constexpr int SEQ_MAX = 256;

@@ -1257,6 +1257,26 @@ __device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, con
   C* xa = reinterpret_cast<C*>(smem_raw) + row * XArea<M>::size;
   C* tile = reinterpret_cast<C*>(smem_raw) + R * XArea<M>::size;
   const C* spec = reinterpret_cast<const C*>(F.spec);
+  const int logR = ilog2(R);
+
+  // Few problems per launch (four points per lane): the group's tile entries
+  // of every component (E per thread and component: R rows x M bins over
+  // R L threads) are loaded up front, so that the components cost one
+  // memory round trip instead of one each
+  C pre[3][E];
+  if constexpr (E == 4) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c < ncomp) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int idx = threadIdx.x + i * blockDim.x;
+          const int r = idx & (R - 1), k = idx >> logR;
+          pre[c][i] = ldc<real>(spec + (size_t)(c * M + k) * ny + y0 + r);
+        }
+      }
+    }
+  }
 
   // CG step length from this tick's row-forward partials (same fixed-order
   // reduction as the controller)
@@ -1271,15 +1291,23 @@ __device__ __forceinline__ void k_rowinvr_body(const int* __restrict__ list, con
     alpha = real(scal[0]);
   }
 
-  const int logR = ilog2(R);
   C v[3][E];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     if (c < ncomp) {
       if (c > 0) __syncthreads();  // the previous component's tile reads are done
-      for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
-        const int r = idx & (R - 1), k = idx >> logR;
-        tile[RowLds<M>::tile_index(k, r, R)] = ldc<real>(spec + (size_t)(c * M + k) * ny + y0 + r);
+      if constexpr (E == 4) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int idx = threadIdx.x + i * blockDim.x;
+          const int r = idx & (R - 1), k = idx >> logR;
+          tile[RowLds<M>::tile_index(k, r, R)] = pre[c][i];
+        }
+      } else {
+        for (int idx = threadIdx.x; idx < M * R; idx += blockDim.x) {
+          const int r = idx & (R - 1), k = idx >> logR;
+          tile[RowLds<M>::tile_index(k, r, R)] = ldc<real>(spec + (size_t)(c * M + k) * ny + y0 + r);
+        }
       }
       __syncthreads();
 #pragma unroll
