@@ -190,13 +190,25 @@ __device__ __forceinline__ RowCtx<real> row_ctx(const SlotCtl& ctl, const SlotPa
 // Row-forward prologue for the pixel pair (o, o + 1): the phase's pointwise
 // work, the values entering the transforms (val[c][0..1]) and the FP64
 // partial sums.
-template <typename real, int PH = -1>
+// Inputs of the row prologue for one pixel pair, loaded ahead of the
+// arithmetic (see row_prologue_n); the slots each phase uses are listed
+// with pro_load_chunk.
+template <typename real>
+struct ProIn {
+  V2<real> a[11];
+  unsigned char m[2];
+};
+
+template <typename real, int PH = -1, bool PRE = false>
 __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotParam& P, const real* __restrict__ Ep,
                                              real* __restrict__ phip, real* __restrict__ prefp,
                                              real* __restrict__ epsp, real* __restrict__ thp,
                                              real* __restrict__ rmp, real* __restrict__ pmp, int o,
-                                             real (&val)[3][2], double (&acc)[NP_ROW]) {
-  // PH >= 0: the phase is known at compile time (the other cases fold away)
+                                             real (&val)[3][2], double (&acc)[NP_ROW],
+                                             const ProIn<real>& in = ProIn<real>{}) {
+  // PH >= 0: the phase is known at compile time (the other cases fold away).
+  // PRE: the inputs of this pair were loaded into `in` (PH one of M_RES,
+  // M_CG, PF_ASM, PF_PQ, PF_R)
   const int phase = PH >= 0 ? PH : X.phase;
   const int flags = X.flags, split = X.split, contact = X.contact, n = X.n, ncomp = X.ncomp;
   const real lt = X.lt, mt = X.mt, kres = X.kres, eb0 = X.eb0, eb1 = X.eb1, eb2 = X.eb2;
@@ -204,11 +216,13 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
   for (int q = 0; q < 2; ++q) val[0][q] = val[1][q] = val[2][q] = real(0);
   switch (phase) {
     case PH_M_RES: {
-      const V2<real> E = ld2(Ep + o), ph = ld2(phip + o);
+      const V2<real> E = PRE ? in.a[0] : ld2(Ep + o), ph = PRE ? in.a[1] : ld2(phip + o);
       if (flags & FL_FIRST_OF_STEP) st2(prefp + o, ph.a, ph.b);
-      V2<real> ex = ld2(epsp + o), ey = ld2(epsp + n + o), exy = ld2(epsp + 2 * n + o);
+      V2<real> ex = PRE ? in.a[2] : ld2(epsp + o), ey = PRE ? in.a[3] : ld2(epsp + n + o),
+               exy = PRE ? in.a[4] : ld2(epsp + 2 * n + o);
       if (flags & FL_THETA_PENDING) {
-        const V2<real> tx = ld2(thp + o), ty = ld2(thp + n + o), txy = ld2(thp + 2 * n + o);
+        const V2<real> tx = PRE ? in.a[5] : ld2(thp + o), ty = PRE ? in.a[6] : ld2(thp + n + o),
+                       txy = PRE ? in.a[7] : ld2(thp + 2 * n + o);
         ex = {ex.a + tx.a, ex.b + tx.b};
         ey = {ey.a + ty.a, ey.b + ty.b};
         exy = {exy.a + txy.a, exy.b + txy.b};
@@ -235,11 +249,13 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       break;
     }
     case PH_M_CG: {
-      const V2<real> E = ld2(Ep + o), ph = ld2(phip + o);
-      V2<real> px = ld2(rmp + o), py = ld2(rmp + n + o), pxy = ld2(rmp + 2 * n + o);
+      const V2<real> E = PRE ? in.a[0] : ld2(Ep + o), ph = PRE ? in.a[1] : ld2(phip + o);
+      V2<real> px = PRE ? in.a[2] : ld2(rmp + o), py = PRE ? in.a[3] : ld2(rmp + n + o),
+               pxy = PRE ? in.a[4] : ld2(rmp + 2 * n + o);
       if (!(flags & FL_CG_FIRST)) {
         const real bt = real(X.beta_m);
-        const V2<real> qx = ld2(pmp + o), qy = ld2(pmp + n + o), qxy = ld2(pmp + 2 * n + o);
+        const V2<real> qx = PRE ? in.a[5] : ld2(pmp + o), qy = PRE ? in.a[6] : ld2(pmp + n + o),
+                       qxy = PRE ? in.a[7] : ld2(pmp + 2 * n + o);
         px = {px.a + bt * qx.a, px.b + bt * qx.b};
         py = {py.a + bt * qy.a, py.b + bt * qy.b};
         pxy = {pxy.a + bt * qxy.a, pxy.b + bt * qxy.b};
@@ -249,9 +265,9 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       st2(pmp + 2 * n + o, pxy.a, pxy.b);
       V2<real> ex = {0, 0}, ey = {0, 0}, exy = {0, 0};
       if (contact != 0) {
-        ex = ld2(epsp + o);
-        ey = ld2(epsp + n + o);
-        exy = ld2(epsp + 2 * n + o);
+        ex = PRE ? in.a[8] : ld2(epsp + o);
+        ey = PRE ? in.a[9] : ld2(epsp + n + o);
+        exy = PRE ? in.a[10] : ld2(epsp + 2 * n + o);
       }
       const real Ev[2] = {E.a, E.b}, pv[2] = {ph.a, ph.b};
       const real xv[2] = {ex.a, ex.b}, yv[2] = {ey.a, ey.b}, sv[2] = {exy.a, exy.b};
@@ -271,8 +287,10 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       break;
     }
     case PH_PF_ASM: {
-      const V2<real> E = ld2(Ep + o), ph = ld2(phip + o), pr = ld2(prefp + o);
-      V2<real> ex = ld2(epsp + o), ey = ld2(epsp + n + o), exy = ld2(epsp + 2 * n + o);
+      const V2<real> E = PRE ? in.a[0] : ld2(Ep + o), ph = PRE ? in.a[1] : ld2(phip + o),
+                     pr = PRE ? in.a[2] : ld2(prefp + o);
+      V2<real> ex = PRE ? in.a[3] : ld2(epsp + o), ey = PRE ? in.a[4] : ld2(epsp + n + o),
+               exy = PRE ? in.a[5] : ld2(epsp + 2 * n + o);
       if (flags & FL_NE_SCALE) {
         // near-equilibrium evolution: eps* <- gamma eps* (eps_bar was scaled
         // by the controller)
@@ -309,18 +327,18 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       break;
     }
     case PH_PF_PQ: {
-      const V2<real> r = ld2(rmp + o), d = ld2(thp + o);
+      const V2<real> r = PRE ? in.a[0] : ld2(rmp + o), d = PRE ? in.a[1] : ld2(thp + o);
       V2<real> p;
       if (flags & FL_PF_FIRST) {
         p = {-r.a, -r.b};
       } else {
-        const V2<real> po = ld2(pmp + o);
+        const V2<real> po = PRE ? in.a[2] : ld2(pmp + o);
         const real bt = real(X.beta_pf);
         p = {-r.a + bt * po.a, -r.b + bt * po.b};
       }
       const unsigned char* mask = reinterpret_cast<const unsigned char*>(pmp + n);
-      if (ldb(mask + o)) p.a = real(0);
-      if (ldb(mask + o + 1)) p.b = real(0);
+      if (PRE ? in.m[0] : ldb(mask + o)) p.a = real(0);
+      if (PRE ? in.m[1] : ldb(mask + o + 1)) p.b = real(0);
       st2(pmp + o, p.a, p.b);
       acc[0] += double(d.a) * double(p.a) * double(p.a) + double(d.b) * double(p.b) * double(p.b);
       acc[1] += double(r.a) * double(p.a) + double(r.b) * double(p.b);
@@ -329,7 +347,8 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
       break;
     }
     case PH_PF_R: {
-      const V2<real> ph = ld2(phip + o), p = ld2(pmp + o), pr = ld2(prefp + o);
+      const V2<real> ph = PRE ? in.a[0] : ld2(phip + o), p = PRE ? in.a[1] : ld2(pmp + o),
+                     pr = PRE ? in.a[2] : ld2(prefp + o);
       const real al = real(X.alpha_pf);
       const real a0 = fmin(fmax(ph.a + al * p.a, lower_bound(pr.a, P)), real(1));
       const real a1 = fmin(fmax(ph.b + al * p.b, lower_bound(pr.b, P)), real(1));
@@ -394,6 +413,89 @@ __device__ __forceinline__ void row_prologue(const RowCtx<real>& X, const SlotPa
 // The prologue for NQ pixel pairs o0 + q OSTEP of one lane.  The field
 // pointers are restrict-qualified here so that the loads of later pairs may
 // be issued before the stores of earlier ones (the pairs never overlap).
+// Loads the prologue inputs of CH pixel pairs o0 + c OSTEP of phase PH, all
+// before any of them is used: the arithmetic of a pair branches (the
+// spectral split), which keeps the compiler from issuing the next pair's
+// loads early, so without this every pair cost a memory round trip.  Loads
+// that depend on the phase's flags are grouped under one test per chunk.
+template <typename real, int PH, int CH, int OSTEP>
+__device__ __forceinline__ void pro_load_chunk(const RowCtx<real>& X, const real* __restrict__ Ep,
+                                               const real* __restrict__ phip, const real* __restrict__ prefp,
+                                               const real* __restrict__ epsp, const real* __restrict__ thp,
+                                               const real* __restrict__ rmp, const real* __restrict__ pmp, int o0,
+                                               ProIn<real> (&in)[CH]) {
+  const int n = X.n, flags = X.flags;
+  if constexpr (PH == PH_M_RES) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int o = o0 + c * OSTEP;
+      in[c].a[0] = ld2(Ep + o);
+      in[c].a[1] = ld2(phip + o);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) in[c].a[2 + k] = ld2(epsp + k * n + o);
+    }
+    if (flags & FL_THETA_PENDING) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) in[c].a[5 + k] = ld2(thp + k * n + o0 + c * OSTEP);
+    }
+  } else if constexpr (PH == PH_M_CG) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int o = o0 + c * OSTEP;
+      in[c].a[0] = ld2(Ep + o);
+      in[c].a[1] = ld2(phip + o);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) in[c].a[2 + k] = ld2(rmp + k * n + o);
+    }
+    if (!(flags & FL_CG_FIRST)) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) in[c].a[5 + k] = ld2(pmp + k * n + o0 + c * OSTEP);
+    }
+    if (X.contact != 0) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) in[c].a[8 + k] = ld2(epsp + k * n + o0 + c * OSTEP);
+    }
+  } else if constexpr (PH == PH_PF_ASM) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int o = o0 + c * OSTEP;
+      in[c].a[0] = ld2(Ep + o);
+      in[c].a[1] = ld2(phip + o);
+      in[c].a[2] = ld2(prefp + o);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) in[c].a[3 + k] = ld2(epsp + k * n + o);
+    }
+  } else if constexpr (PH == PH_PF_PQ) {
+    const unsigned char* mask = reinterpret_cast<const unsigned char*>(pmp + n);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int o = o0 + c * OSTEP;
+      in[c].a[0] = ld2(rmp + o);
+      in[c].a[1] = ld2(thp + o);
+      in[c].m[0] = ldb(mask + o);
+      in[c].m[1] = ldb(mask + o + 1);
+    }
+    if (!(flags & FL_PF_FIRST)) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) in[c].a[2] = ld2(pmp + o0 + c * OSTEP);
+    }
+  } else if constexpr (PH == PH_PF_R) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int o = o0 + c * OSTEP;
+      in[c].a[0] = ld2(phip + o);
+      in[c].a[1] = ld2(pmp + o);
+      in[c].a[2] = ld2(prefp + o);
+    }
+  }
+}
+
 template <typename real, int NQ, int OSTEP>
 __device__ __forceinline__ void row_prologue_n(const RowCtx<real>& X, const SlotParam& P, const real* __restrict__ Ep,
                                                real* __restrict__ phip, real* __restrict__ prefp,
@@ -405,12 +507,33 @@ __device__ __forceinline__ void row_prologue_n(const RowCtx<real>& X, const Slot
     _Pragma("unroll") for (int q = 0; q < NQ; ++q)                                                        \
         row_prologue<real, PHC>(X, P, Ep, phip, prefp, epsp, thp, rmp, pmp, o0 + q * OSTEP, val[q], acc); \
     break;
+  // the phases a solve iterates on: chunks of up to four pairs, each loaded
+  // in full before its arithmetic (with sixteen pairs per lane, 2048-point
+  // rows, the registers are spent and the per-pair path is faster)
+  constexpr bool CHUNK = NQ <= 8;
+  constexpr int CH = NQ < 4 ? NQ : 4;
+  static_assert(NQ % CH == 0, "pairs per lane in whole chunks");
+#define SPFF_PRO_HOT(PHC)                                                                                    \
+  case PHC:                                                                                                 \
+    if constexpr (CHUNK) {                                                                                  \
+      _Pragma("unroll") for (int q0 = 0; q0 < NQ; q0 += CH) {                                               \
+        ProIn<real> in[CH];                                                                                 \
+        pro_load_chunk<real, PHC, CH, OSTEP>(X, Ep, phip, prefp, epsp, thp, rmp, pmp, o0 + q0 * OSTEP, in); \
+        _Pragma("unroll") for (int c = 0; c < CH; ++c)                                                      \
+            row_prologue<real, PHC, true>(X, P, Ep, phip, prefp, epsp, thp, rmp, pmp,                       \
+                                          o0 + (q0 + c) * OSTEP, val[q0 + c], acc, in[c]);                  \
+      }                                                                                                     \
+    } else {                                                                                                \
+      _Pragma("unroll") for (int q = 0; q < NQ; ++q)                                                        \
+          row_prologue<real, PHC>(X, P, Ep, phip, prefp, epsp, thp, rmp, pmp, o0 + q * OSTEP, val[q], acc); \
+    }                                                                                                       \
+    break;
   switch (X.phase) {
-    SPFF_PRO_CASE(PH_M_RES)
-    SPFF_PRO_CASE(PH_M_CG)
-    SPFF_PRO_CASE(PH_PF_ASM)
-    SPFF_PRO_CASE(PH_PF_PQ)
-    SPFF_PRO_CASE(PH_PF_R)
+    SPFF_PRO_HOT(PH_M_RES)
+    SPFF_PRO_HOT(PH_M_CG)
+    SPFF_PRO_HOT(PH_PF_ASM)
+    SPFF_PRO_HOT(PH_PF_PQ)
+    SPFF_PRO_HOT(PH_PF_R)
     SPFF_PRO_CASE(PH_AM_CHK)
     SPFF_PRO_CASE(PH_TD_RESTORE)
     SPFF_PRO_CASE(PH_STATS)
@@ -424,6 +547,7 @@ __device__ __forceinline__ void row_prologue_n(const RowCtx<real>& X, const Slot
       break;
   }
 #undef SPFF_PRO_CASE
+#undef SPFF_PRO_HOT
 }
 
 // Inputs of the controller step that a row-forward kernel runs for the
@@ -994,11 +1118,21 @@ __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const 
 
 // Row-inverse epilogue for the pixel pair (o, o + 1): q[c] holds the
 // transformed values of component c at the pair (x: o, y: o + 1).
-template <typename real, int PH = -1>
+// Inputs of the row epilogue for one pixel pair, loaded ahead of the
+// arithmetic (see epi_load_chunk for the slots of each phase).
+template <typename real>
+struct EpiIn {
+  V2<real> a[9];
+};
+
+template <typename real, int PH = -1, bool PRE = false>
 __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotParam& P, real* __restrict__ phip,
                                              real* __restrict__ prefp, real* __restrict__ thp,
                                              real* __restrict__ rmp, real* __restrict__ pmp, int o,
-                                             const cplx<real> (&q)[3], real alpha, double (&acc)[NP_INV]) {
+                                             const cplx<real> (&q)[3], real alpha, double (&acc)[NP_INV],
+                                             const EpiIn<real>& in = EpiIn<real>{}) {
+  // PRE: the inputs of this pair were loaded into `in` (PH one of M_CG,
+  // PF_ASM, PF_R; see row_epilogue_n)
   using C = cplx<real>;
   const int phase = PH >= 0 ? PH : X.phase;
   const int n = X.n, ncomp = X.ncomp;
@@ -1016,9 +1150,9 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
       const bool first = X.flags & FL_CG_FIRST;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const V2<real> p = ld2(pmp + c * n + o);
-        V2<real> r2 = ld2(rmp + c * n + o);
-        V2<real> th = first ? V2<real>{0, 0} : ld2(thp + c * n + o);
+        const V2<real> p = PRE ? in.a[c] : ld2(pmp + c * n + o);
+        V2<real> r2 = PRE ? in.a[3 + c] : ld2(rmp + c * n + o);
+        V2<real> th = first ? V2<real>{0, 0} : (PRE ? in.a[6 + c] : ld2(thp + c * n + o));
         th = {th.a + alpha * p.a, th.b + alpha * p.b};
         r2 = {r2.a - alpha * q[c].x, r2.b - alpha * q[c].y};
         st2(thp + c * n + o, th.a, th.b);
@@ -1031,8 +1165,9 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
     case PH_PF_ASM:
     case PH_PF_R: {
       const C lap = q[0];
-      const V2<real> ph = ld2(phip + o), d = ld2(thp + o), b = ld2(thp + n + o);
-      const V2<real> pr = ld2(prefp + o);
+      const V2<real> ph = PRE ? in.a[0] : ld2(phip + o), d = PRE ? in.a[1] : ld2(thp + o),
+                     b = PRE ? in.a[2] : ld2(thp + n + o);
+      const V2<real> pr = PRE ? in.a[3] : ld2(prefp + o);
       const real rr0 = d.a * ph.a + lap.x - b.a;
       const real rr1 = d.b * ph.b + lap.y - b.b;
       const real lo0 = lower_bound(pr.a, P), lo1 = lower_bound(pr.b, P);
@@ -1046,7 +1181,7 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
         acc[1] = fmax(acc[1], fmax(-double(rr0), -double(rr1)));
       }
       if (phase == PH_PF_R) {
-        const V2<real> ro = ld2(rmp + o);
+        const V2<real> ro = PRE ? in.a[4] : ld2(rmp + o);
         acc[1] += double(r0) * ro.a + double(r1) * ro.b;
       }
       st2(rmp + o, r0, r1);
@@ -1071,6 +1206,43 @@ __device__ __forceinline__ void row_epilogue(const RowCtx<real>& X, const SlotPa
   }
 }
 
+// Loads the epilogue inputs of CH pixel pairs o0 + c OSTEP of phase PH
+// before any store of the chunk: on this GPU a wait for a load also waits
+// for the stores issued before it, so interleaved per-pair loads and stores
+// cost a round trip per pair.
+template <typename real, int PH, int CH, int OSTEP>
+__device__ __forceinline__ void epi_load_chunk(const RowCtx<real>& X, const real* __restrict__ phip,
+                                               const real* __restrict__ prefp, const real* __restrict__ thp,
+                                               const real* __restrict__ rmp, const real* __restrict__ pmp, int o0,
+                                               EpiIn<real> (&in)[CH]) {
+  const int n = X.n;
+  if constexpr (PH == PH_M_CG) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        in[c].a[k] = ld2(pmp + k * n + o0 + c * OSTEP);
+        in[c].a[3 + k] = ld2(rmp + k * n + o0 + c * OSTEP);
+      }
+    if (!(X.flags & FL_CG_FIRST)) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) in[c].a[6 + k] = ld2(thp + k * n + o0 + c * OSTEP);
+    }
+  } else if constexpr (PH == PH_PF_ASM || PH == PH_PF_R) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int o = o0 + c * OSTEP;
+      in[c].a[0] = ld2(phip + o);
+      in[c].a[1] = ld2(thp + o);
+      in[c].a[2] = ld2(thp + n + o);
+      in[c].a[3] = ld2(prefp + o);
+      if constexpr (PH == PH_PF_R) in[c].a[4] = ld2(rmp + o);
+    }
+  }
+}
+
 // The epilogue for NQ pixel pairs o0 + q OSTEP of one lane (restrict
 // pointers: see row_prologue_n).
 template <typename real, int NQ, int OSTEP>
@@ -1083,11 +1255,28 @@ __device__ __forceinline__ void row_epilogue_n(const RowCtx<real>& X, const Slot
     _Pragma("unroll") for (int i = 0; i < NQ; ++i)                                                    \
         row_epilogue<real, PHC>(X, P, phip, prefp, thp, rmp, pmp, o0 + i * OSTEP, q[i], alpha, acc); \
     break;
+  // up to four pairs per lane (launches with few problems): all loaded
+  // before their stores; with more pairs the registers this takes would
+  // cost occupancy, and the per-pair path stays
+  constexpr bool CHUNK = NQ <= 4;
+#define SPFF_EPI_HOT(PHC)                                                                                    \
+  case PHC:                                                                                                   \
+    if constexpr (CHUNK) {                                                                                    \
+      EpiIn<real> in[NQ];                                                                                     \
+      epi_load_chunk<real, PHC, NQ, OSTEP>(X, phip, prefp, thp, rmp, pmp, o0, in);                            \
+      _Pragma("unroll") for (int c = 0; c < NQ; ++c)                                                          \
+          row_epilogue<real, PHC, true>(X, P, phip, prefp, thp, rmp, pmp, o0 + c * OSTEP, q[c], alpha, acc,   \
+                                        in[c]);                                                               \
+    } else {                                                                                                  \
+      _Pragma("unroll") for (int i = 0; i < NQ; ++i)                                                          \
+          row_epilogue<real, PHC>(X, P, phip, prefp, thp, rmp, pmp, o0 + i * OSTEP, q[i], alpha, acc);       \
+    }                                                                                                         \
+    break;
   switch (X.phase) {
     SPFF_EPI_CASE(PH_M_RES)
-    SPFF_EPI_CASE(PH_M_CG)
-    SPFF_EPI_CASE(PH_PF_ASM)
-    SPFF_EPI_CASE(PH_PF_R)
+    SPFF_EPI_HOT(PH_M_CG)
+    SPFF_EPI_HOT(PH_PF_ASM)
+    SPFF_EPI_HOT(PH_PF_R)
     SPFF_EPI_CASE(PH_X_PROJ)
     SPFF_EPI_CASE(PH_X_DISP)
     SPFF_EPI_CASE(PH_X_LAP)
@@ -1095,6 +1284,7 @@ __device__ __forceinline__ void row_epilogue_n(const RowCtx<real>& X, const Slot
       break;
   }
 #undef SPFF_EPI_CASE
+#undef SPFF_EPI_HOT
 }
 
 // ---------------------------------------------------------------------------
