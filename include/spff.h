@@ -327,9 +327,10 @@ spff_status spff_profile_read(spff_problem* p, spff_profile* out);
  * sums (so results by rounding only), never the arithmetic.
  *   row_kind / col_kind: SPFF_FFT_LDS -- Stockham radix-4/2 passes through
  *     LDS, one point pair per thread (any size); SPFF_FFT_REG -- radix-8
- *     Stockham on registers, 8 points per lane (16 for 1024- and
- *     2048-point transforms), wavefront-local LDS exchanges (a 2048-point
- *     column spans the two wavefronts of its work-group) (FP32 only; rows:
+ *     Stockham on registers, 8 points per lane (16 for 2048-point rows,
+ *     and for 1024- and 2048-point columns a plan may ask for 16 -- see
+ *     col_threads), wavefront-local LDS exchanges (a column of more than 64
+ *     lanes spans the wavefronts of its work-group) (FP32 only; rows:
  *     128 <= nx <= 2048, columns: ny in {128, 256, 512, 1024, 2048});
  *     SPFF_FFT_REG4 (rows only) -- 4 points per lane and radix-4 passes
  *     (twice the lanes per row, for launches with few problems;
@@ -339,9 +340,11 @@ spff_status spff_profile_read(spff_problem* p, spff_profile* out);
  *   row_threads / col_threads: threads per work-group for the LDS kind
  *     (64, 128 or 256, times 8 covering the transform); for the register
  *     kinds derived as rows * (lanes per row: nx/16, nx/32 for nx = 2048,
- *     nx/8 for SPFF_FFT_REG4) and cols * (lanes per column: ny/8, ny/16
- *     for ny >= 1024), which must be a power of two in [64, 256] (cols = 1
- *     for ny = 2048) -- filled in on return. */
+ *     nx/8 for SPFF_FFT_REG4) and cols * (lanes per column), which must be
+ *     a power of two in [64, 256] -- filled in on return.  Lanes per
+ *     column: ny/8; for ny = 1024 or 2048 that holds only with cols = 1
+ *     and col_threads = ny/8 as given (the built-in plans), any other
+ *     plan takes ny/16 (16 points per lane; cols = 1 for ny = 2048). */
 enum { SPFF_FFT_LDS = 1, SPFF_FFT_REG = 2, SPFF_FFT_REG4 = 3 };
 typedef struct spff_plan {
   int32_t row_kind, rows, row_threads;

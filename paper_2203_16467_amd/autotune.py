@@ -5,8 +5,9 @@ over a power-of-two bucket of active problem slots; for every bucket the
 library holds a launch plan (``spff_plan``): the kind of FFT kernel for rows
 and for columns (LDS Stockham radix-4/2 with one point pair per thread, or
 register-resident radix-8 with eight points per lane -- sixteen for
-1024-point transforms --, or for rows radix-4 with four), rows / columns per
-work-group and threads per work-group.  The built-in plans come from a
+1024- and 2048-point transforms, columns of those sizes also eight --, or for
+rows radix-4 with four), rows / columns per work-group and threads per
+work-group.  The built-in plans come from a
 heuristic; this module times the alternatives on the device and installs the
 fastest.
 
@@ -74,6 +75,9 @@ def col_candidates(cfg):
         for W in _pow2_range(max(1, 64 // L), 1 if L > 64 else THREADS // L):
             if W <= M:
                 out.append((spff.FFT_REG, W, W * L))
+        if cfg.ny >= 1024:
+            # 8 points per lane: ny/8 lanes, one column per work-group
+            out.append((spff.FFT_REG, 1, cfg.ny // 8))
     return out
 
 

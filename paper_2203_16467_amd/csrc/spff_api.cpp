@@ -132,6 +132,13 @@ bool reg_cols_ok(const spff_config* c) {
 // for 1024 and 2048 (a 2048-point column takes two wavefronts, alone in its
 // work-group); REG4 rows: 4
 int reg_points(int n) { return n > 512 ? 16 : 8; }
+// Register columns of 1024 or 2048 points may also take 8 points per lane
+// (ny/8 lanes, one column per work-group): a plan asks for it with cols = 1
+// and col_threads = ny/8.
+int reg_col_lanes(const spff_config* c, const spff_plan& pl) {
+  if (c->ny >= 1024 && pl.cols == 1 && pl.col_threads == c->ny / 8) return c->ny / 8;
+  return c->ny / reg_points(c->ny);
+}
 // columns per work-group of the register column kind: at least one
 // wavefront, at most THREADS lanes; a column wider than a wavefront alone
 int reg_cols_min(int Lc) { return Lc >= 64 ? 1 : 64 / Lc; }
@@ -159,12 +166,17 @@ spff_plan auto_plan(const spff_config* c, int S, size_t csize) {
   pl.col_kind = SPFF_FFT_LDS;
   pl.cols = W;
   pl.col_threads = T;
-  // FP32 columns of 128..1024 points: register-resident transforms, a group
-  // of ny/8 (ny/16 for 1024) lanes per column, W columns per work-group (at least one
-  // wavefront, at most THREADS lanes); W is fixed by plan_cols if given so
-  // that the partial sums (hence the results) do not depend on the batch
+  // FP32 columns of 128..2048 points: register-resident transforms, a group
+  // of ny/8 lanes per column (8 points per lane), W columns per work-group
+  // (at least one wavefront, at most THREADS lanes); W is fixed by plan_cols
+  // if given so that the partial sums (hence the results) do not depend on
+  // the batch.  1024- and 2048-point columns take one column per group (the
+  // 16-point form of their lanes holds one wavefront per SIMD in registers);
+  // plan_cols > 1 asks a 1024-point column for that form, 16 points per lane
+  // with up to four columns per group.
   if (reg_cols_ok(c)) {
-    const int Lc = c->ny / reg_points(c->ny);
+    const bool wide = c->ny == 2048 || (c->ny == 1024 && c->plan_cols <= 1);
+    const int Lc = wide ? c->ny / 8 : c->ny / reg_points(c->ny);
     const int wmin = reg_cols_min(Lc), wmax = reg_cols_max(Lc);
     if (wmin <= M) {
       int Wr = wmin;
@@ -242,10 +254,10 @@ spff_status check_plan(const spff_config* c, spff_plan* pl, size_t csize) {
   if (pl->col_kind == SPFF_FFT_REG) {
     if (!reg_cols_ok(c))
       return fail(SPFF_E_INVALID, "register column FFT needs FP32 and ny in {128, ..., 2048}");
-    const int Lc = c->ny / reg_points(c->ny);
+    const int Lc = reg_col_lanes(c, *pl);
     if (!pow2(pl->cols) || pl->cols < reg_cols_min(Lc) || pl->cols > reg_cols_max(Lc) || pl->cols > M)
       return fail(SPFF_E_INVALID, "register column FFT: cols * lanes per column must be a power of two in [64, %d] "
-                                  "(one column per work-group for 2048 points)", THREADS);
+                                  "(one column per work-group where a column spans several wavefronts)", THREADS);
     pl->col_threads = pl->cols * Lc;
   } else if (pl->col_kind == SPFF_FFT_LDS) {
     if (!pow2(pl->cols) || pl->cols > M) return fail(SPFF_E_INVALID, "cols must be a power of two <= nx/2");
@@ -276,6 +288,7 @@ LaunchGeom geom_from_plan(const spff_config* c, int S, size_t csize, const spff_
   G.ngc = M / pl.cols;
   G.threads_col = pl.col_threads;
   G.col_reg = pl.col_kind == SPFF_FFT_REG;
+  G.col_pts = G.col_reg ? c->ny / reg_col_lanes(c, pl) : 0;
   G.nyq_free = c->nyquist == SPFF_NYQ_FREE ? 1 : 0;
   G.lds_col = G.col_reg ? (size_t)pl.cols * (c->ny + c->ny / 8) * csize
                         : 3 * (size_t)pl.cols * (c->ny + PAD) * csize;

@@ -913,24 +913,28 @@ __device__ __forceinline__ void k_col_body(const int* __restrict__ list, const S
   block_reduce_store<NP_COL>(acc, red, part + (size_t)s * NP_COL * ngc + g, ngc, mode == 2 ? 1 : 0);
 }
 
-// Column kernel with register-resident transforms (ny = N in {128, 256,
-// 512}, FP32): a group of N/8 lanes owns one kx column of every component,
-// 8 modes per lane per component (lane l: ky = l + m N/8).  Forward FFTs,
-// the per-mode operator and the inverse FFTs run on the lane's registers;
-// only the two Stockham exchanges per transform go through LDS, inside the
-// group's wavefront.  The packed column kx = 0 (X[0] + i X[nx/2]) takes
-// the partner mode -ky from lane (L - l) mod L by a cross-lane shuffle.
-template <typename real, int N>
+// Column kernel with register-resident transforms (ny = N in {128, ...,
+// 2048}, FP32): a group of L = N/E lanes owns one kx column of every
+// component, E modes per lane per component (lane l: ky = l + m L).
+// Forward FFTs, the per-mode operator and the inverse FFTs run on the lane's
+// registers; only the Stockham exchanges between radix-8 passes go through
+// LDS, inside the group.  The packed column kx = 0 (X[0] + i X[nx/2]) takes
+// the partner mode -ky from lane (L - l) mod L by a cross-lane shuffle
+// (through LDS where the group spans several wavefronts).
+template <typename real, int N, int E>
 __device__ __forceinline__ void k_colr_body(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                             const SlotParam* __restrict__ prms, const SlotCtl* __restrict__ ctls,
                                             const cplx<real>* __restrict__ twy, double* __restrict__ part, int nx,
                                             int ngc, int nyq_free) {
   using C = cplx<real>;
-  // eight points per lane up to 512-point columns, sixteen for 1024 (one
-  // wavefront per column) and 2048 (two wavefronts: the work-group holds
-  // this one column, so every barrier below is reached by all its threads)
-  constexpr int E = N <= 512 ? 8 : 16, L = N / E;
-  static_assert(L <= 64 || N == 2048, "groups wider than a wavefront are 2048-point columns");
+  // E = 8 points per lane up to 512-point columns; 1024 and 2048 points
+  // take 16 (one or two wavefronts per column) or 8 (two or four: twice
+  // the wavefronts in flight for launches with one or two problems).  A
+  // group wider than a wavefront is the work-group's only column, so every
+  // barrier below is reached by all its threads.
+  constexpr int L = N / E;
+  static_assert(E == 8 || E == 16, "8 or 16 points per lane");
+  static_assert(L <= 64 || N >= 1024, "groups wider than a wavefront are 1024- or 2048-point columns");
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[(THREADS / 64) * NP_COL];
   const int s = list[blockIdx.y], g = blockIdx.x;
@@ -2214,7 +2218,7 @@ __global__ __launch_bounds__(THREADS) void k_col(const int* __restrict__ list, c
   kt_end(T.kt);
 }
 
-template <typename real, int N>
+template <typename real, int N, int E>
 __global__ __launch_bounds__(THREADS) void k_colr(const int* __restrict__ list, const SlotPtr<real>* __restrict__ ptrs,
                                                   const SlotParam* __restrict__ prms,
                                                   const SlotCtl* __restrict__ ctls,
@@ -2222,7 +2226,7 @@ __global__ __launch_bounds__(THREADS) void k_colr(const int* __restrict__ list, 
                                                   int nx, int ngc, int nyq_free, const ColTimers T) {
   if (col_timer_group(T)) return;
   kt_begin(T.kt);
-  k_colr_body<real, N>(list, ptrs, prms, ctls, twy, part, nx, ngc, nyq_free);
+  k_colr_body<real, N, E>(list, ptrs, prms, ctls, twy, part, nx, ngc, nyq_free);
   kt_end(T.kt);
 }
 
@@ -2418,15 +2422,27 @@ hipError_t launch_tick(const LaunchGeom& G, const TickBufs<real>& B, int i, hipS
   if constexpr (std::is_same<real, float>::value) {
     if (G.col_reg) {
       col_done = true;
-#define SPFF_COLS(NN)                                                                                           \
-  hipLaunchKernelGGL((k_colr<real, NN>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls, twy, \
+#define SPFF_COLS(NN, EE)                                                                                           \
+  hipLaunchKernelGGL((k_colr<real, NN, EE>), gcol, dim3(G.threads_col), G.lds_col, st, list, ptrs, prms, ctls, twy, \
                      pcol, G.nx, G.ngc, G.nyq_free, T)
       switch (G.ny) {
-        case 128: SPFF_COLS(128); break;
-        case 256: SPFF_COLS(256); break;
-        case 512: SPFF_COLS(512); break;
-        case 1024: SPFF_COLS(1024); break;
-        default: SPFF_COLS(2048); break;
+        case 128: SPFF_COLS(128, 8); break;
+        case 256: SPFF_COLS(256, 8); break;
+        case 512: SPFF_COLS(512, 8); break;
+        case 1024:
+          if (G.col_pts == 8) {
+            SPFF_COLS(1024, 8);
+          } else {
+            SPFF_COLS(1024, 16);
+          }
+          break;
+        default:
+          if (G.col_pts == 8) {
+            SPFF_COLS(2048, 8);
+          } else {
+            SPFF_COLS(2048, 16);
+          }
+          break;
       }
 #undef SPFF_COLS
     }

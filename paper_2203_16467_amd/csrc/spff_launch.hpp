@@ -18,6 +18,7 @@ struct LaunchGeom {
   int threads;      // threads per row work-group
   int threads_col;  // threads per column work-group
   int col_reg;      // column kernel with register-resident transforms
+  int col_pts;      // its points per lane: 8, or 16 (1024- and 2048-point columns)
   int row_reg;      // row kernels with register-resident transforms: 1 = 8, 2 = 4 points per lane
   int nyq_free;     // even grids: Nyquist modes of the strain fluctuation unconstrained
   size_t lds_row, lds_col;

@@ -180,3 +180,20 @@ def test_static_step_rejects_before_any_device_work():
     assert L.spff_load_step_static(ctypes.byref(cfg), None, dummy, eb, None, None) == spff.E_INVALID
     bad = (ctypes.c_double * 3)(0.0, float("nan"), 0.0)
     assert L.spff_load_step_static(ctypes.byref(cfg), dummy, dummy, bad, None, None) == spff.E_INVALID
+
+
+@pytest.mark.parametrize("ny", [128, 512, 1024, 2048])
+def test_autotuner_column_candidates_cover_both_point_counts(ny):
+    """Register column candidates: 8 points per lane (ny/8 lanes per column)
+    at every size, and for 1024 and 2048 points also the 16-point form; a
+    group never exceeds 256 lanes and holds a whole number of columns."""
+    from paper_2203_16467_amd import autotune
+    cfg = spff.default_config(nx=256, ny=ny)
+    reg = [(W, T) for kind, W, T in autotune.col_candidates(cfg) if kind == spff.FFT_REG]
+    assert (max(1, 64 // (ny // 8)), max(1, 64 // (ny // 8)) * (ny // 8)) in reg
+    if ny >= 1024:
+        assert (1, ny // 16) in reg and (1, ny // 8) in reg
+    for W, T in reg:
+        assert 64 <= T <= 256 and T % W == 0 and (T // W) in (ny // 8, ny // 16)
+    cfg64 = spff.default_config(nx=256, ny=ny, precision=spff.FP64)
+    assert not [c for c in autotune.col_candidates(cfg64) if c[0] == spff.FFT_REG]
