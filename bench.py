@@ -16,7 +16,8 @@ iterations) x grid points / seconds of the timed steps, inputs resident in
 HBM.  The library's device-clock kernel timers run during the timed steps
 (they cost about 3% of the kernel time, so `value` is slightly pessimistic)
 and give the per-kernel launch times of the roofline object; the timed steps
-are bracketed by roctxProfilerResume / Pause, so that
+are bracketed by roctxProfilerResume / Pause inside a roctx range
+(`bench_timed`; the large leg's timed steps: `bench_large_timed`), so that
 `rocprofv3 --selected-regions --kernel-trace --stats` profiles exactly them.
 
 The whole run keeps to a wall-clock budget (--budget seconds from the start
@@ -82,15 +83,17 @@ class _Roctx:
             self.lib.roctxProfilerResume.argtypes = [ctypes.c_uint64]
             self.lib.roctxProfilerPause.argtypes = [ctypes.c_uint64]
 
+    # resume before the push and pop before the pause: a marker issued while
+    # the profiler is paused is not recorded
     def begin(self, name):
         if self.ok:
-            self.lib.roctxRangePushA(name.encode())
             self.lib.roctxProfilerResume(0)
+            self.lib.roctxRangePushA(name.encode())
 
     def end(self):
         if self.ok:
-            self.lib.roctxProfilerPause(0)
             self.lib.roctxRangePop()
+            self.lib.roctxProfilerPause(0)
 
 
 ROCTX = _Roctx()
@@ -480,6 +483,7 @@ def large_leg(args, budget):
     p.profile_enable(True)
     dt, cg, pf, st, steps, pf_steps, am = 0.0, 0, 0, 0, 0, 0, 0
     k = args.large_start
+    ROCTX.begin("bench_large_timed")
     # a step after the onset of damage may run the alternating minimisation
     # to its cap (about a minute on this grid): start one only with that
     # much of the budget left
@@ -496,6 +500,7 @@ def large_leg(args, budget):
             pf_steps += 1
             log(f"large 2048^2: load step {k - 1} with phase-field work: {s0['am_iters']} AM, "
                 f"{s0['bccg_iters']} BCCG, {s0['cg_iters']} CG iterations")
+    ROCTX.end()
     pr = p.profile_read()
     p.close()
     kf = kernel_figures(pr)
