@@ -71,7 +71,8 @@ def col_candidates(cfg):
                 out.append((spff.FFT_LDS, W, T))
     if cfg.precision == spff.FP32 and cfg.ny in (128, 256, 512, 1024, 2048):
         L = cfg.ny // (8 if cfg.ny <= 512 else 16)
-        # a 2048-point column (128 lanes) is alone in its work-group
+        # 16 points per lane for 1024 and 2048 points: a 2048-point column
+        # (128 lanes) is alone in its work-group
         for W in _pow2_range(max(1, 64 // L), 1 if L > 64 else THREADS // L):
             if W <= M:
                 out.append((spff.FFT_REG, W, W * L))

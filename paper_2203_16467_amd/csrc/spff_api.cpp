@@ -129,12 +129,12 @@ bool reg_cols_ok(const spff_config* c) {
          (c->ny == 128 || c->ny == 256 || c->ny == 512 || c->ny == 1024 || c->ny == 2048);
 }
 // points per lane of the register kinds: 8 up to 512-point transforms, 16
-// for 1024 and 2048 (a 2048-point column takes two wavefronts, alone in its
-// work-group); REG4 rows: 4
+// for 1024 and 2048 (a 2048-point row is 1024 complex points: 64 lanes);
+// REG4 rows: 4
 int reg_points(int n) { return n > 512 ? 16 : 8; }
-// Register columns of 1024 or 2048 points may also take 8 points per lane
-// (ny/8 lanes, one column per work-group): a plan asks for it with cols = 1
-// and col_threads = ny/8.
+// Register columns of 1024 or 2048 points take 8 points per lane (ny/8
+// lanes: two or four wavefronts, one column per work-group) when a plan has
+// cols = 1 and col_threads = ny/8 (the built-in plans); otherwise 16.
 int reg_col_lanes(const spff_config* c, const spff_plan& pl) {
   if (c->ny >= 1024 && pl.cols == 1 && pl.col_threads == c->ny / 8) return c->ny / 8;
   return c->ny / reg_points(c->ny);

@@ -194,9 +194,9 @@ __device__ void fft_lds(cplx<real>* buf, int M, int ntrans, int stride, const cp
 // per-mode operator in between needs no data movement, and global loads and
 // stores of x[l + m L] are coalesced across lanes.  A group of L <= 64 lanes
 // lies in one wavefront, so an exchange is ordered by wave_sync() alone; a
-// group of L = 128 lanes (2048-point columns) spans the two wavefronts of
-// its work-group, which then holds that one group only, and an exchange is
-// ordered by a work-group barrier.
+// group of 128 or 256 lanes (1024- and 2048-point columns) spans two or
+// four wavefronts of its work-group, which then holds that one group only,
+// and an exchange is ordered by a work-group barrier.
 // tw holds the (N twmul)-th roots of unity exp(-2 pi i e / (N twmul)); the
 // inverse (INV) uses conjugates and is unnormalised.
 // ---------------------------------------------------------------------------
